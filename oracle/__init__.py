@@ -1,0 +1,284 @@
+"""CPU oracle for the tile Cholesky path.
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, by the smoke check and by
+the CPU-baseline leg of the benchmark, never by the product library. It
+shares no code with the GPU path. Everything is binary64.
+
+Paper: arXiv 2410.09819 ("Accelerating Mixed-Precision Out-of-Core Cholesky
+Factorization with Static Task Scheduling").
+
+  tile_cholesky        left-looking tile Cholesky, Section III-A, Algorithm 1
+                       (plain C loops in oracle.c)
+  cholesky_unblocked   row-by-row Cholesky on the whole matrix (cross-check)
+  solve, logdet        Sigma^{-1} y and log|Sigma| from the factor, used by the
+                       likelihood of Eq. 1 (Section III-D)
+  matern, matern_*     Eq. 2, C(h) = sigma^2 / (2^(nu-1) Gamma(nu)) (h/a)^nu
+                       K_nu(h/a), written out with scipy's K_nu; the nugget
+                       tau^2 is added on the diagonal
+  tile_norms, fro_norm, precision_map
+                       the per-tile precision criterion of Section IV-C:
+                       tile (i,j) may be stored in a lower precision p when
+                       Nt ||A_ij||_F / ||A||_F < eps_target / eps_p
+
+Pins (what ties each function to something other than itself) live in
+tests/test_oracle_*.py: exact integer factors, the closed-form factor of the
+second-difference matrix, brute force on small matrices, LAPACK's Cholesky,
+closed forms of the Matern function at half-integer smoothness, and the
+norm bound that the precision criterion guarantees.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_LIB = None
+_c_dbl_p = ctypes.POINTER(ctypes.c_double)
+
+
+def _bind(lib):
+    i64 = ctypes.c_int64
+    lib.oracle_tile_cholesky.restype = i64
+    lib.oracle_tile_cholesky.argtypes = [i64, i64, _c_dbl_p, i64, ctypes.c_int]
+    lib.oracle_cholesky_unblocked.restype = i64
+    lib.oracle_cholesky_unblocked.argtypes = [i64, _c_dbl_p, i64]
+    for f in (lib.oracle_forward_solve, lib.oracle_back_solve):
+        f.restype = None
+        f.argtypes = [i64, _c_dbl_p, i64, _c_dbl_p, i64, i64]
+    lib.oracle_mutant_id.restype = ctypes.c_int
+    return lib
+
+
+def load(path: str | None = None):
+    """The oracle's C library (built with gcc on first use if missing)."""
+    global _LIB
+    if path is not None:
+        return _bind(ctypes.CDLL(path))
+    if _LIB is None:
+        if not os.path.exists(_build.LIB):
+            _build.build()
+        _LIB = _bind(ctypes.CDLL(_build.LIB))
+    return _LIB
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(_c_dbl_p)
+
+
+# ---------------------------------------------------------------------------
+# Factorization, solves, log-determinant
+# ---------------------------------------------------------------------------
+
+def tile_cholesky(A: np.ndarray, nb: int, threads: int = 1, lib=None):
+    """Left-looking tile Cholesky of the symmetric n x n matrix A with tile
+    size nb (Algorithm 1). Returns (L, info): L lower triangular with zero
+    strict upper part; info = 0, or the 1-based global column of the first
+    non-positive pivot (L is then partial)."""
+    lib = lib or load()
+    n = A.shape[0]
+    a = np.array(A, dtype=np.float64, order="F", copy=True)
+    info = lib.oracle_tile_cholesky(n, nb, _ptr(a), n, threads)
+    if info < 0:
+        raise ValueError("bad arguments: n=%d nb=%d" % (n, nb))
+    return np.tril(a), int(info)
+
+
+def cholesky_unblocked(A: np.ndarray, lib=None):
+    """Unblocked row-by-row Cholesky (a different code path). (L, info)."""
+    lib = lib or load()
+    n = A.shape[0]
+    a = np.array(A, dtype=np.float64, order="F", copy=True)
+    info = lib.oracle_cholesky_unblocked(n, _ptr(a), n)
+    return np.tril(a), int(info)
+
+
+def solve(L: np.ndarray, B: np.ndarray, lib=None) -> np.ndarray:
+    """X = (L L^T)^{-1} B by forward then back substitution."""
+    lib = lib or load()
+    Lf = np.asfortranarray(L, dtype=np.float64)
+    X = np.array(B, dtype=np.float64, order="F", copy=True)
+    if X.ndim == 1:
+        X = X.reshape(-1, 1, order="F")
+    n, nrhs = X.shape
+    lib.oracle_forward_solve(n, _ptr(Lf), n, _ptr(X), n, nrhs)
+    lib.oracle_back_solve(n, _ptr(Lf), n, _ptr(X), n, nrhs)
+    return X.reshape(B.shape) if np.ndim(B) == 1 else X
+
+
+def forward_solve(L: np.ndarray, B: np.ndarray, lib=None) -> np.ndarray:
+    """Y = L^{-1} B."""
+    lib = lib or load()
+    Lf = np.asfortranarray(L, dtype=np.float64)
+    X = np.array(B, dtype=np.float64, order="F", copy=True)
+    if X.ndim == 1:
+        X = X.reshape(-1, 1, order="F")
+    n, nrhs = X.shape
+    lib.oracle_forward_solve(n, _ptr(Lf), n, _ptr(X), n, nrhs)
+    return X.reshape(B.shape) if np.ndim(B) == 1 else X
+
+
+def logdet(L: np.ndarray) -> float:
+    """log|A| = 2 sum_i log L_ii, summed with math.fsum (correctly rounded
+    sum of the rounded logarithms)."""
+    return 2.0 * math.fsum(np.log(np.diag(L)).tolist())
+
+
+def backward_error(A: np.ndarray, L: np.ndarray) -> float:
+    """||A - L L^T||_F / ||A||_F on the full symmetric matrix (A symmetric;
+    only its lower triangle is used)."""
+    As = np.tril(A) + np.tril(A, -1).T
+    R = As - L @ L.T
+    return float(np.linalg.norm(R) / np.linalg.norm(As))
+
+
+# ---------------------------------------------------------------------------
+# Matern covariance (Eq. 2) with a nugget on the diagonal
+# ---------------------------------------------------------------------------
+
+def matern(h, sigma2: float, rng: float, nu: float) -> np.ndarray:
+    """C(h) = sigma2 / (2^(nu-1) Gamma(nu)) * x^nu * K_nu(x), x = h / rng,
+    with its limit C(0) = sigma2."""
+    from scipy.special import gamma, kv
+    h = np.asarray(h, dtype=np.float64)
+    x = h / rng
+    out = np.full(x.shape, float(sigma2))
+    pos = x > 0
+    xp = x[pos]
+    out[pos] = sigma2 / (2.0 ** (nu - 1.0) * gamma(nu)) * xp ** nu * kv(nu, xp)
+    return out
+
+
+def distances(pts: np.ndarray, I, J) -> np.ndarray:
+    """Euclidean distance between points I and J (index arrays)."""
+    d = pts[np.asarray(I)] - pts[np.asarray(J)]
+    return np.sqrt(d[..., 0] * d[..., 0] + d[..., 1] * d[..., 1])
+
+
+def matern_entries(pts, I, J, sigma2, rng, nu, nugget) -> np.ndarray:
+    """Entries Sigma[I, J] = C(||s_I - s_J||) + nugget * [I == J]."""
+    I = np.asarray(I)
+    J = np.asarray(J)
+    v = matern(distances(pts, I, J), sigma2, rng, nu)
+    return v + nugget * (I == J)
+
+
+def matern_matrix(pts, sigma2, rng, nu, nugget) -> np.ndarray:
+    """Dense symmetric Sigma (n x n, Fortran order)."""
+    n = len(pts)
+    I, J = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    return np.asfortranarray(matern_entries(pts, I, J, sigma2, rng, nu, nugget))
+
+
+# ---------------------------------------------------------------------------
+# Per-tile precision criterion (Section IV-C)
+# ---------------------------------------------------------------------------
+
+# Storage classes, in the library's numbering.
+FP64, FP32, FP16, BF16, FP8 = 0, 1, 2, 3, 4
+# Significand bits p (including the implicit bit) of each class; the machine
+# epsilon of the class is 2^(1-p), its unit roundoff 2^-p.
+SIGNIFICAND_BITS = {FP64: 53, FP32: 24, FP16: 11, BF16: 8, FP8: 4}
+
+
+def tile_index(Nt: int, i: int, j: int) -> int:
+    """Position of lower tile (i, j), i >= j, when the lower tiles are listed
+    column of tiles by column of tiles, top to bottom."""
+    return j * Nt - j * (j - 1) // 2 + (i - j)
+
+
+def tile_norms(A: np.ndarray, nb: int) -> np.ndarray:
+    """||A_ij||_F of every lower tile (i >= j), in tile_index order."""
+    n = A.shape[0]
+    Nt = n // nb
+    out = np.empty(Nt * (Nt + 1) // 2)
+    for j in range(Nt):
+        for i in range(j, Nt):
+            out[tile_index(Nt, i, j)] = np.linalg.norm(A[i * nb:(i + 1) * nb, j * nb:(j + 1) * nb])
+    return out
+
+
+def fro_norm(norms: np.ndarray, Nt: int) -> float:
+    """||A||_F of the full symmetric matrix from the lower tiles' norms:
+    diagonal tiles once, off-diagonal tiles twice."""
+    s = 0.0
+    for j in range(Nt):
+        for i in range(j, Nt):
+            v = norms[tile_index(Nt, i, j)] ** 2
+            s += v if i == j else 2.0 * v
+    return math.sqrt(s)
+
+
+def class_eps(c: int, unit_roundoff: bool = False) -> float:
+    p = SIGNIFICAND_BITS[c]
+    return 2.0 ** (-p if unit_roundoff else 1 - p)
+
+
+def precision_map(norms: np.ndarray, fro: float, Nt: int, eps: float,
+                  allowed=(FP64, FP32, FP16, FP8), unit_roundoff: bool = False) -> np.ndarray:
+    """Class of every lower tile (uint8, tile_index order). A tile takes the
+    lowest allowed class p (largest eps_p) for which
+        Nt * ||A_ij||_F / ||A||_F < eps / eps_p
+    holds; if none does, or the tile is on the diagonal, FP64."""
+    low_first = sorted((c for c in allowed if c != FP64),
+                       key=lambda c: -class_eps(c, unit_roundoff))
+    out = np.zeros(len(norms), dtype=np.uint8)
+    for j in range(Nt):
+        for i in range(j + 1, Nt):
+            t = tile_index(Nt, i, j)
+            lhs = Nt * norms[t] / fro
+            for c in low_first:
+                if lhs < eps / class_eps(c, unit_roundoff):
+                    out[t] = c
+                    break
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Rounding to the storage classes (Section IV-C: tiles kept in FP32, FP16 or
+# FP8 instead of FP64). Round-to-nearest-even from binary64 in one step,
+# saturating at the class's largest finite value. FP8 is the OCP E4M3 format
+# (4 exponent bits, bias 7, 3 fraction bits, largest finite 448).
+# ---------------------------------------------------------------------------
+
+# (significand bits p, smallest normal exponent emin, largest finite value)
+CLASS_FORMAT = {
+    FP32: (24, -126, float(np.finfo(np.float32).max)),
+    FP16: (11, -14, 65504.0),
+    BF16: (8, -126, float.fromhex("0x1.fep127")),
+    FP8: (4, -6, 448.0),
+}
+
+
+def round_to_class(x: np.ndarray, c: int) -> np.ndarray:
+    """Round binary64 values to class c (RNE, saturating), returned as
+    binary64. The quantum at |x| in [2^e, 2^(e+1)) is 2^(max(e, emin)-p+1),
+    which also covers the subnormal range."""
+    x = np.asarray(x, dtype=np.float64)
+    if c == FP64:
+        return x.copy()
+    p, emin, vmax = CLASS_FORMAT[c]
+    _, e2 = np.frexp(x)                      # x = m 2^e2, 0.5 <= |m| < 1
+    e = np.maximum(e2.astype(np.int64) - 1, emin)
+    q = np.ldexp(1.0, e - (p - 1))
+    r = np.round(x / q) * q                  # np.round: half to even
+    return np.clip(r, -vmax, vmax)
+
+
+def scale_exponent(amax: float, c: int) -> int:
+    """Per-tile power-of-two scale for the narrow-range classes: the tile is
+    stored as x * 2^-e with e = ceil(log2(amax / largest finite)), so its
+    largest entry lands in the top binade. FP32/BF16/FP64 are not scaled."""
+    if c not in (FP16, FP8) or not (amax > 0.0):
+        return 0
+    return int(math.ceil(math.log2(amax / CLASS_FORMAT[c][2])))
+
+
+def round_tile(t: np.ndarray, c: int) -> tuple[np.ndarray, int]:
+    """Round one tile to class c with its per-tile scale. Returns the value
+    it stands for (binary64, already multiplied back by 2^e) and e."""
+    e = scale_exponent(float(np.max(np.abs(t))) if t.size else 0.0, c)
+    return np.ldexp(round_to_class(np.ldexp(t, -e), c), e), e

@@ -1,0 +1,154 @@
+"""Benchmark: FP64 tile Cholesky of the n=65536, nb=1024 Matern covariance
+(nu=1.5, range=0.1, nugget=1e-6) on one MI355X.
+
+One step = factorization (panel GEMM/SYRK, POTRF, TRSM under the static
+left-looking schedule) + log-determinant + solve with 16 right-hand sides,
+with the matrix already resident in HBM (generated on the GPU before the
+timed region; the factor goes to separate storage so the input survives).
+The metric counts n^3/3 flops per step.
+
+Prints one JSON line. `roofline` is the dominant kernel (the panel GEMM)
+timed with HIP events on the library's compute stream: algorithmic flops of
+all its launches / summed launch time, against the FP64 matrix peak.
+`cpu_baseline` times the CPU oracle on a bounded sample of the same workload
+(the leading 4096 x 4096 principal block, same tile size).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP64_PEAK_TFLOPS = 78.6
+METRIC = "Cholesky TFLOP/s (n^3/3) + % peak, MxP vs FP64 at stated backward error"
+
+
+def cpu_baseline(w, ns=4096):
+    import numpy as np
+
+    import oracle
+    import seeded_inputs as si
+    pts = si.points(w["n"], seed=w["seed"])[:ns]
+    A = oracle.matern_matrix(pts, w["sigma2"], w["range"], w["nu"], w["nugget"])
+    threads = min(16, os.cpu_count() or 1)
+    t0 = time.perf_counter()
+    _, info = oracle.tile_cholesky(A, w["nb"], threads=threads)
+    dt = time.perf_counter() - t0
+    assert info == 0
+    return {"value": ns ** 3 / 3.0 / dt / 1e12, "unit": "TFLOP/s", "cores": threads,
+            "kind": "oracle",
+            "sample": "leading %dx%d principal block of the same matrix, nb=%d, factorization only "
+                      "(%.1f s)" % (ns, ns, w["nb"], dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="fp64")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the tile Cholesky here runs on a single MI355X "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2410_09819_amd as tc
+    import seeded_inputs as si
+
+    if not os.path.exists(tc.LIB_PATH):
+        from paper_2410_09819_amd import build
+        build.build()
+    w = si.WORKLOADS[args.workload]
+    n, nb = w["n"], w["nb"]
+    nrhs = 16
+    dev = torch.device("cuda", 0)
+    theta = (w["sigma2"], w["range"], w["nu"], w["nugget"])
+    pts = torch.from_numpy(si.points(n, seed=w["seed"])).to(dev)
+    ctx = tc.Context(n, nb, timed=True)
+    A, _, _ = tc.matern_tiles(ctx, pts, theta, nb, norms=False)
+    storage = torch.empty(tc.factor_bytes(n, nb) // 8, dtype=torch.float64, device=dev)
+    B0 = torch.from_numpy(np.ascontiguousarray(
+        si.standard_normal((n, nrhs), seed=si.rhs_seed(w["seed"])).T)).to(dev)
+    B = torch.empty_like(B0)
+
+    def step():
+        F = tc.factorize(ctx, A, n, nb, storage=storage)
+        ld = tc.logdet(ctx, F)
+        B.copy_(B0)
+        tc.solve(ctx, F, B)
+        return F, ld
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    gemm_ms = gemm_flops = 0.0
+    gemm_launches = 0
+    fact_ms = 0.0
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        F, ld = step()
+        st = F.stats
+        gemm_ms += st.ms_gemm
+        gemm_flops += st.gemm_flops
+        gemm_launches += st.gemm_launches
+        fact_ms += st.ms_total
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_per_step = dt * 1e3 / args.steps
+    flops = n ** 3 / 3.0
+    value = flops / (ms_per_step * 1e-3) / 1e12
+    achieved = gemm_flops / (gemm_ms * 1e-3) / 1e12 if gemm_ms > 0 else None
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "fp64 tile Cholesky, n=%d nb=%d, Matern nu=%g range=%g nugget=%g, "
+                               "factor + logdet + %d-RHS solve" % (n, nb, w["nu"], w["range"],
+                                                                   w["nugget"], nrhs),
+                   "n": n, "nb": nb, "nrhs": nrhs, "precision": "fp64"},
+        "pct_fp64_peak": 100.0 * value / FP64_PEAK_TFLOPS,
+        "ms_factor": fact_ms / args.steps,
+        "factor_tflops": flops / (fact_ms / args.steps * 1e-3) / 1e12,
+        "logdet": ld,
+        "roofline": {
+            "kernel": "panel_update_kernel (FP64 MFMA panel GEMM+SYRK)",
+            "bound": "mfma",
+            "achieved": achieved,
+            "peak": FP64_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": (achieved / FP64_PEAK_TFLOPS) if achieved else None,
+            "traffic": None,
+            "launches_per_step": gemm_launches / args.steps,
+            "avg_launch_ms": gemm_ms / max(gemm_launches, 1),
+            "flops_per_launch": gemm_flops / max(gemm_launches, 1),
+        },
+        "cpu_baseline": None,
+    }
+    del storage, A
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,159 @@
+/*
+ * tilechol.h - C ABI of libtilechol, a tile-based left-looking Cholesky
+ * factorization A = L L^T of dense symmetric positive-definite matrices on
+ * one AMD Instinct MI355X (gfx950), with hand-written HIP kernels.
+ *
+ * Method: arXiv 2410.09819, "Accelerating Mixed-Precision Out-of-Core
+ * Cholesky Factorization with Static Task Scheduling".
+ *   - Section III-A / Algorithm 1: the matrix is cut into Nt x Nt tiles of
+ *     size nb; column of tiles k is produced by SYRK-updating the diagonal
+ *     tile with every tile to its left and factorizing it (POTRF), then
+ *     GEMM-updating each tile below it with the tiles to its left and solving
+ *     it against the transposed diagonal factor (TRSM).
+ *   - Section III-B: a static schedule; the order of all tasks is fixed
+ *     before the factorization starts.
+ *   - Section III-D, Eq. 1 and Eq. 2: the matrix is a Matern covariance over
+ *     spatial locations; its factor gives log|Sigma| and Sigma^{-1} y.
+ *
+ * Conventions for every entry point:
+ *   - Returns tc_status and never throws. 0 is success. A positive value
+ *     from tc_factorize is LAPACK's "info": the 1-based global index of the
+ *     first column whose pivot was not strictly positive (or was NaN).
+ *     Negative values are errors; tc_last_error() then describes them.
+ *   - Tiled storage ("packed lower tiles"): only the Nt(Nt+1)/2 tiles (i,j)
+ *     with i >= j are stored, each nb x nb and column-major (leading
+ *     dimension nb), listed column of tiles by column of tiles, top to
+ *     bottom: tile (i,j) starts at element tc_tile_offset(Nt,i,j) * nb * nb.
+ *     Diagonal tiles are stored in full; their strict upper triangle is
+ *     ignored on input and undefined in a factor (tc_factor_export writes
+ *     zeros there).
+ *   - Device pointers are plain HIP device addresses on the context's
+ *     device; the caller owns and frees every buffer it passes in. Work is
+ *     enqueued on the context's compute stream; each call returns after its
+ *     work has completed unless stated otherwise.
+ *   - n must be a positive multiple of nb, and nb a multiple of 128 with
+ *     nb <= 2048.
+ */
+#ifndef TILECHOL_H
+#define TILECHOL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t tc_status;
+#define TC_OK 0
+#define TC_EINVAL (-1)        /* bad argument (null pointer, bad size, ...) */
+#define TC_ENOMEM (-2)        /* workspace or budget too small */
+#define TC_EHIP (-3)          /* a HIP runtime call failed */
+#define TC_ENOTCONV (-4)      /* refinement did not reach the tolerance */
+#define TC_EUNSUPPORTED (-5)  /* valid request this build does not implement */
+
+/* Storage classes of a tile (Section IV-C: one precision per tile). */
+typedef enum { TC_FP64 = 0, TC_FP32 = 1, TC_FP16 = 2, TC_BF16 = 3, TC_FP8E4M3 = 4 } tc_prec;
+
+typedef struct tc_ctx tc_ctx;       /* device, streams, workspace */
+typedef struct tc_factor tc_factor; /* a computed factor (metadata; tiles live in caller memory) */
+
+/* Matern parameters of Eq. 2 plus a nugget added on the diagonal:
+ * Sigma_ij = sigma2 / (2^(nu-1) Gamma(nu)) x^nu K_nu(x) + nugget [i==j],
+ * x = ||s_i - s_j|| / range. */
+typedef struct {
+    double sigma2;
+    double range;
+    double nu;
+    double nugget;
+} tc_matern;
+
+typedef struct {
+    int32_t inplace;   /* 1: the factor overwrites the input tiles (storage == A) */
+    int32_t reserved[7];
+} tc_opts;
+
+typedef struct {
+    double ms_total;        /* factorization wall time, HIP events on the compute stream */
+    double ms_gemm;         /* summed duration of the panel GEMM/SYRK launches (if timed) */
+    double gemm_flops;      /* algorithmic flops of those launches */
+    int32_t gemm_launches;  /* number of panel GEMM/SYRK launches */
+    int32_t info;           /* same as the positive return value, or 0 */
+    double flops_total;     /* n^3/3 + lower-order terms actually executed (all classes) */
+    double reserved[6];
+} tc_stats;
+
+/* Tiles stored before lower tile (i,j), i >= j, in packed lower order:
+ * j*Nt - j*(j-1)/2 + (i-j). Returns -1 if the indices are out of range. */
+int64_t tc_tile_offset(int32_t Nt, int32_t i, int32_t j);
+
+/* Library version string (static storage). */
+const char *tc_version(void);
+
+/* Text of the last error on the calling thread (static thread-local
+ * storage, valid until the next call on that thread). */
+const char *tc_last_error(void);
+
+/* Bytes of device workspace a context needs for matrices up to order n with
+ * tile size nb and up to nrhs right-hand sides per solve. */
+size_t tc_workspace_bytes(int64_t n, int32_t nb, int32_t nrhs);
+
+/* Create a context on HIP device `device`. `workspace` is a device buffer of
+ * `workspace_bytes` bytes that the context uses for scratch (split-K
+ * partial sums, failure flag, reduction partials); it must stay allocated
+ * until tc_ctx_destroy. `compute_stream` is a hipStream_t (NULL: the null
+ * stream). `flags` bit 0 times each panel GEMM launch with HIP events
+ * (filled into tc_stats). */
+tc_status tc_ctx_create(tc_ctx **ctx, int device, void *workspace, size_t workspace_bytes,
+                        void *compute_stream, uint32_t flags);
+tc_status tc_ctx_destroy(tc_ctx *ctx);
+
+/* Matern covariance tiles (Section III-D, Eq. 2) for n locations.
+ * locs: device, n x 2 binary64, row-major (x0, y0, x1, y1, ...).
+ * A: device, packed lower tiles of Nt = n/nb tiles per side (written; both
+ *    triangles of the diagonal tiles are filled).
+ * tile_fro: device, Nt(Nt+1)/2 binary64 or NULL: Frobenius norm of every
+ *    stored tile (diagonal tiles in full), in packed order.
+ * fro_A: host, 1 binary64 or NULL: ||Sigma||_F of the full symmetric matrix
+ *    (requires tile_fro).
+ * Smoothness nu = 0.5, 1.5 and 2.5 use closed forms; other nu > 0 use the
+ * integral K_nu(x) = int_0^inf exp(-x cosh t) cosh(nu t) dt by the
+ * trapezoid rule. */
+tc_status tc_matern_tiles(tc_ctx *ctx, int64_t n, int32_t nb, const double *locs,
+                          const tc_matern *theta, double *A, double *tile_fro, double *fro_A);
+
+/* Tile Cholesky factorization (Algorithm 1 under a static schedule).
+ * A: device packed lower tiles (n, nb), binary64, read only unless
+ *    storage == A.
+ * map: host, Nt(Nt+1)/2 tc_prec codes in packed order, or NULL for all
+ *    TC_FP64. (This build factors FP64 maps only; others give
+ *    TC_EUNSUPPORTED.)
+ * storage: device buffer of tc_factor_bytes(n, nb, map) bytes that receives
+ *    the factor's tiles; it may equal A (in place). It must outlive *L.
+ * L: receives a new factor handle (free with tc_factor_destroy), also when
+ *    the return value is positive (the factor is then partial).
+ * stats: NULL or filled. */
+size_t tc_factor_bytes(int64_t n, int32_t nb, const uint8_t *map);
+tc_status tc_factorize(tc_ctx *ctx, int64_t n, int32_t nb, const double *A, const uint8_t *map,
+                       const tc_opts *opts, void *storage, size_t storage_bytes,
+                       tc_factor **L, tc_stats *stats);
+
+/* Solve Sigma X = B with the factor: B <- L^{-T} L^{-1} B.
+ * B: device, n x nrhs binary64, column-major with leading dimension ldb >= n. */
+tc_status tc_solve(tc_ctx *ctx, const tc_factor *L, double *B, int64_t ldb, int32_t nrhs);
+
+/* log|Sigma| = 2 sum_i log L_ii (Eq. 1's log-determinant), into *out (host). */
+tc_status tc_logdet(tc_ctx *ctx, const tc_factor *L, double *out);
+
+/* Copy the factor into L64 (device, packed lower tiles, binary64) with the
+ * strict upper triangle of every diagonal tile set to zero. L64 may be the
+ * factor's own storage. */
+tc_status tc_factor_export(tc_ctx *ctx, const tc_factor *L, double *L64);
+
+/* Free the handle (not the caller's storage). NULL is accepted. */
+tc_status tc_factor_destroy(tc_factor *L);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TILECHOL_H */

@@ -1,0 +1,270 @@
+"""Python binding of libtilechol: a tile-based left-looking Cholesky
+factorization on one AMD Instinct MI355X (gfx950).
+
+Argument marshalling only: every step of the factorization, solve,
+log-determinant and covariance generation runs in the library's HIP
+kernels. PyTorch supplies device memory and the stream. The binding fails
+loudly if the library has not been built.
+
+Method: arXiv 2410.09819, Section III-A (Algorithm 1: left-looking tile
+Cholesky), Section III-B (static schedule), Section III-D (Matern
+covariance, Eq. 2, and the Gaussian log-likelihood of Eq. 1).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "lib", "libtilechol.so")
+
+FP64, FP32, FP16, BF16, FP8E4M3 = 0, 1, 2, 3, 4
+TC_OK, TC_EINVAL, TC_ENOMEM, TC_EHIP, TC_ENOTCONV, TC_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+
+
+class TileCholError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("tilechol error %d: %s" % (status, msg))
+        self.status = status
+
+
+class NotPositiveDefinite(TileCholError):
+    def __init__(self, info: int, msg: str):
+        super().__init__(info, msg)
+        self.info = info
+
+
+class Matern(ctypes.Structure):
+    _fields_ = [("sigma2", ctypes.c_double), ("range", ctypes.c_double),
+                ("nu", ctypes.c_double), ("nugget", ctypes.c_double)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("inplace", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("ms_total", ctypes.c_double), ("ms_gemm", ctypes.c_double),
+                ("gemm_flops", ctypes.c_double), ("gemm_launches", ctypes.c_int32),
+                ("info", ctypes.c_int32), ("flops_total", ctypes.c_double),
+                ("reserved", ctypes.c_double * 6)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+
+
+_LIB = None
+_vp = ctypes.c_void_p
+_i32, _i64, _sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+
+
+def lib():
+    """The loaded libtilechol (raises if it has not been built)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libtilechol.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+    L = ctypes.CDLL(LIB_PATH)
+    sig = {
+        "tc_tile_offset": (_i64, [_i32, _i32, _i32]),
+        "tc_version": (ctypes.c_char_p, []),
+        "tc_last_error": (ctypes.c_char_p, []),
+        "tc_workspace_bytes": (_sz, [_i64, _i32, _i32]),
+        "tc_ctx_create": (_i32, [ctypes.POINTER(_vp), ctypes.c_int, _vp, _sz, _vp, ctypes.c_uint32]),
+        "tc_ctx_destroy": (_i32, [_vp]),
+        "tc_matern_tiles": (_i32, [_vp, _i64, _i32, _vp, ctypes.POINTER(Matern), _vp, _vp,
+                                   ctypes.POINTER(ctypes.c_double)]),
+        "tc_factor_bytes": (_sz, [_i64, _i32, _vp]),
+        "tc_factorize": (_i32, [_vp, _i64, _i32, _vp, _vp, ctypes.POINTER(Opts), _vp, _sz,
+                                ctypes.POINTER(_vp), ctypes.POINTER(Stats)]),
+        "tc_solve": (_i32, [_vp, _vp, _vp, _i64, _i32]),
+        "tc_logdet": (_i32, [_vp, _vp, ctypes.POINTER(ctypes.c_double)]),
+        "tc_factor_export": (_i32, [_vp, _vp, _vp]),
+        "tc_factor_destroy": (_i32, [_vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _LIB = L
+    return L
+
+
+def _check(status: int):
+    if status == 0:
+        return
+    msg = (lib().tc_last_error() or b"").decode()
+    if status > 0:
+        raise NotPositiveDefinite(status, msg)
+    raise TileCholError(status, msg)
+
+
+# --- host-side helpers (no device work) -------------------------------------
+
+def tile_offset(Nt: int, i: int, j: int) -> int:
+    return lib().tc_tile_offset(Nt, i, j)
+
+
+def workspace_bytes(n: int, nb: int, nrhs: int = 16) -> int:
+    return lib().tc_workspace_bytes(n, nb, nrhs)
+
+
+def factor_bytes(n: int, nb: int, cmap=None) -> int:
+    if cmap is None:
+        return lib().tc_factor_bytes(n, nb, None)
+    m = np.ascontiguousarray(cmap, dtype=np.uint8)
+    return lib().tc_factor_bytes(n, nb, m.ctypes.data)
+
+
+def num_tiles(n: int, nb: int) -> int:
+    Nt = n // nb
+    return Nt * (Nt + 1) // 2
+
+
+def pack_lower(A: np.ndarray, nb: int) -> np.ndarray:
+    """Dense n x n -> packed lower tiles (layout conversion only)."""
+    n = A.shape[0]
+    Nt = n // nb
+    out = np.empty(num_tiles(n, nb) * nb * nb, dtype=np.float64)
+    t = 0
+    for j in range(Nt):
+        for i in range(j, Nt):
+            out[t * nb * nb:(t + 1) * nb * nb] = np.ravel(A[i * nb:(i + 1) * nb, j * nb:(j + 1) * nb],
+                                                          order="F")
+            t += 1
+    return out
+
+
+def unpack_lower(P: np.ndarray, n: int, nb: int, symmetric: bool = False) -> np.ndarray:
+    """Packed lower tiles -> dense n x n (upper triangle outside the
+    diagonal tiles zero, or mirrored when symmetric=True)."""
+    Nt = n // nb
+    A = np.zeros((n, n), dtype=np.float64, order="F")
+    t = 0
+    for j in range(Nt):
+        for i in range(j, Nt):
+            A[i * nb:(i + 1) * nb, j * nb:(j + 1) * nb] = \
+                P[t * nb * nb:(t + 1) * nb * nb].reshape(nb, nb, order="F")
+            t += 1
+    if symmetric:
+        A = np.tril(A) + np.tril(A, -1).T
+    return A
+
+
+# --- device API -------------------------------------------------------------
+
+class Context:
+    """Device, stream and workspace for matrices up to order n with tile nb."""
+
+    def __init__(self, n: int, nb: int, device: int = 0, stream=None, timed: bool = False,
+                 nrhs: int = 16):
+        import torch
+        self.device = device
+        self.dev = torch.device("cuda", device)
+        nbytes = workspace_bytes(n, nb, nrhs)
+        if nbytes == 0:
+            raise TileCholError(TC_EINVAL, "invalid shape n=%d nb=%d" % (n, nb))
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.dev)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.dev)
+        h = _vp()
+        _check(lib().tc_ctx_create(ctypes.byref(h), device, self.workspace.data_ptr(), nbytes,
+                                   self.stream.cuda_stream, 1 if timed else 0))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().tc_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def matern_tiles(ctx: Context, locs, theta, nb: int, out=None, norms: bool = True):
+    """Packed lower Matern tiles (Eq. 2 + nugget) for device locations
+    `locs` (n x 2 float64). theta = (sigma2, range, nu, nugget).
+    Returns (A, tile_fro or None, fro_A or None)."""
+    import torch
+    n = locs.shape[0]
+    assert locs.dtype == torch.float64 and locs.is_contiguous() and locs.shape[1] == 2
+    th = Matern(*[float(v) for v in theta])
+    A = out if out is not None else torch.empty(num_tiles(n, nb) * nb * nb, dtype=torch.float64,
+                                                 device=locs.device)
+    tf = torch.empty(num_tiles(n, nb), dtype=torch.float64, device=locs.device) if norms else None
+    fro = ctypes.c_double(0.0)
+    _check(lib().tc_matern_tiles(ctx.handle, n, nb, locs.data_ptr(), ctypes.byref(th),
+                                 A.data_ptr(), tf.data_ptr() if norms else None,
+                                 ctypes.byref(fro) if norms else None))
+    return A, tf, (fro.value if norms else None)
+
+
+class Factor:
+    def __init__(self, handle, n, nb, storage, stats: Stats):
+        self.handle, self.n, self.nb, self.storage, self.stats = handle, n, nb, storage, stats
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().tc_factor_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def factorize(ctx: Context, A, n: int, nb: int, cmap=None, inplace: bool = False,
+              storage=None) -> Factor:
+    """Tile Cholesky of the packed lower tiles A (device float64). With
+    inplace=True the factor overwrites A. Raises NotPositiveDefinite."""
+    import torch
+    if inplace:
+        storage = A
+    elif storage is None:
+        storage = torch.empty(factor_bytes(n, nb, cmap) // 8, dtype=torch.float64, device=A.device)
+    m = None if cmap is None else np.ascontiguousarray(cmap, dtype=np.uint8)
+    opts = Opts(1 if inplace else 0)
+    st = Stats()
+    h = _vp()
+    status = lib().tc_factorize(ctx.handle, n, nb, A.data_ptr(), None if m is None else m.ctypes.data,
+                                ctypes.byref(opts), storage.data_ptr(),
+                                storage.numel() * storage.element_size(), ctypes.byref(h),
+                                ctypes.byref(st))
+    F = Factor(h, n, nb, storage, st) if h.value else None
+    if status != 0:
+        if F is not None:
+            F.close()
+        _check(status)
+    return F
+
+
+def solve(ctx: Context, F: Factor, B):
+    """In place: B <- Sigma^{-1} B. B is a device float64 tensor of shape
+    (nrhs, n) (each row one right-hand side; column-major n x nrhs)."""
+    assert B.is_contiguous() and B.shape[-1] == F.n
+    nrhs = 1 if B.dim() == 1 else B.shape[0]
+    _check(lib().tc_solve(ctx.handle, F.handle, B.data_ptr(), F.n, nrhs))
+    return B
+
+
+def logdet(ctx: Context, F: Factor) -> float:
+    out = ctypes.c_double(0.0)
+    _check(lib().tc_logdet(ctx.handle, F.handle, ctypes.byref(out)))
+    return out.value
+
+
+def export(ctx: Context, F: Factor, out=None):
+    """FP64 packed lower tiles of the factor with zero strict upper parts."""
+    import torch
+    if out is None:
+        out = torch.empty(num_tiles(F.n, F.nb) * F.nb * F.nb, dtype=torch.float64,
+                          device=F.storage.device)
+    _check(lib().tc_factor_export(ctx.handle, F.handle, out.data_ptr()))
+    return out

@@ -95,15 +95,17 @@ __global__ __launch_bounds__(kGemmThreads, 2) void panel_update_kernel(
 #pragma unroll
     for (int mi = 0; mi < Tl::MI; ++mi)
 #pragma unroll
-        for (int ni = 0; ni < Tl::NI; ++ni) {
-            const int row = acc_row<kPanelBM, kPanelBM>(mi, 0);
-            const int col = acc_col<kPanelBM, kPanelBM>(ni);
-            d4* p = reinterpret_cast<d4*>(out + (int64_t)col * nb + row);
-            if (splits == 1)
-                *p = *p - acc[mi][ni];
-            else
-                *p = acc[mi][ni];
-        }
+        for (int ni = 0; ni < Tl::NI; ++ni)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = acc_row<kPanelBM, kPanelBM>(mi);
+                const int col = acc_col<kPanelBM, kPanelBM>(ni, v);
+                double* p = out + (int64_t)col * nb + row;
+                if (splits == 1)
+                    *p -= acc[mi][ni][v];
+                else
+                    *p = acc[mi][ni][v];
+            }
 }
 
 // C_tile -= sum_s partial_s over the computed blocks of the panel.
@@ -145,7 +147,7 @@ __global__ __launch_bounds__(kGemmThreads) void syrk_sub_kernel(double* __restri
     while ((int64_t)(br + 1) * (br + 2) / 2 <= b) ++br;
     while ((int64_t)br * (br + 1) / 2 > b) --br;
     const int bc = (int)(b - (int64_t)br * (br + 1) / 2);
-    const int64_t kchunk = ((kdim / splits + 15) / 16) * 16;
+    const int64_t kchunk = (((kdim + splits - 1) / splits + 15) / 16) * 16;
     const int64_t kbeg = (int64_t)split * kchunk;
     const int64_t kend = kbeg + kchunk < kdim ? kbeg + kchunk : kdim;
 
@@ -171,15 +173,17 @@ __global__ __launch_bounds__(kGemmThreads) void syrk_sub_kernel(double* __restri
 #pragma unroll
     for (int mi = 0; mi < Tl::MI; ++mi)
 #pragma unroll
-        for (int ni = 0; ni < Tl::NI; ++ni) {
-            const int row = acc_row<kSubB, kSubB>(mi, 0);
-            const int col = acc_col<kSubB, kSubB>(ni);
-            d4* p = reinterpret_cast<d4*>(out + (int64_t)col * ldo + row);
-            if (splits == 1)
-                *p = *p - acc[mi][ni];
-            else
-                *p = acc[mi][ni];
-        }
+        for (int ni = 0; ni < Tl::NI; ++ni)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = acc_row<kSubB, kSubB>(mi);
+                const int col = acc_col<kSubB, kSubB>(ni, v);
+                double* p = out + (int64_t)col * ldo + row;
+                if (splits == 1)
+                    *p -= acc[mi][ni][v];
+                else
+                    *p = acc[mi][ni][v];
+            }
 }
 
 __global__ void syrk_sub_reduce_kernel(double* __restrict__ C, int ld, int m, int splits,
@@ -218,7 +222,7 @@ hipError_t launch_panel_update(hipStream_t s, double* L, int Nt, int nb, int k, 
                                double* partial) {
     const int64_t W = panel_blocks(Nt, nb, k);
     const int64_t K = (int64_t)k * nb;
-    const int64_t kchunk = ((K / splits + 15) / 16) * 16;
+    const int64_t kchunk = (((K + splits - 1) / splits + 15) / 16) * 16;  // covers K
     hipLaunchKernelGGL(panel_update_kernel, dim3((unsigned)(W * splits)), dim3(kGemmThreads), 0, s,
                        L, Nt, nb, k, splits, W, kchunk, partial);
     return hipGetLastError();

@@ -9,9 +9,12 @@
 //
 // 256 threads = 4 waves in a 2 x 2 arrangement; each wave owns a
 // (BM/2) x (BN/2) sub-tile made of 16 x 16 blocks of
-// v_mfma_f64_16x16x4_f64. Lane l supplies A[i = l%16][k = l/16] and
-// B^T[k = l/16][j = l%16]; accumulator element v of lane l is
-// C[4*(l/16) + v][l%16].
+// v_mfma_f64_16x16x4_f64. For D = X Y (X 16x4, Y 4x16) lane l supplies
+// X[l%16][l/16] and Y[l/16][l%16], and accumulator element v of lane l is
+// D[l/16 + 4v][l%16] (checked on the device). The blocks are computed
+// transposed, D = B_blk A_blk^T = C^T, so that element v of lane l is
+// C[l%16][l/16 + 4v]: for each v, 16 lanes hold 16 consecutive rows of one
+// column, and stores to column-major tiles are 128-byte contiguous runs.
 #pragma once
 
 #include "common.hpp"
@@ -109,7 +112,7 @@ __device__ __forceinline__ void mfma_mainloop(d4 (&acc)[BM / 32][BN / 32], const
             for (int mi = 0; mi < T::MI; ++mi)
 #pragma unroll
                 for (int ni = 0; ni < T::NI; ++ni)
-                    acc[mi][ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[mi], b[ni], acc[mi][ni],
+                    acc[mi][ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[ni], a[mi], acc[mi][ni],
                                                                       0, 0, 0);
         }
         if (more) sstore(buf ^ 1);
@@ -121,14 +124,14 @@ __device__ __forceinline__ void mfma_mainloop(d4 (&acc)[BM / 32][BN / 32], const
 // Row / column (within the BM x BN block) of accumulator element v of
 // block (mi, ni) for the calling lane.
 template <int BM, int BN>
-__device__ __forceinline__ int acc_row(int mi, int v) {
+__device__ __forceinline__ int acc_row(int mi) {
     const int lane = threadIdx.x & 63, wm = (threadIdx.x >> 6) & 1;
-    return wm * (BM / 2) + mi * 16 + (lane >> 4) * 4 + v;
+    return wm * (BM / 2) + mi * 16 + (lane & 15);
 }
 template <int BM, int BN>
-__device__ __forceinline__ int acc_col(int ni) {
+__device__ __forceinline__ int acc_col(int ni, int v) {
     const int lane = threadIdx.x & 63, wn = threadIdx.x >> 7;
-    return wn * (BN / 2) + ni * 16 + (lane & 15);
+    return wn * (BN / 2) + ni * 16 + (lane >> 4) + 4 * v;
 }
 
 }  // namespace tc

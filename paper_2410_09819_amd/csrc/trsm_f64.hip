@@ -52,16 +52,13 @@ __global__ __launch_bounds__(kGemmThreads) void trsm_kernel(double* __restrict__
 #pragma unroll
         for (int mi = 0; mi < Tl::MI; ++mi)
 #pragma unroll
-            for (int ni = 0; ni < Tl::NI; ++ni) {
-                const int row = acc_row<kRows, kCol>(mi, 0);
-                const int col = acc_col<kRows, kCol>(ni);
-                const d4 c = *reinterpret_cast<const d4*>(Cb + (int64_t)(jb + col) * nb + row);
-                const d4 r = c - acc[mi][ni];
-                S[(row + 0) * kP + col] = r.x;
-                S[(row + 1) * kP + col] = r.y;
-                S[(row + 2) * kP + col] = r.z;
-                S[(row + 3) * kP + col] = r.w;
-            }
+            for (int ni = 0; ni < Tl::NI; ++ni)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = acc_row<kRows, kCol>(mi);
+                    const int col = acc_col<kRows, kCol>(ni, v);
+                    S[row * kP + col] = Cb[(int64_t)(jb + col) * nb + row] - acc[mi][ni][v];
+                }
         // diagonal block of L, lower part
         for (int e = tid; e < kCol * kCol; e += kGemmThreads) {
             const int l = e / kCol, j = e % kCol;  // column l, row j: coalesced in j

@@ -282,3 +282,81 @@ def round_tile(t: np.ndarray, c: int) -> tuple[np.ndarray, int]:
     it stands for (binary64, already multiplied back by 2^e) and e."""
     e = scale_exponent(float(np.max(np.abs(t))) if t.size else 0.0, c)
     return np.ldexp(round_to_class(np.ldexp(t, -e), c), e), e
+
+
+# ---------------------------------------------------------------------------
+# Mixed-precision tile Cholesky (Section IV-C), emulated on the CPU.
+#
+# Reading of the paper used here (the paper does not spell the arithmetic
+# out): a tile's class governs how it is stored and how the updates *into*
+# it are computed.
+#   * diagonal tiles are FP64: SYRK in FP64 on the stored operands, POTRF in
+#     FP64;
+#   * an off-diagonal tile (m, k) of class p gets
+#       C = A_mk - sum_{n<k} Q_p(Lh_mn) Q_p(Lh_kn)^T
+#     where Q_p rounds a stored tile to class p (with its per-tile scale for
+#     FP16 / FP8) and the products are accumulated in FP32 (FP64 for p =
+#     FP64); then L_mk = C L_kk^{-T} in FP64 and the stored tile is
+#     Lh_mk = Q_p(L_mk).
+# Products of operands of class <= FP32 are exact in binary64; the FP32
+# accumulation is emulated with float32 matrix products per operand tile,
+# summed in float32. The GPU accumulates in a different order, so results
+# agree to within the error bounds, not bitwise.
+# ---------------------------------------------------------------------------
+
+def mxp_tile_cholesky(A: np.ndarray, nb: int, cmap: np.ndarray):
+    """Mixed-precision left-looking tile Cholesky. Returns (Lh, info): Lh the
+    stored factor as binary64 values (each tile exactly representable in
+    its class with its scale), info as in tile_cholesky."""
+    from scipy.linalg import solve_triangular
+    n = A.shape[0]
+    Nt = n // nb
+    As = np.tril(A) + np.tril(A, -1).T
+    Lh = np.zeros((n, n))
+
+    def T(M, i, j):
+        return M[i * nb:(i + 1) * nb, j * nb:(j + 1) * nb]
+
+    for k in range(Nt):
+        C = T(As, k, k).copy()
+        for n2 in range(k):
+            C -= T(Lh, k, n2) @ T(Lh, k, n2).T
+        Lkk, info = tile_cholesky(C, nb)
+        if info:
+            return Lh, k * nb + info
+        T(Lh, k, k)[:] = Lkk
+        for m in range(k + 1, Nt):
+            p = int(cmap[tile_index(Nt, m, k)])
+            C = T(As, m, k).copy()
+            if p == FP64:
+                for n2 in range(k):
+                    C -= T(Lh, m, n2) @ T(Lh, k, n2).T
+            else:
+                acc = np.zeros((nb, nb), dtype=np.float32)
+                for n2 in range(k):
+                    a, _ = round_tile(T(Lh, m, n2), p)
+                    b, _ = round_tile(T(Lh, k, n2), p)
+                    acc += (a.astype(np.float32) @ b.astype(np.float32).T).astype(np.float32)
+                C -= acc.astype(np.float64)
+            X = solve_triangular(Lkk, C.T, lower=True).T  # C L_kk^{-T}
+            T(Lh, m, k)[:] = round_tile(X, p)[0]
+    return Lh, 0
+
+
+def refine(A: np.ndarray, Lh: np.ndarray, B: np.ndarray, tol: float = 1e-9, max_iter: int = 30):
+    """Iterative refinement with a (possibly low-precision) factor Lh, all
+    arithmetic binary64: x = (Lh Lh^T)^{-1} b, then repeat r = b - A x,
+    x += (Lh Lh^T)^{-1} r until max_j ||r_j|| / ||b_j|| <= tol.
+    Returns (X, iterations, relative residuals)."""
+    As = np.tril(A) + np.tril(A, -1).T
+    B = np.asarray(B, dtype=np.float64)
+    X = solve(Lh, B)
+    bn = np.linalg.norm(B, axis=0)
+    it = 0
+    while True:
+        R = B - As @ X
+        rel = np.linalg.norm(R, axis=0) / bn
+        if rel.max() <= tol or it >= max_iter:
+            return X, it, rel
+        X = X + solve(Lh, R)
+        it += 1

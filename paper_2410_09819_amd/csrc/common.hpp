@@ -14,6 +14,14 @@ __host__ __device__ inline int64_t tile_off(int64_t Nt, int64_t i, int64_t j) {
 typedef double d2 __attribute__((ext_vector_type(2)));
 typedef double d4 __attribute__((ext_vector_type(4)));
 
+// Value of v in lane `lane` of the wave (lane must be wave-uniform): two
+// v_readlane_b32 into scalar registers, no LDS round trip.
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+    return __hiloint2double(hi, lo);
+}
+
 // ---- launchers (all enqueue on `s`, return hipGetLastError()) -------------
 
 // Matern tiles + per-tile sum of squares partials (matern.hip).

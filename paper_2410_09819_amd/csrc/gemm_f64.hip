@@ -206,16 +206,34 @@ int64_t panel_blocks(int Nt, int nb, int k) {
     return T * (T + 1) / 2 + (int64_t)(Nt - k - 1) * T * T;
 }
 
-// Enough workgroups for two rounds of two resident workgroups per CU, with
-// at least 512 of K per split.
+// Split K for columns whose panel has few output blocks. Each split keeps
+// >= 512 of K and the partial sums stay under 512 MiB. The count minimises
+// an estimate of the column's time: rounds of 512 resident workgroups
+// (2 per CU) times one workgroup's K/S share at the FP64 MFMA rate, plus
+// writing and re-reading the partial sums at HBM speed; fewer splits win
+// unless clearly faster.
 int panel_splits(int Nt, int nb, int k) {
     const int64_t W = panel_blocks(Nt, nb, k);
     const int64_t K = (int64_t)k * nb;
-    int64_t s = (1024 + W - 1) / W;
-    const int64_t smax = K / 512;
-    if (s > smax) s = smax;
-    if (s > 32) s = 32;
-    return s < 1 ? 1 : (int)s;
+    const double panel_bytes = (double)(Nt - k) * nb * nb * sizeof(double);
+    int64_t smax = K / 512;
+    if (smax > 32) smax = 32;
+    while (smax > 1 && smax * panel_bytes > 512.0 * 1024 * 1024) --smax;
+    if (smax < 1) return 1;
+    const int64_t slots = 512;
+    const double slot_flops = 78.6e12 / slots;
+    double best = 1e300;
+    int bests = 1;
+    for (int64_t s = 1; s <= smax; ++s) {
+        const double rounds = (double)((W * s + slots - 1) / slots);
+        double t = rounds * (2.0 * 128 * 128 * ((double)K / s)) / slot_flops;
+        if (s > 1) t += 2.0 * s * panel_bytes / 5e12;
+        if (t < best * 0.97) {
+            best = t;
+            bests = (int)s;
+        }
+    }
+    return bests;
 }
 
 hipError_t launch_panel_update(hipStream_t s, double* L, int Nt, int nb, int k, int splits,

@@ -15,71 +15,98 @@
 namespace tc {
 namespace {
 
-constexpr int kNR = 16;   // right-hand sides per workgroup
-constexpr int kDB = 32;   // diagonal sub-block of the in-tile solve
+constexpr int kNR = 16;   // right-hand sides per workgroup of the update kernels
+constexpr int kDR = 4;    // right-hand sides per workgroup of the diagonal solve
+constexpr int kDB = 64;   // diagonal sub-block of the in-tile solve
 constexpr int kDBP = kDB + 1;
 
-// One workgroup per group of 16 right-hand sides: blocked substitution with
-// L_kk (or L_kk^T), sub-blocks of 32 rows staged in LDS.
+// Solve with the diagonal tile L_kk (or L_kk^T) for 4 right-hand sides per
+// workgroup, in 64-row sub-blocks. Wave w solves right-hand side w of the
+// sub-block by substitution across its 64 lanes (one row per lane, the
+// solved value broadcast with a lane shuffle); then all 256 threads apply
+// the sub-block to the remaining rows of the tile.
 __global__ __launch_bounds__(256) void trsv_diag_kernel(const double* __restrict__ Lkk, int nb,
                                                         double* __restrict__ B, int64_t ldb,
                                                         int nrhs, int transpose) {
-    __shared__ double Ls[kDB * kDBP];  // Ls[r * kDBP + c] = L[jb + r][jb + c]
-    __shared__ double Ys[kDB * kNR];   // Ys[r * kNR + c]
+    __shared__ double Ls[kDB * kDBP];  // Ls[l * kDBP + j] = L[jb + l][jb + j], l >= j
+    __shared__ double Rd[kDB];         // 1 / L[jb + j][jb + j]
+    __shared__ double X[kDB * kDR];    // X[l * kDR + c]: solved sub-block
     const int tid = threadIdx.x;
-    const int c0 = blockIdx.x * kNR;
-    const int nr = nrhs - c0 < kNR ? nrhs - c0 : kNR;
-    double* Bc = B + (int64_t)c0 * ldb;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int c0 = blockIdx.x * kDR;
+    const int nr = nrhs - c0 < kDR ? nrhs - c0 : kDR;
     const int nblk = nb / kDB;
     for (int bi = 0; bi < nblk; ++bi) {
         const int jb = transpose ? (nblk - 1 - bi) * kDB : bi * kDB;
         for (int e = tid; e < kDB * kDB; e += 256) {
-            const int c = e / kDB, r = e % kDB;
-            Ls[r * kDBP + c] = (r >= c) ? Lkk[(int64_t)(jb + c) * nb + jb + r] : 0.0;
-        }
-        for (int e = tid; e < kDB * kNR; e += 256) {
-            const int c = e / kDB, r = e % kDB;
-            if (c < nr) Ys[r * kNR + c] = Bc[(int64_t)c * ldb + jb + r];
+            const int j = e / kDB, l = e % kDB;
+            if (l >= j) {
+                const double v = Lkk[(int64_t)(jb + j) * nb + jb + l];
+                Ls[l * kDBP + j] = v;
+                if (l == j) Rd[j] = 1.0 / v;
+            }
         }
         __syncthreads();
-        if (tid < nr) {
-            const int c = tid;
+        if (wave < nr) {
+            double* bcol = B + (int64_t)(c0 + wave) * ldb + jb;
+            double y = bcol[lane];
+            const double rd = Rd[lane];
             if (!transpose) {
                 for (int j = 0; j < kDB; ++j) {
-                    double y = Ys[j * kNR + c];
-                    for (int l = 0; l < j; ++l) y -= Ls[j * kDBP + l] * Ys[l * kNR + c];
-                    Ys[j * kNR + c] = y / Ls[j * kDBP + j];
+                    const double xj = readlane_d(y, j) * readlane_d(rd, j);
+                    if (lane == j) y = xj;
+                    if (lane > j) y -= xj * Ls[lane * kDBP + j];
                 }
             } else {
                 for (int j = kDB - 1; j >= 0; --j) {
-                    double y = Ys[j * kNR + c];
-                    for (int l = j + 1; l < kDB; ++l) y -= Ls[l * kDBP + j] * Ys[l * kNR + c];
-                    Ys[j * kNR + c] = y / Ls[j * kDBP + j];
+                    const double xj = readlane_d(y, j) * readlane_d(rd, j);
+                    if (lane == j) y = xj;
+                    if (lane < j) y -= xj * Ls[j * kDBP + lane];
                 }
             }
+            X[lane * kDR + wave] = y;
+            bcol[lane] = y;
         }
         __syncthreads();
-        for (int e = tid; e < kDB * kNR; e += 256) {
-            const int c = e / kDB, r = e % kDB;
-            if (c < nr) Bc[(int64_t)c * ldb + jb + r] = Ys[r * kNR + c];
-        }
-        // update the rest of the tile's rows with this block
+        // apply the solved sub-block to the rest of the tile's rows; loads
+        // are issued 16 at a time
         if (!transpose) {
-            const int rows = nb - jb - kDB;
-            for (int e = tid; e < rows * nr; e += 256) {
-                const int c = e / rows, i = jb + kDB + e % rows;
-                double s = 0.0;
-                for (int l = 0; l < kDB; ++l) s += Lkk[(int64_t)(jb + l) * nb + i] * Ys[l * kNR + c];
-                Bc[(int64_t)c * ldb + i] -= s;
+            for (int i = jb + kDB + tid; i < nb; i += 256) {
+                double s[kDR] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 1
+                for (int l0 = 0; l0 < kDB; l0 += 16) {
+                    double lv[16];
+#pragma unroll
+                    for (int u = 0; u < 16; ++u) lv[u] = Lkk[(int64_t)(jb + l0 + u) * nb + i];
+#pragma unroll
+                    for (int u = 0; u < 16; ++u)
+#pragma unroll
+                        for (int c = 0; c < kDR; ++c) s[c] += lv[u] * X[(l0 + u) * kDR + c];
+                }
+#pragma unroll
+                for (int c = 0; c < kDR; ++c)
+                    if (c < nr) B[(int64_t)(c0 + c) * ldb + i] -= s[c];
             }
         } else {
-            const int rows = jb;
-            for (int e = tid; e < rows * nr; e += 256) {
-                const int c = e / rows, i = e % rows;
-                const double* li = Lkk + (int64_t)i * nb + jb;  // L[jb + l][i] = li[l]
-                double s = 0.0;
-                for (int l = 0; l < kDB; ++l) s += li[l] * Ys[l * kNR + c];
-                Bc[(int64_t)c * ldb + i] -= s;
+            for (int i = tid; i < jb; i += 256) {
+                const d2* li = reinterpret_cast<const d2*>(Lkk + (int64_t)i * nb + jb);  // L[jb + l][i]
+                double s[kDR] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 1
+                for (int l0 = 0; l0 < kDB / 2; l0 += 8) {
+                    d2 lv[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) lv[u] = li[l0 + u];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u)
+#pragma unroll
+                        for (int c = 0; c < kDR; ++c)
+                            s[c] += lv[u].x * X[(2 * (l0 + u)) * kDR + c] +
+                                    lv[u].y * X[(2 * (l0 + u) + 1) * kDR + c];
+                }
+#pragma unroll
+                for (int c = 0; c < kDR; ++c)
+                    if (c < nr) B[(int64_t)(c0 + c) * ldb + i] -= s[c];
             }
         }
         __threadfence_block();
@@ -87,41 +114,59 @@ __global__ __launch_bounds__(256) void trsv_diag_kernel(const double* __restrict
     }
 }
 
-// B_below[r][c] -= sum_j Lpanel[r][j] Y[j][c]; one thread per row.
-constexpr int kFwdRows = 256;
-constexpr int kFwdChunk = 128;
-__global__ __launch_bounds__(kFwdRows) void fwd_update_kernel(const double* __restrict__ Lcol,
-                                                              int nb, int64_t rows,
-                                                              const double* __restrict__ Y,
-                                                              double* __restrict__ Bb,
-                                                              int64_t ldb, int nrhs) {
-    __shared__ double Ys[kFwdChunk * kNR];
+// B_below[r][c] -= sum_j Lpanel[r][j] Y[j][c]. A workgroup owns 64 rows
+// (one per lane); its 4 waves split the nb columns j and combine their
+// partial sums in LDS in a fixed order. Y entries are uniform across a wave.
+constexpr int kFwdRows = 64;
+__global__ __launch_bounds__(256) void fwd_update_kernel(const double* __restrict__ Lcol, int nb,
+                                                         int64_t rows, const double* __restrict__ Y,
+                                                         double* __restrict__ Bb, int64_t ldb,
+                                                         int nrhs) {
+    __shared__ double red[4 * kFwdRows * kNR];
     const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int c0 = blockIdx.y * kNR;
     const int nr = nrhs - c0 < kNR ? nrhs - c0 : kNR;
-    const int64_t r = (int64_t)blockIdx.x * kFwdRows + tid;
+    const int64_t r = (int64_t)blockIdx.x * kFwdRows + lane;
     const int64_t nb2 = (int64_t)nb * nb;
     const double* lrow = Lcol + (r / nb) * nb2 + (r % nb);
+    const double* Yc = Y + (int64_t)c0 * ldb;
     double acc[kNR];
 #pragma unroll
     for (int c = 0; c < kNR; ++c) acc[c] = 0.0;
-    for (int j0 = 0; j0 < nb; j0 += kFwdChunk) {
-        __syncthreads();
-        for (int e = tid; e < kFwdChunk * kNR; e += kFwdRows) {
-            const int c = e / kFwdChunk, j = e % kFwdChunk;
-            Ys[j * kNR + c] = (c < nr) ? Y[(int64_t)(c0 + c) * ldb + j0 + j] : 0.0;
-        }
-        __syncthreads();
-        if (r < rows) {
-            for (int j = 0; j < kFwdChunk; ++j) {
-                const double lv = lrow[(int64_t)(j0 + j) * nb];
+    const int jq = nb / 4;
+    const int jbeg = wave * jq, jend = jbeg + jq;
+    if (nr == kNR) {
+        // 8 columns per iteration: their loads are issued together
+        for (int j = jbeg; j < jend; j += 8) {
+            double lv[8];
 #pragma unroll
-                for (int c = 0; c < kNR; ++c) acc[c] += lv * Ys[j * kNR + c];
-            }
+            for (int u = 0; u < 8; ++u) lv[u] = lrow[(int64_t)(j + u) * nb];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+#pragma unroll
+                for (int c = 0; c < kNR; ++c) acc[c] += lv[u] * Yc[(int64_t)c * ldb + j + u];
+        }
+    } else {
+        for (int j = jbeg; j < jend; ++j) {
+            const double lv = lrow[(int64_t)j * nb];
+#pragma unroll
+            for (int c = 0; c < kNR; ++c)
+                if (c < nr) acc[c] += lv * Yc[(int64_t)c * ldb + j];
         }
     }
-    if (r < rows)
-        for (int c = 0; c < nr; ++c) Bb[(int64_t)(c0 + c) * ldb + r] -= acc[c];
+#pragma unroll
+    for (int c = 0; c < kNR; ++c) red[(wave * kFwdRows + lane) * kNR + c] = acc[c];
+    __syncthreads();
+    for (int e = tid; e < kFwdRows * kNR; e += 256) {
+        const int rr = e % kFwdRows, c = e / kFwdRows;
+        if (c < nr) {
+            const double s = (red[(0 * kFwdRows + rr) * kNR + c] + red[(1 * kFwdRows + rr) * kNR + c]) +
+                             (red[(2 * kFwdRows + rr) * kNR + c] + red[(3 * kFwdRows + rr) * kNR + c]);
+            Bb[(int64_t)(c0 + c) * ldb + (int64_t)blockIdx.x * kFwdRows + rr] -= s;
+        }
+    }
 }
 
 // partial[split][j][c] = sum over the split's rows r of Lpanel[r][j] X[r][c]
@@ -194,16 +239,17 @@ __global__ __launch_bounds__(256) void logdet_kernel(const double* __restrict__ 
 
 hipError_t launch_trsv_diag(hipStream_t s, const double* Lkk, int nb, double* B, int64_t ldb,
                             int nrhs, bool transpose) {
-    hipLaunchKernelGGL(trsv_diag_kernel, dim3((nrhs + kNR - 1) / kNR), dim3(256), 0, s, Lkk, nb, B,
+    hipLaunchKernelGGL(trsv_diag_kernel, dim3((nrhs + kDR - 1) / kDR), dim3(256), 0, s, Lkk, nb, B,
                        ldb, nrhs, transpose ? 1 : 0);
     return hipGetLastError();
 }
 
 hipError_t launch_fwd_update(hipStream_t s, const double* Lcol, int nb, int64_t rows,
                              const double* Yk, double* Bbelow, int64_t ldb, int nrhs) {
-    dim3 grid((unsigned)((rows + kFwdRows - 1) / kFwdRows), (nrhs + kNR - 1) / kNR);
-    hipLaunchKernelGGL(fwd_update_kernel, grid, dim3(kFwdRows), 0, s, Lcol, nb, rows, Yk, Bbelow,
-                       ldb, nrhs);
+    if (rows % kFwdRows != 0 || nb % 32 != 0) return hipErrorInvalidValue;
+    dim3 grid((unsigned)(rows / kFwdRows), (nrhs + kNR - 1) / kNR);
+    hipLaunchKernelGGL(fwd_update_kernel, grid, dim3(256), 0, s, Lcol, nb, rows, Yk, Bbelow, ldb,
+                       nrhs);
     return hipGetLastError();
 }
 

@@ -1,16 +1,19 @@
 // Triangular solve X L^T = C for the tiles below a diagonal tile (the TRSM
-// task of Section III-A / Algorithm 1: L_mk = A_mk L_kk^{-T}), as one launch
-// over the whole column of tiles.
+// task of Section III-A / Algorithm 1: L_mk = A_mk L_kk^{-T}), over the whole
+// column of tiles at once.
 //
-// Each workgroup owns 64 rows of the panel and walks the w columns in
-// 64-wide blocks, left to right (blocked forward substitution, no explicit
-// inverse, so the solve stays backward stable):
-//   1. R = C[:, jb] - X[:, 0:jb] L[jb, 0:jb]^T   (FP64 MFMA, K = jb)
-//   2. X[:, jb] = R L[jb, jb]^{-T}               (substitution, one thread
-//                                                  per row, L block in LDS)
-// X overwrites C. Rows of the workgroup are re-read from global memory by
-// the same workgroup in later blocks; a workgroup-scope fence and barrier
-// order those accesses.
+// Recursive on the width w of L (no explicit inverse anywhere, so the solve
+// stays backward stable):
+//   X1 = C1 L11^{-T};  C2 -= X1 L21^T;  X2 = C2 L22^{-T}
+// The middle step is a large MFMA GEMM (M x w/2 x w/2) and carries 7/8 of
+// the flops for w = 1024. Widths <= 128 are solved by a fused leaf kernel:
+// each workgroup owns 64 rows and walks the columns in 64-wide blocks
+// (MFMA update with the columns already solved, then substitution against
+// the 64 x 64 diagonal block of L in LDS, four threads per row).
+//
+// C rows are "tile-strided": row r of the panel lives at
+// C + (r / nb) * nb^2 + (r % nb), column c at + c * nb (rows of consecutive
+// tiles of a tile column, or rows of one tile when M <= nb).
 #include "gemm_f64.hpp"
 
 namespace tc {
@@ -26,17 +29,23 @@ struct ColOp {
     __device__ const double* operator()(int64_t kk) const { return base + kk * ld; }
 };
 
-__global__ __launch_bounds__(kGemmThreads) void trsm_kernel(double* __restrict__ C,
-                                                            const double* __restrict__ L, int nb,
-                                                            int w) {
+__global__ __launch_bounds__(kGemmThreads) void trsm_leaf_kernel(double* __restrict__ C,
+                                                                 const double* __restrict__ L,
+                                                                 int nb, int w) {
     using Tl = MfmaTile<kRows, kCol>;
+    static_assert(kRows * kP <= Tl::LDS_DOUBLES, "solve block must fit the GEMM staging area");
     __shared__ double lds[Tl::LDS_DOUBLES];
-    __shared__ double S[kRows * kP];  // S[r * kP + c]: the block being solved, row-major
-    __shared__ double Ld[kCol * kP];  // Ld[j * kP + l] = L[jb + j][jb + l], l <= j
+    // S[r * kP + c]: the block being solved, row-major. It reuses the GEMM
+    // staging area, which the main loop has finished with (its last step ends
+    // with a barrier) before S is written.
+    double* S = lds;
+    __shared__ double Ld[kCol * kP];  // Ld[l * kP + j] = L[jb + l][jb + j], l >= j (column j contiguous in l)
     const int tid = threadIdx.x;
     const int64_t r0 = (int64_t)blockIdx.x * kRows;
     const int64_t nb2 = (int64_t)nb * nb;
     double* Cb = C + (r0 / nb) * nb2 + (r0 % nb);  // row 0 of this block; column c at + c*nb
+    // substitution layout: 4 threads per row; thread owns columns q + 4u
+    const int sr = tid >> 2, sq = tid & 3;
 
     for (int jb = 0; jb < w; jb += kCol) {
         d4 acc[Tl::MI][Tl::NI];
@@ -59,29 +68,35 @@ __global__ __launch_bounds__(kGemmThreads) void trsm_kernel(double* __restrict__
                     const int col = acc_col<kRows, kCol>(ni, v);
                     S[row * kP + col] = Cb[(int64_t)(jb + col) * nb + row] - acc[mi][ni][v];
                 }
-        // diagonal block of L, lower part
         for (int e = tid; e < kCol * kCol; e += kGemmThreads) {
-            const int l = e / kCol, j = e % kCol;  // column l, row j: coalesced in j
-            if (j >= l) Ld[j * kP + l] = L[(int64_t)(jb + l) * nb + jb + j];
+            const int j = e / kCol, l = e % kCol;  // column j, row l: coalesced in l
+            if (l >= j) Ld[l * kP + j] = L[(int64_t)(jb + j) * nb + jb + l];
         }
         __syncthreads();
 
-        if (tid < kRows) {
-            double* s = S + tid * kP;
-            for (int j = 0; j < kCol; ++j) {
-                const double* lj = Ld + j * kP;
-                double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
-                int l = 0;
-                for (; l + 4 <= j; l += 4) {
-                    p0 += s[l] * lj[l];
-                    p1 += s[l + 1] * lj[l + 1];
-                    p2 += s[l + 2] * lj[l + 2];
-                    p3 += s[l + 3] * lj[l + 3];
-                }
-                for (; l < j; ++l) p0 += s[l] * lj[l];
-                s[j] = (s[j] - ((p0 + p1) + (p2 + p3))) / lj[j];
+        // right-looking substitution on row sr: for j: x_j = y_j / L_jj, then
+        // y_l -= x_j L[l][j] for l > j. Thread sq holds y_l for l = sq + 4u.
+        double y[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) y[u] = S[sr * kP + sq + 4 * u];
+#pragma unroll
+        for (int j = 0; j < kCol; ++j) {
+            const int ju = j >> 2, jq = j & 3;
+            double xj = 0.0;
+            if (sq == jq) {
+                y[ju] = y[ju] / Ld[j * kP + j];
+                xj = y[ju];
+            }
+            xj = __shfl(xj, (threadIdx.x & 63 & ~3) | jq, 64);
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                if (4 * u + 3 <= j) continue;  // all four columns done (compile time)
+                const int l = sq + 4 * u;
+                if (l > j) y[u] -= xj * Ld[l * kP + j];
             }
         }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) S[sr * kP + sq + 4 * u] = y[u];
         __syncthreads();
 
         // X block -> global, coalesced along rows
@@ -94,12 +109,82 @@ __global__ __launch_bounds__(kGemmThreads) void trsm_kernel(double* __restrict__
     }
 }
 
+// C (M x N, tile-strided rows) -= A (M x K, tile-strided rows) B^T, B N x K
+// inside one tile (leading dimension nb). 128 x 128 blocks; M, N multiples
+// of 128, K a multiple of 16.
+constexpr int kGB = 128;
+
+struct StridedOp {
+    const double* base;  // row 0 of the block
+    int64_t ld;
+    __device__ const double* operator()(int64_t kk) const { return base + kk * ld; }
+};
+
+__device__ __forceinline__ int64_t xcd_remap_t(int64_t hw, int64_t total) {
+    const int64_t xcd = hw % 8, idx = hw / 8;
+    const int64_t q = total / 8, r = total % 8;
+    return xcd * q + (xcd < r ? xcd : r) + idx;
+}
+
+__global__ __launch_bounds__(kGemmThreads, 2) void strided_gemm_kernel(
+    double* __restrict__ C, const double* __restrict__ A, const double* __restrict__ B, int nb,
+    int64_t M, int N, int K) {
+    using Tl = MfmaTile<kGB, kGB>;
+    __shared__ double lds[Tl::LDS_DOUBLES];
+    const int nbc = N / kGB;
+    const int64_t total = (M / kGB) * nbc;
+    const int64_t logical = xcd_remap_t(blockIdx.x, total);
+    const int64_t br = logical / nbc;
+    const int bc = (int)(logical - br * nbc);
+    const int64_t r0 = br * kGB;
+    const int64_t nb2 = (int64_t)nb * nb;
+    const int64_t roff = (r0 / nb) * nb2 + (r0 % nb);
+
+    d4 acc[Tl::MI][Tl::NI];
+#pragma unroll
+    for (int mi = 0; mi < Tl::MI; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < Tl::NI; ++ni) acc[mi][ni] = d4{0.0, 0.0, 0.0, 0.0};
+    const StridedOp aop{A + roff, nb};
+    const StridedOp bop{B + (int64_t)bc * kGB, nb};
+    mfma_mainloop<kGB, kGB>(acc, aop, bop, nb, 0, K, lds);
+
+    double* out = C + roff + (int64_t)bc * kGB * nb;
+#pragma unroll
+    for (int mi = 0; mi < Tl::MI; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < Tl::NI; ++ni)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = acc_row<kGB, kGB>(mi);
+                const int col = acc_col<kGB, kGB>(ni, v);
+                out[(int64_t)col * nb + row] -= acc[mi][ni][v];
+            }
+}
+
+hipError_t trsm_rec(hipStream_t s, double* C, const double* L, int nb, int64_t M, int w) {
+    if (w <= 128) {
+        hipLaunchKernelGGL(trsm_leaf_kernel, dim3((unsigned)(M / kRows)), dim3(kGemmThreads), 0, s,
+                           C, L, nb, w);
+        return hipGetLastError();
+    }
+    const int h = ((w / 2 + 127) / 128) * 128;
+    hipError_t e = trsm_rec(s, C, L, nb, M, h);
+    if (e != hipSuccess) return e;
+    // C2 -= X1 L21^T: C2 = columns [h, w), X1 = columns [0, h), L21 = L[h:w, 0:h]
+    const int64_t blocks = (M / kGB) * ((w - h) / kGB);
+    hipLaunchKernelGGL(strided_gemm_kernel, dim3((unsigned)blocks), dim3(kGemmThreads), 0, s,
+                       C + (int64_t)h * nb, C, L + h, nb, M, w - h, h);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return trsm_rec(s, C + (int64_t)h * nb, L + h + (int64_t)h * nb, nb, M, w - h);
+}
+
 }  // namespace
 
 hipError_t launch_trsm(hipStream_t s, double* C, const double* L, int nb, int64_t M, int w) {
-    hipLaunchKernelGGL(trsm_kernel, dim3((unsigned)(M / kRows)), dim3(kGemmThreads), 0, s, C, L,
-                       nb, w);
-    return hipGetLastError();
+    if (M % kGB != 0 || w % kGB != 0) return hipErrorInvalidValue;
+    return trsm_rec(s, C, L, nb, M, w);
 }
 
 }  // namespace tc

@@ -1,5 +1,8 @@
 """Benchmark: FP64 tile Cholesky of the n=65536, nb=1024 Matern covariance
-(nu=1.5, range=0.1, nugget=1e-6) on one MI355X.
+(nu=1.5, range=0.1, nugget=1e-6) on one MI355X, plus the mixed-precision
+versus FP64 time-to-solution on the n=131072, nb=1024 Matern workload
+(nu=0.5, range=0.03, nugget=1e-4, target accuracy 1e-9, 16 right-hand sides,
+refined to 1e-9 relative residual).
 
 One step = factorization (panel GEMM/SYRK, POTRF, TRSM under the static
 left-looking schedule) + log-determinant + solve with 16 right-hand sides,
@@ -46,6 +49,73 @@ def cpu_baseline(w, ns=4096):
                       "(%.1f s)" % (ns, ns, w["nb"], dt)}
 
 
+def mxp_comparison(tc, si, dev):
+    """Time-to-solution at n=131072: FP64 = factorization + 16-RHS solve;
+    mixed precision = tile norms already known from generation, precision
+    map + factorization + refined 16-RHS solve to 1e-9. Same matrix, same
+    right-hand sides, matrix resident in HBM."""
+    import numpy as np
+    import torch
+    w = si.WORKLOADS["mxp"]
+    n, nb, nrhs = w["n"], w["nb"], w["nrhs"]
+    theta = (w["sigma2"], w["range"], w["nu"], w["nugget"])
+    pts = torch.from_numpy(si.points(n, seed=w["seed"])).to(dev)
+    ctx = tc.Context(n, nb, nrhs=nrhs)
+    A, tf, fro = tc.matern_tiles(ctx, pts, theta, nb)
+    tf_h = tf.cpu().numpy()
+    B0 = torch.from_numpy(np.ascontiguousarray(
+        si.standard_normal((n, nrhs), seed=si.rhs_seed(w["seed"])).T)).to(dev)
+    B = torch.empty_like(B0)
+    Nt = n // nb
+    out = {"workload": "mxp tile Cholesky, n=%d nb=%d, Matern nu=%g range=%g nugget=%g, target %g, "
+                       "%d RHS refined to 1e-9" % (n, nb, w["nu"], w["range"], w["nugget"], w["eps"], nrhs)}
+    # FP64 path
+    storage = torch.empty(tc.factor_bytes(n, nb) // 8, dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    F = tc.factorize(ctx, A, n, nb, storage=storage)
+    B.copy_(B0)
+    tc.solve(ctx, F, B)
+    torch.cuda.synchronize()
+    t_fp64 = time.perf_counter() - t0
+    ms_f64 = F.stats.ms_total
+    F.close()
+    del storage, F
+    torch.cuda.empty_cache()
+    # mixed precision
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cm = tc.precision_map(Nt, tf_h, fro, w["eps"])
+    storage = torch.empty(tc.factor_bytes(n, nb, cm) // 8, dtype=torch.float64, device=dev)
+    F = tc.factorize(ctx, A, n, nb, cmap=cm, storage=storage)
+    B.copy_(B0)
+    st = tc.solve_refine(ctx, F, A, B, max_iter=30, tol=1e-9)
+    torch.cuda.synchronize()
+    t_mxp = time.perf_counter() - t0
+    flops = n ** 3 / 3.0
+    cls = list(F.stats.class_tiles)
+    cf = list(F.stats.class_flops)
+    out.update({
+        "fp64_time_to_solution_s": t_fp64,
+        "fp64_factor_ms": ms_f64,
+        "fp64_tflops": flops / (ms_f64 * 1e-3) / 1e12,
+        "mxp_time_to_solution_s": t_mxp,
+        "mxp_factor_ms": F.stats.ms_total,
+        "mxp_tflops_fp64_equivalent": flops / (F.stats.ms_total * 1e-3) / 1e12,
+        "speedup_time_to_solution": t_fp64 / t_mxp,
+        "ir_iterations": st["iterations"],
+        "ir_rel_residual": st["rel_residual"],
+        "ir_ms": st["ms_total"],
+        "class_tiles": dict(zip(["fp64", "fp32", "fp16", "bf16", "fp8"], cls)),
+        "class_flop_share": dict(zip(["fp64", "fp32", "fp16", "bf16", "fp8"],
+                                     [c / max(sum(cf), 1.0) for c in cf])),
+    })
+    F.close()
+    del storage, F, A
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -53,6 +123,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mxp", action="store_true", help="skip the mixed-precision comparison")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the tile Cholesky here runs on a single MI355X "
@@ -143,8 +214,10 @@ def main():
         },
         "cpu_baseline": None,
     }
-    del storage, A
+    F.close()
+    del storage, A, F
     torch.cuda.empty_cache()
+    out["mxp_vs_fp64"] = None if args.no_mxp else mxp_comparison(tc, si, dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)

@@ -79,9 +79,32 @@ typedef struct {
     double gemm_flops;      /* algorithmic flops of those launches */
     int32_t gemm_launches;  /* number of panel GEMM/SYRK launches */
     int32_t info;           /* same as the positive return value, or 0 */
-    double flops_total;     /* n^3/3 + lower-order terms actually executed (all classes) */
-    double reserved[6];
+    double flops_total;     /* n^3/3, the count the throughput metric uses */
+    double class_flops[5];  /* panel-update flops executed per class (tc_prec order) */
+    int32_t class_tiles[5]; /* stored tiles per class */
+    int32_t reserved;
 } tc_stats;
+
+typedef struct {
+    int32_t iterations;     /* refinement corrections applied */
+    int32_t converged;      /* 1 if max_j ||b_j - A x_j|| / ||b_j|| <= tol */
+    double rel_residual;    /* final max_j ||b_j - A x_j||_2 / ||b_j||_2 (binary64) */
+    double history[32];     /* the same quantity after the first solve and each correction */
+    double ms_total;        /* wall time of the whole solve, HIP events */
+} tc_ir_stats;
+
+typedef struct {
+    uint64_t bytes_h2d;      /* host -> HBM bytes (accumulators and reloaded operand tiles) */
+    uint64_t bytes_d2h;      /* HBM -> host bytes (write-back of the factor) */
+    int32_t tiles_reloaded;  /* operand tiles loaded from the host copy of L */
+    int32_t evictions;       /* cached tiles evicted to make room */
+    int32_t chunks;          /* panel-update launches (K chunks) */
+    int32_t cache_slots;     /* tiles the cache holds */
+    double ms_total;         /* wall time, HIP events */
+    double flops_total;      /* n^3/3 */
+    int32_t info;            /* LAPACK info or 0 */
+    int32_t reserved;
+} tc_ooc_stats;
 
 /* Tiles stored before lower tile (i,j), i >= j, in packed lower order:
  * j*Nt - j*(j-1)/2 + (i-j). Returns -1 if the indices are out of range. */
@@ -95,7 +118,7 @@ const char *tc_version(void);
 const char *tc_last_error(void);
 
 /* Bytes of device workspace a context needs for matrices up to order n with
- * tile size nb and up to nrhs right-hand sides per solve. */
+ * tile size nb and up to nrhs right-hand sides per refined solve. */
 size_t tc_workspace_bytes(int64_t n, int32_t nb, int32_t nrhs);
 
 /* Create a context on HIP device `device`. `workspace` is a device buffer of
@@ -122,14 +145,29 @@ tc_status tc_ctx_destroy(tc_ctx *ctx);
 tc_status tc_matern_tiles(tc_ctx *ctx, int64_t n, int32_t nb, const double *locs,
                           const tc_matern *theta, double *A, double *tile_fro, double *fro_A);
 
+/* Per-tile precision map (Section IV-C): tile (i,j), i > j, takes the lowest
+ * class p in allowed_mask (bit c set = class c allowed) for which
+ *   Nt * tile_fro[t] / fro_A < eps / eps_p
+ * holds, eps_p being the class's machine epsilon 2^(1-p_bits) (or its unit
+ * roundoff 2^-p_bits when unit_roundoff != 0); otherwise, and on the
+ * diagonal, TC_FP64. tile_fro: host, Nt(Nt+1)/2 Frobenius norms in packed
+ * order; fro_A: ||A||_F of the full symmetric matrix; map_out: host,
+ * Nt(Nt+1)/2 bytes. Host-only computation. */
+tc_status tc_precision_map(int32_t Nt, const double *tile_fro, double fro_A, double eps,
+                           uint32_t allowed_mask, int32_t unit_roundoff, uint8_t *map_out);
+
 /* Tile Cholesky factorization (Algorithm 1 under a static schedule).
  * A: device packed lower tiles (n, nb), binary64, read only unless
- *    storage == A.
+ *    storage == A (allowed for all-FP64 maps only).
  * map: host, Nt(Nt+1)/2 tc_prec codes in packed order, or NULL for all
- *    TC_FP64. (This build factors FP64 maps only; others give
- *    TC_EUNSUPPORTED.)
+ *    TC_FP64. Diagonal tiles must be TC_FP64. With low-precision tiles the
+ *    factor is stored per tile in its class (FP16 and FP8 tiles with a
+ *    power-of-two scale), each update into a tile of class p is computed
+ *    from operands rounded to p with FP32 accumulation, POTRF and TRSM run
+ *    in FP64 and each new tile is rounded to its class.
  * storage: device buffer of tc_factor_bytes(n, nb, map) bytes that receives
- *    the factor's tiles; it may equal A (in place). It must outlive *L.
+ *    the factor (tiles, operand copies for the low-precision updates and the
+ *    factor's own tables). It must outlive *L.
  * L: receives a new factor handle (free with tc_factor_destroy), also when
  *    the return value is positive (the factor is then partial).
  * stats: NULL or filled. */
@@ -138,16 +176,50 @@ tc_status tc_factorize(tc_ctx *ctx, int64_t n, int32_t nb, const double *A, cons
                        const tc_opts *opts, void *storage, size_t storage_bytes,
                        tc_factor **L, tc_stats *stats);
 
-/* Solve Sigma X = B with the factor: B <- L^{-T} L^{-1} B.
+/* Solve Sigma X = B with the factor: B <- L^{-T} L^{-1} B (tiles used as
+ * stored, upcast to binary64).
  * B: device, n x nrhs binary64, column-major with leading dimension ldb >= n. */
 tc_status tc_solve(tc_ctx *ctx, const tc_factor *L, double *B, int64_t ldb, int32_t nrhs);
+
+/* Iterative refinement in binary64 (not in the paper; the classic scheme it
+ * cites): x = (L L^T)^{-1} b, then repeat r = b - A x (binary64, A from its
+ * packed lower tiles), x += (L L^T)^{-1} r until max_j ||r_j|| / ||b_j|| <= tol
+ * or max_iter corrections. A: the matrix that was factored (device packed
+ * lower tiles). B: on input b, on output x (device, column-major, ldb).
+ * Returns TC_ENOTCONV (with stats filled) if tol is not reached. The
+ * workspace must be sized with tc_workspace_bytes(n, nb, nrhs') for some
+ * nrhs' >= nrhs. */
+tc_status tc_solve_refine(tc_ctx *ctx, const tc_factor *L, const double *A, double *B,
+                          int64_t ldb, int32_t nrhs, int32_t max_iter, double tol,
+                          tc_ir_stats *stats);
 
 /* log|Sigma| = 2 sum_i log L_ii (Eq. 1's log-determinant), into *out (host). */
 tc_status tc_logdet(tc_ctx *ctx, const tc_factor *L, double *out);
 
-/* Copy the factor into L64 (device, packed lower tiles, binary64) with the
- * strict upper triangle of every diagonal tile set to zero. L64 may be the
- * factor's own storage. */
+/* Out-of-core FP64 tile Cholesky (Sections III-C and IV-B): the matrix and
+ * the factor stay in host memory and stream through HBM under the static
+ * left-looking schedule.
+ * A_host: pinned host memory (hipHostMalloc or equivalent), packed lower
+ *    tiles (n, nb), binary64, read.
+ * L_host: pinned host memory of the same size receiving the factor; it may
+ *    equal A_host (in place: column k of A is read before column k of L is
+ *    written back).
+ * cache: device buffer of cache_bytes bytes used as a fixed-slot tile cache
+ *    (at least 2 * Nt tiles of nb*nb binary64); the two working columns come
+ *    from the context workspace.
+ * Operand tiles are streamed through the cache in chunks of tile columns
+ * when it cannot hold a column's whole working set; evictions take the tile
+ * with the farthest next use under the static schedule. The work runs on
+ * the compute stream and two library streams (host->device, device->host),
+ * all at the default priority. Returns after everything has completed; the
+ * factor is L_host (no tc_factor handle). */
+tc_status tc_factorize_ooc(tc_ctx *ctx, int64_t n, int32_t nb, const double *A_host,
+                           double *L_host, void *cache, size_t cache_bytes, tc_ooc_stats *stats);
+
+/* Copy the factor into L64 (device, packed lower tiles, binary64; each tile
+ * upcast from its class) with the strict upper triangle of every diagonal
+ * tile set to zero. For an all-FP64 factor L64 may be the factor's own
+ * storage; otherwise it must be a separate buffer. */
 tc_status tc_factor_export(tc_ctx *ctx, const tc_factor *L, double *L64);
 
 /* Free the handle (not the caller's storage). NULL is accepted. */

@@ -360,3 +360,61 @@ def refine(A: np.ndarray, Lh: np.ndarray, B: np.ndarray, tol: float = 1e-9, max_
             return X, it, rel
         X = X + solve(Lh, R)
         it += 1
+
+
+# ---------------------------------------------------------------------------
+# Gaussian log-likelihood (Eq. 1) and its gradient with respect to
+# theta = (sigma2, range, nugget) at fixed smoothness nu.
+# ---------------------------------------------------------------------------
+
+def loglik(pts, y, sigma2, rng, nu, nugget, nb=None):
+    """l = -n/2 log(2 pi) - 1/2 log|Sigma| - 1/2 y^T Sigma^{-1} y, through the
+    oracle's tile Cholesky."""
+    n = len(pts)
+    A = matern_matrix(pts, sigma2, rng, nu, nugget)
+    L, info = tile_cholesky(A, nb or n, threads=8)
+    if info:
+        raise ValueError("not positive definite")
+    z = forward_solve(L, np.asarray(y, dtype=np.float64))
+    return -0.5 * n * math.log(2.0 * math.pi) - 0.5 * logdet(L) - 0.5 * float(np.sum(z * z))
+
+
+def matern_dcov(pts, sigma2, rng, nu):
+    """(dSigma/dsigma2, dSigma/drange) as dense matrices (dSigma/dnugget = I).
+    dC/dsigma2 = C / sigma2; with x = h / a and d/dx[x^nu K_nu(x)] =
+    -x^nu K_{nu-1}(x), dC/da = sigma2 / (2^(nu-1) Gamma(nu)) x^(nu+1)
+    K_{nu-1}(x) / a, which is 0 at h = 0."""
+    from scipy.special import gamma, kv
+    n = len(pts)
+    I, J = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    h = distances(pts, I, J)
+    C = matern(h, sigma2, rng, nu)
+    x = h / rng
+    dA = np.zeros_like(x)
+    pos = x > 0
+    xp = x[pos]
+    dA[pos] = sigma2 / (2.0 ** (nu - 1.0) * gamma(nu)) * xp ** (nu + 1.0) * kv(nu - 1.0, xp) / rng
+    return C / sigma2, dA
+
+
+def loglik_grad(pts, y, sigma2, rng, nu, nugget, nb=None):
+    """Gradient of l by the trace formula
+        dl/dtheta_p = 1/2 alpha^T (dSigma/dtheta_p) alpha
+                      - 1/2 tr(Sigma^{-1} dSigma/dtheta_p),
+    alpha = Sigma^{-1} y, Sigma^{-1} from the oracle's factor. Returns
+    (l, [dl/dsigma2, dl/drange, dl/dnugget])."""
+    n = len(pts)
+    A = matern_matrix(pts, sigma2, rng, nu, nugget)
+    L, info = tile_cholesky(A, nb or n, threads=8)
+    if info:
+        raise ValueError("not positive definite")
+    y = np.asarray(y, dtype=np.float64)
+    z = forward_solve(L, y)
+    alpha = solve(L, y)
+    Sinv = solve(L, np.eye(n))
+    l = -0.5 * n * math.log(2.0 * math.pi) - 0.5 * logdet(L) - 0.5 * float(np.sum(z * z))
+    d_s2, d_a = matern_dcov(pts, sigma2, rng, nu)
+    g = []
+    for D in (d_s2, d_a, np.eye(n)):
+        g.append(0.5 * float(alpha @ D @ alpha) - 0.5 * float(np.sum(Sinv * D)))
+    return l, np.array(g)

@@ -49,7 +49,34 @@ class Stats(ctypes.Structure):
     _fields_ = [("ms_total", ctypes.c_double), ("ms_gemm", ctypes.c_double),
                 ("gemm_flops", ctypes.c_double), ("gemm_launches", ctypes.c_int32),
                 ("info", ctypes.c_int32), ("flops_total", ctypes.c_double),
-                ("reserved", ctypes.c_double * 6)]
+                ("class_flops", ctypes.c_double * 5), ("class_tiles", ctypes.c_int32 * 5),
+                ("reserved", ctypes.c_int32)]
+
+    def as_dict(self):
+        d = {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+        d["class_flops"] = list(self.class_flops)
+        d["class_tiles"] = list(self.class_tiles)
+        return d
+
+
+class IrStats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("rel_residual", ctypes.c_double), ("history", ctypes.c_double * 32),
+                ("ms_total", ctypes.c_double)]
+
+    def as_dict(self):
+        return {"iterations": self.iterations, "converged": bool(self.converged),
+                "rel_residual": self.rel_residual,
+                "history": list(self.history[:min(self.iterations + 1, 32)]),
+                "ms_total": self.ms_total}
+
+
+class OocStats(ctypes.Structure):
+    _fields_ = [("bytes_h2d", ctypes.c_uint64), ("bytes_d2h", ctypes.c_uint64),
+                ("tiles_reloaded", ctypes.c_int32), ("evictions", ctypes.c_int32),
+                ("chunks", ctypes.c_int32), ("cache_slots", ctypes.c_int32),
+                ("ms_total", ctypes.c_double), ("flops_total", ctypes.c_double),
+                ("info", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
@@ -81,7 +108,12 @@ def lib():
         "tc_factorize": (_i32, [_vp, _i64, _i32, _vp, _vp, ctypes.POINTER(Opts), _vp, _sz,
                                 ctypes.POINTER(_vp), ctypes.POINTER(Stats)]),
         "tc_solve": (_i32, [_vp, _vp, _vp, _i64, _i32]),
+        "tc_solve_refine": (_i32, [_vp, _vp, _vp, _vp, _i64, _i32, _i32, ctypes.c_double,
+                                   ctypes.POINTER(IrStats)]),
+        "tc_precision_map": (_i32, [_i32, _vp, ctypes.c_double, ctypes.c_double, ctypes.c_uint32,
+                                    _i32, _vp]),
         "tc_logdet": (_i32, [_vp, _vp, ctypes.POINTER(ctypes.c_double)]),
+        "tc_factorize_ooc": (_i32, [_vp, _i64, _i32, _vp, _vp, _vp, _sz, ctypes.POINTER(OocStats)]),
         "tc_factor_export": (_i32, [_vp, _vp, _vp]),
         "tc_factor_destroy": (_i32, [_vp]),
     }
@@ -117,6 +149,20 @@ def factor_bytes(n: int, nb: int, cmap=None) -> int:
         return lib().tc_factor_bytes(n, nb, None)
     m = np.ascontiguousarray(cmap, dtype=np.uint8)
     return lib().tc_factor_bytes(n, nb, m.ctypes.data)
+
+
+def precision_map(Nt: int, tile_fro, fro: float, eps: float,
+                  allowed=(FP64, FP32, FP16, FP8E4M3), unit_roundoff: bool = False) -> np.ndarray:
+    """Per-tile class codes (uint8, packed order) from the tile norms
+    (Section IV-C criterion, computed by the library on the host)."""
+    tf = np.ascontiguousarray(np.asarray(tile_fro, dtype=np.float64))
+    out = np.zeros(Nt * (Nt + 1) // 2, dtype=np.uint8)
+    mask = 0
+    for c in allowed:
+        mask |= 1 << int(c)
+    _check(lib().tc_precision_map(Nt, tf.ctypes.data, float(fro), float(eps), mask,
+                                  1 if unit_roundoff else 0, out.ctypes.data))
+    return out
 
 
 def num_tiles(n: int, nb: int) -> int:
@@ -252,6 +298,36 @@ def solve(ctx: Context, F: Factor, B):
     nrhs = 1 if B.dim() == 1 else B.shape[0]
     _check(lib().tc_solve(ctx.handle, F.handle, B.data_ptr(), F.n, nrhs))
     return B
+
+
+def solve_refine(ctx: Context, F: Factor, A, B, max_iter: int = 30, tol: float = 1e-9,
+                 check: bool = True):
+    """In place: B <- x refined to max_j ||b_j - A x_j|| / ||b_j|| <= tol, A the
+    packed lower tiles that were factored. Returns the statistics dict;
+    raises TileCholError(TC_ENOTCONV) when check is set and tol is not met."""
+    assert B.is_contiguous() and B.shape[-1] == F.n
+    nrhs = 1 if B.dim() == 1 else B.shape[0]
+    st = IrStats()
+    status = lib().tc_solve_refine(ctx.handle, F.handle, A.data_ptr(), B.data_ptr(), F.n, nrhs,
+                                   max_iter, tol, ctypes.byref(st))
+    if status != 0 and (check or status != TC_ENOTCONV):
+        _check(status)
+    return st.as_dict()
+
+
+def factorize_ooc(ctx: Context, A_host, n: int, nb: int, cache, L_host=None) -> dict:
+    """Out-of-core factorization: A_host (pinned CPU float64 tensor, packed
+    lower tiles) streams through the device tile cache `cache` (a device
+    tensor); the factor is written to L_host (default: in place over A_host).
+    Returns the transfer statistics. Raises NotPositiveDefinite."""
+    assert A_host.device.type == "cpu" and A_host.is_pinned()
+    L_host = A_host if L_host is None else L_host
+    assert L_host.device.type == "cpu" and L_host.is_pinned()
+    st = OocStats()
+    _check(lib().tc_factorize_ooc(ctx.handle, n, nb, A_host.data_ptr(), L_host.data_ptr(),
+                                  cache.data_ptr(), cache.numel() * cache.element_size(),
+                                  ctypes.byref(st)))
+    return st.as_dict()
 
 
 def logdet(ctx: Context, F: Factor) -> float:

@@ -22,6 +22,18 @@ __device__ __forceinline__ double readlane_d(double v, int lane) {
     return __hiloint2double(hi, lo);
 }
 
+// Read-only view of a factor's tiles. Without tables (toff == nullptr) the
+// tiles are binary64 in packed lower order at `base`; otherwise tile t is
+// stored in class tcls[t] at base + toff[t] bytes, scaled by 2^tscl[t].
+struct TileView {
+    const char* base;
+    const int64_t* toff;
+    const uint8_t* tcls;
+    const int* tscl;
+    int Nt;
+    int nb;
+};
+
 // ---- launchers (all enqueue on `s`, return hipGetLastError()) -------------
 
 // Matern tiles + per-tile sum of squares partials (matern.hip).
@@ -65,15 +77,43 @@ hipError_t launch_zero_info(hipStream_t s, int* info);
 // Strict upper triangle of every diagonal tile to zero (export).
 hipError_t launch_zero_upper(hipStream_t s, double* L, int Nt, int nb);
 
-// Solves with the factor (solve.hip).
+// Solves with the factor (solve.hip). Lkk is the (binary64) diagonal tile.
 hipError_t launch_trsv_diag(hipStream_t s, const double* Lkk, int nb, double* B, int64_t ldb,
                             int nrhs, bool transpose);
-hipError_t launch_fwd_update(hipStream_t s, const double* Lcol, int nb, int64_t rows,
-                             const double* Yk, double* Bbelow, int64_t ldb, int nrhs);
-hipError_t launch_bwd_update(hipStream_t s, const double* Lcol, int nb, int64_t rows,
-                             const double* Xbelow, double* Yk, int64_t ldb, int nrhs,
-                             double* partial, int splits);
+// B rows below tile k -= L[k+1.., k] Y_k (Y_k = B rows of tile k).
+hipError_t launch_fwd_update(hipStream_t s, const TileView& L, int k, const double* Yk,
+                             double* Bbelow, int64_t ldb, int nrhs);
+// Y_k -= sum_{m>k} L_mk^T X_m (X = B rows below tile k).
+hipError_t launch_bwd_update(hipStream_t s, const TileView& L, int k, const double* Xbelow,
+                             double* Yk, int64_t ldb, int nrhs, double* partial, int splits);
 int bwd_splits(int64_t rows);
-hipError_t launch_logdet_partials(hipStream_t s, const double* L, int Nt, int nb, double* partial);
+hipError_t launch_logdet_partials(hipStream_t s, const TileView& L, double* partial);
+
+// Mixed precision (mxp.hip): class-group panel updates into the working
+// column W (binary64, tile-strided rows, W[0] = diagonal tile), and the
+// finalize step that rounds column k's new tiles into storage.
+hipError_t launch_mxp_gemm_f64(hipStream_t s, double* W, int Nt, int nb, int k, const int* rows,
+                               int nrows, bool diag, const char* storage, const int64_t* toff,
+                               const uint8_t* tcls, const int* tscl);
+hipError_t launch_mxp_gemm_f32(hipStream_t s, double* W, int Nt, int nb, int k, const int* rows,
+                               int nrows, int cls, const char* storage, const int64_t* shoff);
+hipError_t launch_mxp_finalize(hipStream_t s, const double* W, int Nt, int nb, int k, double* part,
+                               char* storage, const int64_t* toff, const uint8_t* tcls, int* tscl,
+                               const int64_t* shoff);
+hipError_t launch_export(hipStream_t s, const TileView& L, double* out);
+
+// Refinement (ir.hip).
+int symv_chunk();
+size_t residual_partial_doubles(int Nt, int nb, int nrhs);
+hipError_t launch_residual(hipStream_t s, const double* A, int Nt, int nb, const double* X,
+                           int64_t ldx, const double* B, int64_t ldb, int nrhs, double* partial,
+                           double* R, int64_t ldr);
+int colnorm_blocks();
+hipError_t launch_colnorm(hipStream_t s, const double* X, int64_t ld, int64_t n, int nrhs,
+                          double* part);
+hipError_t launch_axpy(hipStream_t s, double* Y, int64_t ldy, const double* D, int64_t ldd,
+                       int64_t n, int nrhs);
+hipError_t launch_copy_cols(hipStream_t s, double* Y, int64_t ldy, const double* X, int64_t ldx,
+                            int64_t n, int nrhs);
 
 }  // namespace tc

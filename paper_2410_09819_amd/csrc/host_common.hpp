@@ -1,0 +1,88 @@
+// Host-side pieces shared by the C-ABI translation units: the context and
+// factor objects, error reporting, workspace layout, argument checks and the
+// recursive in-tile POTRF driver.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+#include "tilechol.h"
+
+struct tc_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    uint32_t flags = 0;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    std::vector<hipEvent_t> gemm_ev;
+    // out-of-core resources, created on first use
+    hipStream_t h2d = nullptr, d2h = nullptr;
+    void* pinned = nullptr;
+    size_t pinned_bytes = 0;
+};
+
+struct tc_factor {
+    int64_t n = 0;
+    int nb = 0;
+    int Nt = 0;
+    double* tiles = nullptr;  // all-FP64 factor: packed binary64 tiles
+    int info = 0;
+    // mixed-precision factor: tiles per class inside `storage`, tables on the
+    // device (also inside `storage`) and the tile offsets on the host
+    bool mixed = false;
+    char* storage = nullptr;
+    const int64_t* d_toff = nullptr;
+    const uint8_t* d_tcls = nullptr;
+    const int* d_tscl = nullptr;
+    std::vector<int64_t> toff;
+};
+
+namespace tc {
+namespace host {
+
+// Records msg as the calling thread's last error and returns s.
+tc_status fail(tc_status s, const std::string& msg);
+extern thread_local std::string g_err;
+
+inline size_t align_up(size_t x) { return (x + 255) / 256 * 256; }
+
+struct Layout {
+    size_t info, big, small, panel, lists, ir, total;
+};
+
+Layout layout(int64_t n, int nb, int nrhs = 16);
+bool valid_shape(int64_t n, int nb);
+tc_status check_shape(int64_t n, int nb);
+tc_status check_ws(tc_ctx* ctx, int64_t n, int nb);
+// Create the out-of-core streams and a pinned staging buffer of at least
+// `bytes` bytes in the context (once).
+tc_status ctx_ooc_resources(tc_ctx* ctx, size_t bytes);
+// POTRF of the s x s block at offset o of a diagonal tile (leading dim nb),
+// recursive halving down to 128 x 128 leaves; failures set *info.
+tc_status potrf_rec(tc_ctx* ctx, double* T, int nb, int o, int s, int64_t col0, int* info,
+                    double* big);
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+}  // namespace host
+}  // namespace tc
+
+#define TC_HIP(expr)                                                                          \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return ::tc::host::fail(TC_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)

@@ -11,6 +11,7 @@
 // B is column-major (ldb), up to 16 right-hand sides per workgroup; more
 // right-hand sides use more workgroups.
 #include "common.hpp"
+#include "formats.hpp"
 
 namespace tc {
 namespace {
@@ -23,9 +24,9 @@ constexpr int kDBP = kDB + 1;
 // Solve with the diagonal tile L_kk (or L_kk^T) for 4 right-hand sides per
 // workgroup, in 64-row sub-blocks. Wave w solves right-hand side w of the
 // sub-block by substitution across its 64 lanes (one row per lane, the
-// solved value broadcast with a lane shuffle); then all 256 threads apply
+// solved value broadcast with v_readlane); then all 1024 threads apply
 // the sub-block to the remaining rows of the tile.
-__global__ __launch_bounds__(256) void trsv_diag_kernel(const double* __restrict__ Lkk, int nb,
+__global__ __launch_bounds__(1024) void trsv_diag_kernel(const double* __restrict__ Lkk, int nb,
                                                         double* __restrict__ B, int64_t ldb,
                                                         int nrhs, int transpose) {
     __shared__ double Ls[kDB * kDBP];  // Ls[l * kDBP + j] = L[jb + l][jb + j], l >= j
@@ -39,7 +40,7 @@ __global__ __launch_bounds__(256) void trsv_diag_kernel(const double* __restrict
     const int nblk = nb / kDB;
     for (int bi = 0; bi < nblk; ++bi) {
         const int jb = transpose ? (nblk - 1 - bi) * kDB : bi * kDB;
-        for (int e = tid; e < kDB * kDB; e += 256) {
+        for (int e = tid; e < kDB * kDB; e += 1024) {
             const int j = e / kDB, l = e % kDB;
             if (l >= j) {
                 const double v = Lkk[(int64_t)(jb + j) * nb + jb + l];
@@ -69,10 +70,10 @@ __global__ __launch_bounds__(256) void trsv_diag_kernel(const double* __restrict
             bcol[lane] = y;
         }
         __syncthreads();
-        // apply the solved sub-block to the rest of the tile's rows; loads
-        // are issued 16 at a time
+        // apply the solved sub-block to the rest of the tile's rows (one row
+        // per thread; loads issued 32 at a time)
         if (!transpose) {
-            for (int i = jb + kDB + tid; i < nb; i += 256) {
+            for (int i = jb + kDB + tid; i < nb; i += 1024) {
                 double s[kDR] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll 1
                 for (int l0 = 0; l0 < kDB; l0 += 16) {
@@ -89,7 +90,7 @@ __global__ __launch_bounds__(256) void trsv_diag_kernel(const double* __restrict
                     if (c < nr) B[(int64_t)(c0 + c) * ldb + i] -= s[c];
             }
         } else {
-            for (int i = tid; i < jb; i += 256) {
+            for (int i = tid; i < jb; i += 1024) {
                 const d2* li = reinterpret_cast<const d2*>(Lkk + (int64_t)i * nb + jb);  // L[jb + l][i]
                 double s[kDR] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll 1
@@ -114,47 +115,89 @@ __global__ __launch_bounds__(256) void trsv_diag_kernel(const double* __restrict
     }
 }
 
-// B_below[r][c] -= sum_j Lpanel[r][j] Y[j][c]. A workgroup owns 64 rows
-// (one per lane); its 4 waves split the nb columns j and combine their
-// partial sums in LDS in a fixed order. Y entries are uniform across a wave.
+// Tile (m, k) of a factor view: its first element, class and scale.
+__device__ __forceinline__ const char* view_tile(const TileView& L, int m, int k, int& cls,
+                                                 int& scale) {
+    const int64_t t = tile_off(L.Nt, m, k);
+    if (!L.toff) {
+        cls = kFP64;
+        scale = 0;
+        return L.base + t * (int64_t)L.nb * L.nb * sizeof(double);
+    }
+    cls = L.tcls[t];
+    scale = L.tscl[t];
+    return L.base + L.toff[t];
+}
+
+template <int C>
+__device__ __forceinline__ double ld_cls(const char* base, int64_t i) {
+    if (C == kFP64) return reinterpret_cast<const double*>(base)[i];
+    if (C == kFP32) return reinterpret_cast<const float*>(base)[i];
+    if (C == kFP16) return dec_fp16(reinterpret_cast<const uint16_t*>(base)[i]);
+    if (C == kBF16) return dec_bf16(reinterpret_cast<const uint16_t*>(base)[i]);
+    return dec_fp8(reinterpret_cast<const uint8_t*>(base)[i]);
+}
+
+// acc[c] += sum_{j in [jbeg, jend)} L[row][j] Y[j][c] for one row of a tile
+// stored in class C (unscaled values; the caller applies the tile's scale).
+template <int C>
+__device__ __forceinline__ void fwd_row(double (&acc)[kNR], const char* tile, int nb, int row,
+                                        int jbeg, int jend, const double* Yc, int64_t ldb, int nr) {
+    for (int j = jbeg; j < jend; j += 8) {
+        double lv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) lv[u] = ld_cls<C>(tile, (int64_t)(j + u) * nb + row);
+        if (nr == kNR) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+#pragma unroll
+                for (int c = 0; c < kNR; ++c) acc[c] += lv[u] * Yc[(int64_t)c * ldb + j + u];
+        } else {
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+#pragma unroll
+                for (int c = 0; c < kNR; ++c)
+                    if (c < nr) acc[c] += lv[u] * Yc[(int64_t)c * ldb + j + u];
+        }
+    }
+}
+
+// B_below[r][c] -= sum_j L[k+1+r/nb, k][r%nb][j] Y[j][c]. A workgroup owns 64
+// rows of one tile (one per lane); its 4 waves split the nb columns j and
+// combine their partial sums in LDS in a fixed order. Y entries are uniform
+// across a wave.
 constexpr int kFwdRows = 64;
-__global__ __launch_bounds__(256) void fwd_update_kernel(const double* __restrict__ Lcol, int nb,
-                                                         int64_t rows, const double* __restrict__ Y,
+__global__ __launch_bounds__(256) void fwd_update_kernel(TileView L, int k,
+                                                         const double* __restrict__ Y,
                                                          double* __restrict__ Bb, int64_t ldb,
                                                          int nrhs) {
     __shared__ double red[4 * kFwdRows * kNR];
+    const int nb = L.nb;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int c0 = blockIdx.y * kNR;
     const int nr = nrhs - c0 < kNR ? nrhs - c0 : kNR;
-    const int64_t r = (int64_t)blockIdx.x * kFwdRows + lane;
-    const int64_t nb2 = (int64_t)nb * nb;
-    const double* lrow = Lcol + (r / nb) * nb2 + (r % nb);
+    const int64_t r0 = (int64_t)blockIdx.x * kFwdRows;
+    int cls, scale;
+    const char* tile = view_tile(L, k + 1 + (int)(r0 / nb), k, cls, scale);
+    const int row = (int)(r0 % nb) + lane;
     const double* Yc = Y + (int64_t)c0 * ldb;
     double acc[kNR];
 #pragma unroll
     for (int c = 0; c < kNR; ++c) acc[c] = 0.0;
     const int jq = nb / 4;
     const int jbeg = wave * jq, jend = jbeg + jq;
-    if (nr == kNR) {
-        // 8 columns per iteration: their loads are issued together
-        for (int j = jbeg; j < jend; j += 8) {
-            double lv[8];
+    switch (cls) {
+        case kFP64: fwd_row<kFP64>(acc, tile, nb, row, jbeg, jend, Yc, ldb, nr); break;
+        case kFP32: fwd_row<kFP32>(acc, tile, nb, row, jbeg, jend, Yc, ldb, nr); break;
+        case kFP16: fwd_row<kFP16>(acc, tile, nb, row, jbeg, jend, Yc, ldb, nr); break;
+        case kBF16: fwd_row<kBF16>(acc, tile, nb, row, jbeg, jend, Yc, ldb, nr); break;
+        default: fwd_row<kFP8>(acc, tile, nb, row, jbeg, jend, Yc, ldb, nr); break;
+    }
+    if (scale) {
 #pragma unroll
-            for (int u = 0; u < 8; ++u) lv[u] = lrow[(int64_t)(j + u) * nb];
-#pragma unroll
-            for (int u = 0; u < 8; ++u)
-#pragma unroll
-                for (int c = 0; c < kNR; ++c) acc[c] += lv[u] * Yc[(int64_t)c * ldb + j + u];
-        }
-    } else {
-        for (int j = jbeg; j < jend; ++j) {
-            const double lv = lrow[(int64_t)j * nb];
-#pragma unroll
-            for (int c = 0; c < kNR; ++c)
-                if (c < nr) acc[c] += lv * Yc[(int64_t)c * ldb + j];
-        }
+        for (int c = 0; c < kNR; ++c) acc[c] = ldexp(acc[c], scale);
     }
 #pragma unroll
     for (int c = 0; c < kNR; ++c) red[(wave * kFwdRows + lane) * kNR + c] = acc[c];
@@ -164,36 +207,37 @@ __global__ __launch_bounds__(256) void fwd_update_kernel(const double* __restric
         if (c < nr) {
             const double s = (red[(0 * kFwdRows + rr) * kNR + c] + red[(1 * kFwdRows + rr) * kNR + c]) +
                              (red[(2 * kFwdRows + rr) * kNR + c] + red[(3 * kFwdRows + rr) * kNR + c]);
-            Bb[(int64_t)(c0 + c) * ldb + (int64_t)blockIdx.x * kFwdRows + rr] -= s;
+            Bb[(int64_t)(c0 + c) * ldb + r0 + rr] -= s;
         }
     }
 }
 
-// partial[split][j][c] = sum over the split's rows r of Lpanel[r][j] X[r][c]
-// for the 64 columns j of this workgroup's strip.
+// partial[split][j][c] = sum over the split's rows r of L[k+1+r/nb, k][r%nb][j]
+// X[r][c] for the 64 columns j of this workgroup's strip.
 constexpr int kBwdStrip = 64;
 constexpr int kBwdSub = 64;
-__global__ __launch_bounds__(256) void bwd_partial_kernel(const double* __restrict__ Lcol, int nb,
-                                                          int64_t rows_per_split,
+__global__ __launch_bounds__(256) void bwd_partial_kernel(TileView L, int k, int64_t rows_per_split,
                                                           const double* __restrict__ X,
                                                           int64_t ldb, int nrhs, int rhs0,
                                                           double* __restrict__ partial) {
     __shared__ double Ls[kBwdStrip * (kBwdSub + 1)];  // Ls[j * 65 + r]
     __shared__ double Xs[kBwdSub * kNR];
+    const int nb = L.nb;
     const int tid = threadIdx.x;
     const int j0 = blockIdx.x * kBwdStrip;
     const int split = blockIdx.y;
     const int nr = nrhs - rhs0 < kNR ? nrhs - rhs0 : kNR;
     const int jj = tid & 63, cg = tid >> 6;  // column of the strip, group of 4 RHS
-    const int64_t nb2 = (int64_t)nb * nb;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     const int64_t rbeg = (int64_t)split * rows_per_split;
     for (int64_t rb = rbeg; rb < rbeg + rows_per_split; rb += kBwdSub) {
         __syncthreads();
-        const double* lt = Lcol + (rb / nb) * nb2 + (rb % nb);
+        int cls, scale;
+        const char* tile = view_tile(L, k + 1 + (int)(rb / nb), k, cls, scale);
+        const int rr = (int)(rb % nb);
         for (int e = tid; e < kBwdStrip * kBwdSub; e += 256) {
             const int j = e / kBwdSub, r = e % kBwdSub;
-            Ls[j * (kBwdSub + 1) + r] = lt[(int64_t)(j0 + j) * nb + r];
+            Ls[j * (kBwdSub + 1) + r] = load_elem(tile, (int64_t)(j0 + j) * nb + rr + r, cls, scale);
         }
         for (int e = tid; e < kBwdSub * kNR; e += 256) {
             const int c = e / kBwdSub, r = e % kBwdSub;
@@ -222,11 +266,12 @@ __global__ void bwd_reduce_kernel(double* __restrict__ Y, int nb, int64_t ldb, i
     Y[(int64_t)(rhs0 + c) * ldb + j] -= s;
 }
 
-__global__ __launch_bounds__(256) void logdet_kernel(const double* __restrict__ L, int Nt, int nb,
-                                                     double* __restrict__ partial) {
+__global__ __launch_bounds__(256) void logdet_kernel(TileView L, double* __restrict__ partial) {
     __shared__ double red[4];
     const int k = blockIdx.x;
-    const double* t = L + tile_off(Nt, k, k) * (int64_t)nb * nb;
+    const int nb = L.nb;
+    int cls, scale;
+    const double* t = reinterpret_cast<const double*>(view_tile(L, k, k, cls, scale));
     double s = 0.0;
     for (int i = threadIdx.x; i < nb; i += 256) s += log(t[(int64_t)i * nb + i]);
     for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
@@ -235,21 +280,41 @@ __global__ __launch_bounds__(256) void logdet_kernel(const double* __restrict__ 
     if (threadIdx.x == 0) partial[k] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
+// Factor tiles as binary64 (packed lower order), strict upper triangle of
+// diagonal tiles zero.
+constexpr int kExpStrips = 16;
+__global__ __launch_bounds__(256) void export_kernel(TileView L, double* __restrict__ out) {
+    const int nb = L.nb, Nt = L.Nt;
+    const int64_t t = blockIdx.y;
+    int64_t j = 0;
+    while (tile_off(Nt, Nt - 1, j) < t) ++j;
+    const int64_t i = j + (t - tile_off(Nt, j, j));
+    int cls, scale;
+    const char* tile = view_tile(L, (int)i, (int)j, cls, scale);
+    const int64_t per = (int64_t)nb * nb / kExpStrips;
+    double* o = out + t * (int64_t)nb * nb;
+    for (int64_t e = blockIdx.x * per + threadIdx.x; e < (blockIdx.x + 1) * per; e += 256) {
+        const int64_t c = e / nb, r = e - c * nb;
+        o[e] = (i == j && r < c) ? 0.0 : load_elem(tile, e, cls, scale);
+    }
+}
+
 }  // namespace
 
 hipError_t launch_trsv_diag(hipStream_t s, const double* Lkk, int nb, double* B, int64_t ldb,
                             int nrhs, bool transpose) {
-    hipLaunchKernelGGL(trsv_diag_kernel, dim3((nrhs + kDR - 1) / kDR), dim3(256), 0, s, Lkk, nb, B,
+    hipLaunchKernelGGL(trsv_diag_kernel, dim3((nrhs + kDR - 1) / kDR), dim3(1024), 0, s, Lkk, nb, B,
                        ldb, nrhs, transpose ? 1 : 0);
     return hipGetLastError();
 }
 
-hipError_t launch_fwd_update(hipStream_t s, const double* Lcol, int nb, int64_t rows,
-                             const double* Yk, double* Bbelow, int64_t ldb, int nrhs) {
-    if (rows % kFwdRows != 0 || nb % 32 != 0) return hipErrorInvalidValue;
+hipError_t launch_fwd_update(hipStream_t s, const TileView& L, int k, const double* Yk,
+                             double* Bbelow, int64_t ldb, int nrhs) {
+    const int64_t rows = (int64_t)(L.Nt - k - 1) * L.nb;
+    if (rows <= 0) return hipSuccess;
+    if (rows % kFwdRows != 0 || L.nb % 32 != 0) return hipErrorInvalidValue;
     dim3 grid((unsigned)(rows / kFwdRows), (nrhs + kNR - 1) / kNR);
-    hipLaunchKernelGGL(fwd_update_kernel, grid, dim3(256), 0, s, Lcol, nb, rows, Yk, Bbelow, ldb,
-                       nrhs);
+    hipLaunchKernelGGL(fwd_update_kernel, grid, dim3(256), 0, s, L, k, Yk, Bbelow, ldb, nrhs);
     return hipGetLastError();
 }
 
@@ -262,26 +327,32 @@ int bwd_splits(int64_t rows) {
     return s < 1 ? 1 : (int)s;
 }
 
-hipError_t launch_bwd_update(hipStream_t s, const double* Lcol, int nb, int64_t rows,
-                             const double* Xbelow, double* Yk, int64_t ldb, int nrhs,
-                             double* partial, int splits) {
+hipError_t launch_bwd_update(hipStream_t s, const TileView& L, int k, const double* Xbelow,
+                             double* Yk, int64_t ldb, int nrhs, double* partial, int splits) {
+    const int64_t rows = (int64_t)(L.Nt - k - 1) * L.nb;
+    if (rows <= 0) return hipSuccess;
     for (int rhs0 = 0; rhs0 < nrhs; rhs0 += kNR) {
-        dim3 grid(nb / kBwdStrip, splits);
-        hipLaunchKernelGGL(bwd_partial_kernel, grid, dim3(256), 0, s, Lcol, nb, rows / splits,
-                           Xbelow, ldb, nrhs, rhs0, partial);
+        dim3 grid(L.nb / kBwdStrip, splits);
+        hipLaunchKernelGGL(bwd_partial_kernel, grid, dim3(256), 0, s, L, k, rows / splits, Xbelow,
+                           ldb, nrhs, rhs0, partial);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(bwd_reduce_kernel, dim3((nb * kNR + 255) / 256), dim3(256), 0, s, Yk, nb,
-                           ldb, nrhs, rhs0, splits, partial);
+        hipLaunchKernelGGL(bwd_reduce_kernel, dim3((L.nb * kNR + 255) / 256), dim3(256), 0, s, Yk,
+                           L.nb, ldb, nrhs, rhs0, splits, partial);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
 }
 
-hipError_t launch_logdet_partials(hipStream_t s, const double* L, int Nt, int nb,
-                                  double* partial) {
-    hipLaunchKernelGGL(logdet_kernel, dim3(Nt), dim3(256), 0, s, L, Nt, nb, partial);
+hipError_t launch_logdet_partials(hipStream_t s, const TileView& L, double* partial) {
+    hipLaunchKernelGGL(logdet_kernel, dim3(L.Nt), dim3(256), 0, s, L, partial);
+    return hipGetLastError();
+}
+
+hipError_t launch_export(hipStream_t s, const TileView& L, double* out) {
+    const int64_t ntiles = (int64_t)L.Nt * (L.Nt + 1) / 2;
+    hipLaunchKernelGGL(export_kernel, dim3(kExpStrips, (unsigned)ntiles), dim3(256), 0, s, L, out);
     return hipGetLastError();
 }
 

@@ -22,27 +22,12 @@
 #include <vector>
 
 #include "common.hpp"
+#include "formats.hpp"
+#include "host_common.hpp"
 #include "tilechol.h"
 
-struct tc_ctx {
-    int device = 0;
-    hipStream_t stream = nullptr;
-    char* ws = nullptr;
-    size_t ws_bytes = 0;
-    uint32_t flags = 0;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    std::vector<hipEvent_t> gemm_ev;
-};
-
-struct tc_factor {
-    int64_t n = 0;
-    int nb = 0;
-    int Nt = 0;
-    double* tiles = nullptr;
-    int info = 0;
-};
-
-namespace {
+namespace tc {
+namespace host {
 
 thread_local std::string g_err;
 
@@ -51,25 +36,16 @@ tc_status fail(tc_status s, const std::string& msg) {
     return s;
 }
 
-#define TC_HIP(expr)                                                                   \
-    do {                                                                               \
-        hipError_t e_ = (expr);                                                        \
-        if (e_ != hipSuccess)                                                          \
-            return fail(TC_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));   \
-    } while (0)
-
-constexpr size_t kAlign = 256;
-size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 // Workspace regions (all carved from the caller's buffer):
 //   info   : one int (failure flag)
 //   big    : split-K partial sums of the panel and in-tile updates, and the
 //            backward-solve partial sums (used one at a time, stream-ordered)
-//   small  : Matern strip sums of squares, log-determinant partials
-struct Layout {
-    size_t info, big, small, total;
-};
-
+//   small  : Matern strip sums of squares, log-determinant partials, amax
+//            partials of the mixed-precision finalize, column norms
+//   panel  : binary64 working column of the mixed-precision factorization
+//   lists  : row-tile lists per column and class (mixed precision)
+//   ir     : refinement vectors (b, r) and residual partial sums
 size_t big_bytes(int64_t n, int nb) {
     const int Nt = (int)(n / nb);
     size_t mx = 0;
@@ -77,11 +53,7 @@ size_t big_bytes(int64_t n, int nb) {
         const int s = tc::panel_splits(Nt, nb, k);
         if (s > 1) mx = std::max(mx, (size_t)s * (size_t)(Nt - k) * nb * nb * sizeof(double));
     }
-    for (int m = nb / 2; m >= 128; m /= 2) {
-        const int s = tc::syrk_sub_splits(m, m);
-        if (s > 1) mx = std::max(mx, (size_t)s * m * m * sizeof(double));
-    }
-    // in-tile recursion sizes that are not halves (nb not a power of two times 128)
+    // in-tile recursion (sizes are multiples of 128 below nb)
     for (int m = 128; m < nb; m += 128) {
         for (int kd = 128; kd < nb; kd += 128) {
             const int s = tc::syrk_sub_splits(m, kd);
@@ -92,18 +64,42 @@ size_t big_bytes(int64_t n, int nb) {
     return mx;
 }
 
-Layout layout(int64_t n, int nb) {
+Layout layout(int64_t n, int nb, int nrhs) {
     const int64_t Nt = n / nb;
     const int64_t ntiles = Nt * (Nt + 1) / 2;
+    if (nrhs < 16) nrhs = 16;
     Layout L;
     L.info = 0;
     L.big = align_up(sizeof(int) * 64);
-    const size_t big = align_up(big_bytes(n, nb));
-    L.small = L.big + big;
-    const size_t small = align_up(std::max<size_t>((size_t)ntiles * tc::matern_strips(nb),
-                                                   (size_t)Nt) * sizeof(double));
-    L.total = L.small + small;
+    L.small = L.big + align_up(big_bytes(n, nb));
+    size_t small = std::max<size_t>((size_t)ntiles * tc::matern_strips(nb), (size_t)Nt * 16);
+    small = std::max<size_t>(small, (size_t)2 * nrhs * tc::colnorm_blocks());
+    L.panel = L.small + align_up(small * sizeof(double));
+    // two working columns (the out-of-core path prefetches the next one)
+    L.lists = L.panel + align_up((size_t)2 * Nt * nb * nb * sizeof(double));
+    // row lists (mixed precision) or the out-of-core pointer-table ring
+    const size_t lists = std::max<size_t>((size_t)5 * Nt * Nt * sizeof(int),
+                                          (size_t)64 * ((size_t)Nt * Nt / 4 + Nt) * sizeof(void*));
+    L.ir = L.lists + align_up(lists);
+    const size_t ir = (size_t)2 * n * nrhs + tc::residual_partial_doubles((int)Nt, nb, nrhs);
+    L.total = L.ir + align_up(ir * sizeof(double));
     return L;
+}
+
+tc_status ctx_ooc_resources(tc_ctx* ctx, size_t bytes) {
+    if (!ctx->h2d) TC_HIP(hipStreamCreateWithFlags(&ctx->h2d, hipStreamNonBlocking));
+    if (!ctx->d2h) TC_HIP(hipStreamCreateWithFlags(&ctx->d2h, hipStreamNonBlocking));
+    if (ctx->pinned_bytes < bytes) {
+        if (ctx->pinned) {
+            TC_HIP(hipDeviceSynchronize());
+            TC_HIP(hipHostFree(ctx->pinned));
+            ctx->pinned = nullptr;
+            ctx->pinned_bytes = 0;
+        }
+        TC_HIP(hipHostMalloc(&ctx->pinned, bytes, hipHostMallocDefault));
+        ctx->pinned_bytes = bytes;
+    }
+    return TC_OK;
 }
 
 bool valid_shape(int64_t n, int nb) {
@@ -125,16 +121,82 @@ tc_status check_ws(tc_ctx* ctx, int64_t n, int nb) {
     return TC_OK;
 }
 
-struct DeviceGuard {
-    int prev = -1;
-    explicit DeviceGuard(int dev) {
-        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-        if (prev != dev) (void)hipSetDevice(dev);
-    }
-    ~DeviceGuard() {
-        if (prev >= 0) (void)hipSetDevice(prev);
-    }
+// Storage plan of a mixed-precision factor. Tiles are stored in their class
+// in packed order; then come the binary32 operand copies Q_c(Lh_t) for every
+// tile t and low class c that the static schedule multiplies it in (as the
+// A operand of tile (m, k), class c = class(m, k), n < k < m, or as the B
+// operand of the tiles (m', m), m' > m); then the device tables.
+struct Plan {
+    int Nt = 0, nb = 0;
+    int64_t ntiles = 0;
+    std::vector<uint8_t> cls;
+    std::vector<int64_t> toff, shoff;  // shoff[t * 4 + c - 1], -1 if absent
+    size_t tab_toff = 0, tab_shoff = 0, tab_tscl = 0, tab_tcls = 0, total = 0;
+    bool mixed = false;
 };
+
+bool make_plan(int64_t n, int nb, const uint8_t* map, Plan& P) {
+    P.Nt = (int)(n / nb);
+    P.nb = nb;
+    const int Nt = P.Nt;
+    P.ntiles = (int64_t)Nt * (Nt + 1) / 2;
+    P.cls.assign(P.ntiles, TC_FP64);
+    P.mixed = false;
+    if (map) {
+        for (int64_t t = 0; t < P.ntiles; ++t) {
+            if (map[t] > TC_FP8E4M3) return false;
+            P.cls[t] = map[t];
+            if (map[t] != TC_FP64) P.mixed = true;
+        }
+        for (int k = 0; k < Nt; ++k)
+            if (P.cls[tc::tile_off(Nt, k, k)] != TC_FP64) return false;
+    }
+    const size_t tb = (size_t)nb * nb;
+    P.toff.assign(P.ntiles, 0);
+    size_t off = 0;
+    for (int64_t t = 0; t < P.ntiles; ++t) {
+        P.toff[t] = (int64_t)off;
+        off += align_up(tb * tc::fmt_bytes(P.cls[t]));
+    }
+    if (!P.mixed) {
+        P.total = off;
+        return true;
+    }
+    auto C = [&](int i, int j) { return (int)P.cls[tc::tile_off(Nt, i, j)]; };
+    // classes present in each row m left of the diagonal and in each column m
+    // below it (as bit masks)
+    P.shoff.assign((size_t)P.ntiles * 4, -1);
+    for (int m = 1; m < Nt; ++m) {
+        uint32_t colmask = 0;
+        for (int mp = m + 1; mp < Nt; ++mp) colmask |= 1u << C(mp, m);
+        // suffix masks of row m: classes of (m, k) for k in (n, m)
+        std::vector<uint32_t> suf(m + 1, 0);
+        for (int k = m - 1; k >= 0; --k) suf[k] = suf[k + 1] | (1u << C(m, k));
+        for (int n2 = 0; n2 < m; ++n2) {
+            const uint32_t need = (suf[n2 + 1] | colmask) & ~1u;  // low classes only
+            const int64_t t = tc::tile_off(Nt, m, n2);
+            for (int c = 1; c <= 4; ++c) {
+                if (!(need & (1u << c))) continue;
+                if (c == TC_FP32 && P.cls[t] == TC_FP32) {
+                    P.shoff[t * 4 + c - 1] = P.toff[t];  // the stored tile is the copy
+                } else {
+                    P.shoff[t * 4 + c - 1] = (int64_t)off;
+                    off += align_up(tb * sizeof(float));
+                }
+            }
+        }
+    }
+    P.tab_toff = off;
+    off += align_up(P.ntiles * sizeof(int64_t));
+    P.tab_shoff = off;
+    off += align_up(P.ntiles * 4 * sizeof(int64_t));
+    P.tab_tscl = off;
+    off += align_up(P.ntiles * sizeof(int));
+    P.tab_tcls = off;
+    off += align_up(P.ntiles);
+    P.total = off;
+    return true;
+}
 
 // Recursive POTRF of the s x s block at offset o of a diagonal tile.
 tc_status potrf_rec(tc_ctx* ctx, double* T, int nb, int o, int s, int64_t col0, int* info,
@@ -155,6 +217,79 @@ tc_status potrf_rec(tc_ctx* ctx, double* T, int nb, int o, int s, int64_t col0, 
     return potrf_rec(ctx, T, nb, o + h, s - h, col0, info, big);
 }
 
+}  // namespace host
+}  // namespace tc
+
+using namespace tc::host;
+
+namespace {
+
+tc::TileView view_of(const tc_factor* F) {
+    tc::TileView v;
+    v.Nt = F->Nt;
+    v.nb = F->nb;
+    if (F->mixed) {
+        v.base = F->storage;
+        v.toff = F->d_toff;
+        v.tcls = F->d_tcls;
+        v.tscl = F->d_tscl;
+    } else {
+        v.base = reinterpret_cast<const char*>(F->tiles);
+        v.toff = nullptr;
+        v.tcls = nullptr;
+        v.tscl = nullptr;
+    }
+    return v;
+}
+
+const double* diag_tile(const tc_factor* F, int k) {
+    const int64_t t = tc::tile_off(F->Nt, k, k);
+    if (F->mixed) return reinterpret_cast<const double*>(F->storage + F->toff[t]);
+    return F->tiles + t * (int64_t)F->nb * F->nb;
+}
+
+// B <- (L L^T)^{-1} B, enqueued on the context stream (no synchronization).
+tc_status solve_enqueue(tc_ctx* ctx, const tc_factor* F, double* B, int64_t ldb, int nrhs,
+                        double* big) {
+    const int Nt = F->Nt, nb = F->nb;
+    const tc::TileView V = view_of(F);
+    for (int k = 0; k < Nt; ++k) {
+        TC_HIP(tc::launch_trsv_diag(ctx->stream, diag_tile(F, k), nb, B + (int64_t)k * nb, ldb, nrhs,
+                                    false));
+        if (k + 1 < Nt)
+            TC_HIP(tc::launch_fwd_update(ctx->stream, V, k, B + (int64_t)k * nb,
+                                         B + (int64_t)(k + 1) * nb, ldb, nrhs));
+    }
+    for (int k = Nt - 1; k >= 0; --k) {
+        if (k + 1 < Nt) {
+            const int64_t rows = (int64_t)(Nt - k - 1) * nb;
+            TC_HIP(tc::launch_bwd_update(ctx->stream, V, k, B + (int64_t)(k + 1) * nb,
+                                         B + (int64_t)k * nb, ldb, nrhs, big, tc::bwd_splits(rows)));
+        }
+        TC_HIP(tc::launch_trsv_diag(ctx->stream, diag_tile(F, k), nb, B + (int64_t)k * nb, ldb, nrhs,
+                                    true));
+    }
+    return TC_OK;
+}
+
+// Column norms of X (n x nrhs): ||x_j||_2 into out[j] (synchronizes).
+tc_status colnorms(tc_ctx* ctx, const double* X, int64_t ld, int64_t n, int nrhs, double* part,
+                   std::vector<double>& out) {
+    TC_HIP(tc::launch_colnorm(ctx->stream, X, ld, n, nrhs, part));
+    const int nbk = tc::colnorm_blocks();
+    std::vector<double> h((size_t)nrhs * nbk);
+    TC_HIP(hipMemcpyAsync(h.data(), part, h.size() * sizeof(double), hipMemcpyDeviceToHost,
+                          ctx->stream));
+    TC_HIP(hipStreamSynchronize(ctx->stream));
+    out.assign(nrhs, 0.0);
+    for (int c = 0; c < nrhs; ++c) {
+        double s = 0.0;
+        for (int b = 0; b < nbk; ++b) s += h[(size_t)c * nbk + b];
+        out[c] = std::sqrt(s);
+    }
+    return TC_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -164,14 +299,13 @@ int64_t tc_tile_offset(int32_t Nt, int32_t i, int32_t j) {
     return tc::tile_off(Nt, i, j);
 }
 
-const char* tc_version(void) { return "tilechol 0.1 (gfx950, FP64 MFMA)"; }
+const char* tc_version(void) { return "tilechol 0.2 (gfx950, FP64/FP32 MFMA, mixed precision)"; }
 
 const char* tc_last_error(void) { return g_err.c_str(); }
 
 size_t tc_workspace_bytes(int64_t n, int32_t nb, int32_t nrhs) {
-    (void)nrhs;
-    if (!valid_shape(n, nb)) return 0;
-    return layout(n, nb).total;
+    if (!valid_shape(n, nb) || nrhs < 0) return 0;
+    return layout(n, nb, nrhs).total;
 }
 
 tc_status tc_ctx_create(tc_ctx** out, int device, void* workspace, size_t workspace_bytes,
@@ -205,6 +339,15 @@ tc_status tc_ctx_destroy(tc_ctx* ctx) {
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
     for (hipEvent_t e : ctx->gemm_ev) (void)hipEventDestroy(e);
+    if (ctx->h2d) {
+        (void)hipStreamSynchronize(ctx->h2d);
+        (void)hipStreamDestroy(ctx->h2d);
+    }
+    if (ctx->d2h) {
+        (void)hipStreamSynchronize(ctx->d2h);
+        (void)hipStreamDestroy(ctx->d2h);
+    }
+    if (ctx->pinned) (void)hipHostFree(ctx->pinned);
     delete ctx;
     return TC_OK;
 }
@@ -250,57 +393,64 @@ tc_status tc_matern_tiles(tc_ctx* ctx, int64_t n, int32_t nb, const double* locs
     return TC_OK;
 }
 
-size_t tc_factor_bytes(int64_t n, int32_t nb, const uint8_t* map) {
-    if (!valid_shape(n, nb)) return 0;
-    const int64_t Nt = n / nb;
-    const int64_t ntiles = Nt * (Nt + 1) / 2;
-    static const size_t bytes_of[5] = {8, 4, 2, 2, 1};
-    if (!map) return (size_t)ntiles * nb * nb * sizeof(double);
-    size_t tot = 0;
-    for (int64_t t = 0; t < ntiles; ++t) {
-        if (map[t] > 4) return 0;
-        tot += bytes_of[map[t]] * (size_t)nb * nb;
-    }
-    return tot;
+tc_status tc_precision_map(int32_t Nt, const double* tile_fro, double fro_A, double eps,
+                           uint32_t allowed_mask, int32_t unit_roundoff, uint8_t* map_out) {
+    if (Nt <= 0 || !tile_fro || !map_out) return fail(TC_EINVAL, "NULL argument or Nt <= 0");
+    if (!(fro_A > 0) || !(eps > 0)) return fail(TC_EINVAL, "fro_A and eps must be positive");
+    if (allowed_mask & ~0x1Fu) return fail(TC_EINVAL, "allowed_mask has unknown classes");
+    // candidate low classes, largest epsilon (lowest precision) first
+    int order[4], nc = 0;
+    const int by_eps[4] = {TC_FP8E4M3, TC_BF16, TC_FP16, TC_FP32};
+    for (int c : by_eps)
+        if (allowed_mask & (1u << c)) order[nc++] = c;
+    for (int32_t j = 0; j < Nt; ++j)
+        for (int32_t i = j; i < Nt; ++i) {
+            const int64_t t = tc::tile_off(Nt, i, j);
+            uint8_t cls = TC_FP64;
+            if (i != j) {
+                const double lhs = (double)Nt * tile_fro[t] / fro_A;
+                for (int q = 0; q < nc; ++q) {
+                    const int p = tc::fmt_spec(order[q]).p;
+                    const double eps_p = std::ldexp(1.0, unit_roundoff ? -p : 1 - p);
+                    if (lhs < eps / eps_p) {
+                        cls = (uint8_t)order[q];
+                        break;
+                    }
+                }
+            }
+            map_out[t] = cls;
+        }
+    return TC_OK;
 }
 
-tc_status tc_factorize(tc_ctx* ctx, int64_t n, int32_t nb, const double* A, const uint8_t* map,
-                       const tc_opts* opts, void* storage, size_t storage_bytes, tc_factor** Lout,
-                       tc_stats* stats) {
-    (void)opts;
-    if (!ctx || !A || !storage || !Lout) return fail(TC_EINVAL, "NULL argument");
-    *Lout = nullptr;
-    if (tc_status s = check_shape(n, nb)) return s;
+size_t tc_factor_bytes(int64_t n, int32_t nb, const uint8_t* map) {
+    if (!valid_shape(n, nb)) return 0;
+    Plan P;
+    if (!make_plan(n, nb, map, P)) return 0;
+    if (!P.mixed) return (size_t)P.ntiles * nb * nb * sizeof(double);
+    return P.total;
+}
+
+namespace {
+
+// All-FP64 factorization (storage: packed binary64 tiles, may equal A).
+tc_status factorize_fp64(tc_ctx* ctx, int64_t n, int nb, const double* A, double* L,
+                         tc_factor** Lout, tc_stats* stats) {
     const int Nt = (int)(n / nb);
     const int64_t ntiles = (int64_t)Nt * (Nt + 1) / 2;
-    if (map) {
-        for (int64_t t = 0; t < ntiles; ++t) {
-            if (map[t] > 4) return fail(TC_EINVAL, "bad precision code in map");
-            if (map[t] != TC_FP64)
-                return fail(TC_EUNSUPPORTED, "mixed-precision maps are not implemented in this build");
-        }
-    }
     const size_t need = (size_t)ntiles * nb * nb * sizeof(double);
-    if (storage_bytes < need)
-        return fail(TC_EINVAL, "storage too small: need " + std::to_string(need) + " bytes");
-    if (tc_status s = check_ws(ctx, n, nb)) return s;
-    DeviceGuard g(ctx->device);
     const Layout Ly = layout(n, nb);
     int* d_info = reinterpret_cast<int*>(ctx->ws + Ly.info);
     double* big = reinterpret_cast<double*>(ctx->ws + Ly.big);
-    double* L = static_cast<double*>(storage);
     const int64_t nb2 = (int64_t)nb * nb;
     const bool timed = (ctx->flags & 1u) != 0;
-    if (timed && ctx->gemm_ev.size() < (size_t)2 * Nt) {
-        while (ctx->gemm_ev.size() < (size_t)2 * Nt) {
-            hipEvent_t e;
-            TC_HIP(hipEventCreate(&e));
-            ctx->gemm_ev.push_back(e);
-        }
+    while (timed && ctx->gemm_ev.size() < (size_t)2 * Nt) {
+        hipEvent_t e;
+        TC_HIP(hipEventCreate(&e));
+        ctx->gemm_ev.push_back(e);
     }
-
     TC_HIP(hipEventRecord(ctx->ev0, ctx->stream));
-    if (storage != (const void*)A)
+    if ((const void*)L != (const void*)A)
         TC_HIP(hipMemcpyAsync(L, A, need, hipMemcpyDeviceToDevice, ctx->stream));
     TC_HIP(tc::launch_zero_info(ctx->stream, d_info));
     double gemm_flops = 0.0;
@@ -354,12 +504,138 @@ tc_status tc_factorize(tc_ctx* ctx, int64_t n, int32_t nb, const double* A, cons
         stats->info = info;
         const double nd = (double)n;
         stats->flops_total = nd * nd * nd / 3.0;
+        stats->class_flops[TC_FP64] = gemm_flops;
+        stats->class_tiles[TC_FP64] = (int32_t)ntiles;
     }
-    if (info > 0) {
-        g_err = "matrix is not positive definite (column " + std::to_string(info) + ")";
-        return info;
+    return info > 0 ? info : TC_OK;
+}
+
+// Mixed-precision factorization. Column k: copy A's column of tiles into the
+// binary64 working column W, subtract the updates class group by class
+// group, POTRF the diagonal tile and TRSM the rest in FP64, then store the
+// diagonal tile in FP64 and round the others into their classes.
+tc_status factorize_mixed(tc_ctx* ctx, int64_t n, int nb, const double* A, const Plan& P,
+                          char* storage, tc_factor** Lout, tc_stats* stats) {
+    const int Nt = P.Nt;
+    const Layout Ly = layout(n, nb);
+    int* d_info = reinterpret_cast<int*>(ctx->ws + Ly.info);
+    double* big = reinterpret_cast<double*>(ctx->ws + Ly.big);
+    double* part = reinterpret_cast<double*>(ctx->ws + Ly.small);
+    double* W = reinterpret_cast<double*>(ctx->ws + Ly.panel);
+    int* d_lists = reinterpret_cast<int*>(ctx->ws + Ly.lists);
+    const int64_t nb2 = (int64_t)nb * nb;
+    int64_t* d_toff = reinterpret_cast<int64_t*>(storage + P.tab_toff);
+    int64_t* d_shoff = reinterpret_cast<int64_t*>(storage + P.tab_shoff);
+    int* d_tscl = reinterpret_cast<int*>(storage + P.tab_tscl);
+    uint8_t* d_tcls = reinterpret_cast<uint8_t*>(storage + P.tab_tcls);
+
+    // row lists: for column k and class c, rows r >= 1 (tile k + r) of that class
+    std::vector<int> lists((size_t)5 * Nt * Nt, 0);
+    std::vector<int> lcount((size_t)5 * Nt, 0);
+    double cflops[5] = {0, 0, 0, 0, 0};
+    int ctiles[5] = {0, 0, 0, 0, 0};
+    for (int64_t t = 0; t < P.ntiles; ++t) ctiles[P.cls[t]]++;
+    for (int k = 0; k < Nt; ++k) {
+        const double K = (double)k * nb;
+        cflops[TC_FP64] += (double)nb2 * K;  // diagonal SYRK (lower half)
+        for (int r = 1; r < Nt - k; ++r) {
+            const int c = P.cls[tc::tile_off(Nt, k + r, k)];
+            lists[((size_t)k * 5 + c) * Nt + lcount[(size_t)k * 5 + c]++] = r;
+            cflops[c] += 2.0 * nb2 * K;
+        }
     }
-    return TC_OK;
+    std::vector<int> zeros(P.ntiles, 0);
+    TC_HIP(hipEventRecord(ctx->ev0, ctx->stream));
+    TC_HIP(hipMemcpyAsync(d_lists, lists.data(), lists.size() * sizeof(int), hipMemcpyHostToDevice,
+                          ctx->stream));
+    TC_HIP(hipMemcpyAsync(d_toff, P.toff.data(), P.toff.size() * sizeof(int64_t),
+                          hipMemcpyHostToDevice, ctx->stream));
+    TC_HIP(hipMemcpyAsync(d_shoff, P.shoff.data(), P.shoff.size() * sizeof(int64_t),
+                          hipMemcpyHostToDevice, ctx->stream));
+    TC_HIP(hipMemcpyAsync(d_tcls, P.cls.data(), P.cls.size(), hipMemcpyHostToDevice, ctx->stream));
+    TC_HIP(hipMemcpyAsync(d_tscl, zeros.data(), zeros.size() * sizeof(int), hipMemcpyHostToDevice,
+                          ctx->stream));
+    TC_HIP(tc::launch_zero_info(ctx->stream, d_info));
+    for (int k = 0; k < Nt; ++k) {
+        TC_HIP(hipMemcpyAsync(W, A + tc::tile_off(Nt, k, k) * nb2, (size_t)(Nt - k) * nb2 * sizeof(double),
+                              hipMemcpyDeviceToDevice, ctx->stream));
+        if (k > 0) {
+            const int* l64 = d_lists + ((size_t)k * 5 + TC_FP64) * Nt;
+            TC_HIP(tc::launch_mxp_gemm_f64(ctx->stream, W, Nt, nb, k, l64, lcount[(size_t)k * 5 + TC_FP64],
+                                           true, storage, d_toff, d_tcls, d_tscl));
+            for (int c = 1; c <= 4; ++c) {
+                const int cnt = lcount[(size_t)k * 5 + c];
+                if (!cnt) continue;
+                TC_HIP(tc::launch_mxp_gemm_f32(ctx->stream, W, Nt, nb, k,
+                                               d_lists + ((size_t)k * 5 + c) * Nt, cnt, c, storage,
+                                               d_shoff));
+            }
+        }
+        if (tc_status s = potrf_rec(ctx, W, nb, 0, nb, (int64_t)k * nb, d_info, big)) return s;
+        if (k + 1 < Nt) TC_HIP(tc::launch_trsm(ctx->stream, W + nb2, W, nb, (int64_t)(Nt - k - 1) * nb, nb));
+        TC_HIP(hipMemcpyAsync(storage + P.toff[tc::tile_off(Nt, k, k)], W, nb2 * sizeof(double),
+                              hipMemcpyDeviceToDevice, ctx->stream));
+        TC_HIP(tc::launch_mxp_finalize(ctx->stream, W, Nt, nb, k, part, storage, d_toff, d_tcls, d_tscl,
+                                       d_shoff));
+    }
+    TC_HIP(hipEventRecord(ctx->ev1, ctx->stream));
+    int info = 0;
+    TC_HIP(hipMemcpyAsync(&info, d_info, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    TC_HIP(hipStreamSynchronize(ctx->stream));
+
+    tc_factor* f = new (std::nothrow) tc_factor();
+    if (!f) return fail(TC_ENOMEM, "out of host memory");
+    f->n = n;
+    f->nb = nb;
+    f->Nt = Nt;
+    f->info = info;
+    f->mixed = true;
+    f->storage = storage;
+    f->d_toff = d_toff;
+    f->d_tcls = d_tcls;
+    f->d_tscl = d_tscl;
+    f->toff = P.toff;
+    *Lout = f;
+    if (stats) {
+        std::memset(stats, 0, sizeof(*stats));
+        float ms = 0.f;
+        TC_HIP(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+        stats->ms_total = ms;
+        stats->info = info;
+        const double nd = (double)n;
+        stats->flops_total = nd * nd * nd / 3.0;
+        for (int c = 0; c < 5; ++c) {
+            stats->class_flops[c] = cflops[c];
+            stats->class_tiles[c] = ctiles[c];
+            stats->gemm_flops += cflops[c];
+        }
+    }
+    return info > 0 ? info : TC_OK;
+}
+
+}  // namespace
+
+tc_status tc_factorize(tc_ctx* ctx, int64_t n, int32_t nb, const double* A, const uint8_t* map,
+                       const tc_opts* opts, void* storage, size_t storage_bytes, tc_factor** Lout,
+                       tc_stats* stats) {
+    (void)opts;
+    if (!ctx || !A || !storage || !Lout) return fail(TC_EINVAL, "NULL argument");
+    *Lout = nullptr;
+    if (tc_status s = check_shape(n, nb)) return s;
+    Plan P;
+    if (!make_plan(n, nb, map, P))
+        return fail(TC_EINVAL, "bad precision map (codes 0..4, diagonal tiles TC_FP64)");
+    const size_t need = P.mixed ? P.total : (size_t)P.ntiles * nb * nb * sizeof(double);
+    if (storage_bytes < need)
+        return fail(TC_EINVAL, "storage too small: need " + std::to_string(need) + " bytes");
+    if (P.mixed && storage == (const void*)A)
+        return fail(TC_EINVAL, "a mixed-precision factor cannot overwrite its input");
+    if (tc_status s = check_ws(ctx, n, nb)) return s;
+    DeviceGuard g(ctx->device);
+    tc_status st = P.mixed ? factorize_mixed(ctx, n, nb, A, P, static_cast<char*>(storage), Lout, stats)
+                           : factorize_fp64(ctx, n, nb, A, static_cast<double*>(storage), Lout, stats);
+    if (st > 0) g_err = "matrix is not positive definite (column " + std::to_string(st) + ")";
+    return st;
 }
 
 tc_status tc_solve(tc_ctx* ctx, const tc_factor* F, double* B, int64_t ldb, int32_t nrhs) {
@@ -371,28 +647,63 @@ tc_status tc_solve(tc_ctx* ctx, const tc_factor* F, double* B, int64_t ldb, int3
     DeviceGuard g(ctx->device);
     const Layout Ly = layout(F->n, F->nb);
     double* big = reinterpret_cast<double*>(ctx->ws + Ly.big);
-    const int Nt = F->Nt, nb = F->nb;
-    const int64_t nb2 = (int64_t)nb * nb;
-    const double* L = F->tiles;
-    for (int k = 0; k < Nt; ++k) {
-        const double* Lkk = L + tc::tile_off(Nt, k, k) * nb2;
-        TC_HIP(tc::launch_trsv_diag(ctx->stream, Lkk, nb, B + (int64_t)k * nb, ldb, nrhs, false));
-        if (k + 1 < Nt)
-            TC_HIP(tc::launch_fwd_update(ctx->stream, L + tc::tile_off(Nt, k + 1, k) * nb2, nb,
-                                         (int64_t)(Nt - k - 1) * nb, B + (int64_t)k * nb,
-                                         B + (int64_t)(k + 1) * nb, ldb, nrhs));
-    }
-    for (int k = Nt - 1; k >= 0; --k) {
-        if (k + 1 < Nt) {
-            const int64_t rows = (int64_t)(Nt - k - 1) * nb;
-            TC_HIP(tc::launch_bwd_update(ctx->stream, L + tc::tile_off(Nt, k + 1, k) * nb2, nb, rows,
-                                         B + (int64_t)(k + 1) * nb, B + (int64_t)k * nb, ldb, nrhs,
-                                         big, tc::bwd_splits(rows)));
-        }
-        const double* Lkk = L + tc::tile_off(Nt, k, k) * nb2;
-        TC_HIP(tc::launch_trsv_diag(ctx->stream, Lkk, nb, B + (int64_t)k * nb, ldb, nrhs, true));
-    }
+    if (tc_status s = solve_enqueue(ctx, F, B, ldb, nrhs, big)) return s;
     TC_HIP(hipStreamSynchronize(ctx->stream));
+    return TC_OK;
+}
+
+tc_status tc_solve_refine(tc_ctx* ctx, const tc_factor* F, const double* A, double* B, int64_t ldb,
+                          int32_t nrhs, int32_t max_iter, double tol, tc_ir_stats* stats) {
+    if (!ctx || !F || !A || !B) return fail(TC_EINVAL, "NULL argument");
+    if (nrhs <= 0 || ldb < F->n || max_iter < 0 || !(tol > 0))
+        return fail(TC_EINVAL, "bad nrhs, ldb, max_iter or tol");
+    if (F->info > 0) return fail(TC_EINVAL, "factor is not valid (factorization failed)");
+    const Layout Ly = layout(F->n, F->nb, nrhs);
+    if (ctx->ws == nullptr || ctx->ws_bytes < Ly.total)
+        return fail(TC_ENOMEM, "workspace too small for " + std::to_string(nrhs) +
+                                   " right-hand sides: need " + std::to_string(Ly.total) + " bytes");
+    DeviceGuard g(ctx->device);
+    const int64_t n = F->n;
+    double* big = reinterpret_cast<double*>(ctx->ws + Ly.big);
+    double* part = reinterpret_cast<double*>(ctx->ws + Ly.small);
+    double* Bc = reinterpret_cast<double*>(ctx->ws + Ly.ir);  // b
+    double* R = Bc + (size_t)n * nrhs;                          // residual / correction
+    double* rp = R + (size_t)n * nrhs;                          // residual partial sums
+    TC_HIP(hipEventRecord(ctx->ev0, ctx->stream));
+    TC_HIP(tc::launch_copy_cols(ctx->stream, Bc, n, B, ldb, n, nrhs));
+    std::vector<double> bn, rn;
+    if (tc_status s = colnorms(ctx, Bc, n, n, nrhs, part, bn)) return s;
+    if (tc_status s = solve_enqueue(ctx, F, B, ldb, nrhs, big)) return s;
+    tc_ir_stats st;
+    std::memset(&st, 0, sizeof(st));
+    double rel = 0.0;
+    int it = 0;
+    for (;;) {
+        TC_HIP(tc::launch_residual(ctx->stream, A, F->Nt, F->nb, B, ldb, Bc, n, nrhs, rp, R, n));
+        if (tc_status s = colnorms(ctx, R, n, n, nrhs, part, rn)) return s;
+        rel = 0.0;
+        for (int c = 0; c < nrhs; ++c) {
+            const double r = bn[c] > 0 ? rn[c] / bn[c] : rn[c];
+            if (!(r <= rel)) rel = r;  // NaN propagates
+        }
+        if (it < 32) st.history[it] = rel;
+        if (rel <= tol || it >= max_iter) break;
+        if (tc_status s = solve_enqueue(ctx, F, R, n, nrhs, big)) return s;
+        TC_HIP(tc::launch_axpy(ctx->stream, B, ldb, R, n, n, nrhs));
+        ++it;
+    }
+    TC_HIP(hipEventRecord(ctx->ev1, ctx->stream));
+    TC_HIP(hipStreamSynchronize(ctx->stream));
+    float ms = 0.f;
+    TC_HIP(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+    st.iterations = it;
+    st.converged = rel <= tol ? 1 : 0;
+    st.rel_residual = rel;
+    st.ms_total = ms;
+    if (stats) *stats = st;
+    if (!st.converged)
+        return fail(TC_ENOTCONV, "refinement stopped at relative residual " + std::to_string(rel) +
+                                     " after " + std::to_string(it) + " corrections");
     return TC_OK;
 }
 
@@ -403,7 +714,7 @@ tc_status tc_logdet(tc_ctx* ctx, const tc_factor* F, double* out) {
     DeviceGuard g(ctx->device);
     const Layout Ly = layout(F->n, F->nb);
     double* part = reinterpret_cast<double*>(ctx->ws + Ly.small);
-    TC_HIP(tc::launch_logdet_partials(ctx->stream, F->tiles, F->Nt, F->nb, part));
+    TC_HIP(tc::launch_logdet_partials(ctx->stream, view_of(F), part));
     std::vector<double> h(F->Nt);
     TC_HIP(hipMemcpyAsync(h.data(), part, F->Nt * sizeof(double), hipMemcpyDeviceToHost,
                           ctx->stream));
@@ -417,11 +728,17 @@ tc_status tc_logdet(tc_ctx* ctx, const tc_factor* F, double* out) {
 tc_status tc_factor_export(tc_ctx* ctx, const tc_factor* F, double* L64) {
     if (!ctx || !F || !L64) return fail(TC_EINVAL, "NULL argument");
     DeviceGuard g(ctx->device);
-    const int64_t ntiles = (int64_t)F->Nt * (F->Nt + 1) / 2;
-    if (L64 != F->tiles)
-        TC_HIP(hipMemcpyAsync(L64, F->tiles, (size_t)ntiles * F->nb * F->nb * sizeof(double),
-                              hipMemcpyDeviceToDevice, ctx->stream));
-    TC_HIP(tc::launch_zero_upper(ctx->stream, L64, F->Nt, F->nb));
+    if (F->mixed) {
+        if ((const void*)L64 == (const void*)F->storage)
+            return fail(TC_EINVAL, "export of a mixed-precision factor needs a separate buffer");
+        TC_HIP(tc::launch_export(ctx->stream, view_of(F), L64));
+    } else {
+        const int64_t ntiles = (int64_t)F->Nt * (F->Nt + 1) / 2;
+        if (L64 != F->tiles)
+            TC_HIP(hipMemcpyAsync(L64, F->tiles, (size_t)ntiles * F->nb * F->nb * sizeof(double),
+                                  hipMemcpyDeviceToDevice, ctx->stream));
+        TC_HIP(tc::launch_zero_upper(ctx->stream, L64, F->Nt, F->nb));
+    }
     TC_HIP(hipStreamSynchronize(ctx->stream));
     return TC_OK;
 }

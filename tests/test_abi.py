@@ -54,7 +54,8 @@ def test_sizes_and_validation():
     cm = np.array([tc.FP64] * 36, dtype=np.uint8)
     cm[1] = tc.FP32
     cm[2] = tc.FP8E4M3
-    assert tc.factor_bytes(2048, 256, cm) == (34 * 8 + 4 + 1) * 256 * 256
+    # tiles in their classes, plus operand copies and tables
+    assert tc.factor_bytes(2048, 256, cm) >= (34 * 8 + 4 + 1) * 256 * 256
     assert tc.workspace_bytes(2048, 256) > 0
     for n, nb in [(2048, 100), (2000, 256), (0, 256), (4096, 4096)]:
         assert tc.workspace_bytes(n, nb) == 0
@@ -80,3 +81,33 @@ def test_pack_unpack_roundtrip():
     t = tc.tile_offset(n // nb, 3, 1)
     assert np.array_equal(P[t * nb * nb:(t + 1) * nb * nb].reshape(nb, nb, order="F"),
                           A[3 * nb:4 * nb, nb:2 * nb])
+
+
+@pytest.mark.parametrize("eps", [1e-3, 1e-5, 1e-7, 1e-9])
+@pytest.mark.parametrize("unit", [False, True])
+def test_library_precision_map_equals_oracle(eps, unit):
+    """tc_precision_map (host code in the library) takes the same decisions
+    as the oracle's criterion on the same norms."""
+    import oracle
+    import seeded_inputs as si
+    tc = _lib()
+    n, nb = 2048, 128
+    A = oracle.matern_matrix(si.points(n, seed=3), 1.0, 0.03, 0.5, 1e-4)
+    Nt = n // nb
+    norms = oracle.tile_norms(A, nb)
+    fro = oracle.fro_norm(norms, Nt)
+    for allowed in [(0, 1, 2, 4), (0, 1), (0, 3, 4), (0, 1, 2, 3, 4)]:
+        got = tc.precision_map(Nt, norms, fro, eps, allowed=allowed, unit_roundoff=unit)
+        want = oracle.precision_map(norms, fro, Nt, eps, allowed=allowed, unit_roundoff=unit)
+        assert np.array_equal(got, want)
+
+
+def test_mixed_factor_bytes_cover_tiles():
+    tc = _lib()
+    Nt, nb = 6, 128
+    cm = np.zeros(Nt * (Nt + 1) // 2, dtype=np.uint8)
+    cm[[1, 2, 3]] = [tc.FP32, tc.FP16, tc.FP8E4M3]
+    assert tc.factor_bytes(Nt * nb, nb, cm) > (18 * 8 + 4 + 2 + 1) * nb * nb
+    bad = cm.copy()
+    bad[0] = tc.FP32  # diagonal tile must stay FP64
+    assert tc.factor_bytes(Nt * nb, nb, bad) == 0

@@ -1,0 +1,130 @@
+"""GPU parity of the mixed-precision factorization (Section IV-C) and the
+FP64 refinement solve against the CPU oracle.
+
+The GPU and the oracle run the same algorithm (operands rounded to the
+output tile's class, FP32 accumulation, FP64 POTRF/TRSM, results rounded to
+the tile's class) but accumulate in different orders, so they are compared
+through properties and bounds:
+  * every stored tile is exactly representable in its class;
+  * the backward error ||A - Lh Lh^T||_F / ||A||_F is at most the target
+    accuracy eps and within 10x of the oracle's (the per-map bound);
+  * both factors are exact factors of A + E with ||E|| <= be ||A||, so they
+    differ by at most ~4 kappa(A) (be_gpu + be_oracle) relative;
+  * refinement reaches max_j ||b_j - A x_j|| / ||b_j|| <= 1e-9, checked on the
+    CPU in binary64 from A.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import seeded_inputs as si
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def tc():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2410_09819_amd as tc
+    tc.lib()
+    return tc
+
+
+def to_dev(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).to(torch.device("cuda", 0))
+
+
+@pytest.fixture(scope="module")
+def case():
+    n, nb = 2048, 128
+    pts = si.points(n, seed=3)
+    A = oracle.matern_matrix(pts, 1.0, 0.03, 0.5, 1e-4)
+    Nt = n // nb
+    norms = oracle.tile_norms(A, nb)
+    return dict(n=n, nb=nb, Nt=Nt, pts=pts, A=A, norms=norms, fro=oracle.fro_norm(norms, Nt),
+                kappa=np.linalg.cond(A))
+
+
+@pytest.mark.parametrize("eps", [1e-4, 1e-6, 1e-9])
+def test_mixed_factor_matches_oracle(tc, case, eps):
+    n, nb, Nt, A = case["n"], case["nb"], case["Nt"], case["A"]
+    cm = tc.precision_map(Nt, case["norms"], case["fro"], eps)
+    assert len(set(cm.tolist())) >= 3
+    ctx = tc.Context(n, nb)
+    Ad = to_dev(tc.pack_lower(A, nb))
+    F = tc.factorize(ctx, Ad, n, nb, cmap=cm)
+    assert F.stats.info == 0
+    assert list(F.stats.class_tiles) == np.bincount(cm, minlength=5).tolist()
+    Lg = tc.unpack_lower(tc.export(ctx, F).cpu().numpy(), n, nb)
+    for j in range(Nt):
+        for i in range(j + 1, Nt):
+            t = Lg[i * nb:(i + 1) * nb, j * nb:(j + 1) * nb]
+            c = int(cm[oracle.tile_index(Nt, i, j)])
+            assert np.array_equal(oracle.round_tile(t, c)[0], t), (i, j, c)
+    Lo, info = oracle.mxp_tile_cholesky(A, nb, cm)
+    assert info == 0
+    be_g, be_o = oracle.backward_error(A, Lg), oracle.backward_error(A, Lo)
+    assert be_g <= eps and be_g <= 10 * be_o, (be_g, be_o)
+    diff = np.linalg.norm(Lg - Lo) / np.linalg.norm(Lo)
+    assert diff <= 4 * case["kappa"] * (be_g + be_o) + 1e-13, diff
+    ld = tc.logdet(ctx, F)
+    assert abs(ld - oracle.logdet(Lo)) <= 4 * case["kappa"] * (be_g + be_o) * n + 1e-9 * abs(ld)
+
+
+def test_all_fp64_map_equals_fp64_path(tc, case):
+    n, nb, Nt, A = case["n"], case["nb"], case["Nt"], case["A"]
+    ctx = tc.Context(n, nb)
+    Ad = to_dev(tc.pack_lower(A, nb))
+    L1 = tc.export(ctx, tc.factorize(ctx, Ad, n, nb)).cpu().numpy()
+    cm = np.zeros(Nt * (Nt + 1) // 2, dtype=np.uint8)
+    L2 = tc.export(ctx, tc.factorize(ctx, Ad, n, nb, cmap=cm)).cpu().numpy()
+    assert np.array_equal(L1, L2)
+
+
+@pytest.mark.parametrize("eps,nrhs", [(1e-5, 16), (1e-9, 3)])
+def test_refined_solve(tc, case, eps, nrhs):
+    n, nb, Nt, A = case["n"], case["nb"], case["Nt"], case["A"]
+    cm = tc.precision_map(Nt, case["norms"], case["fro"], eps)
+    ctx = tc.Context(n, nb, nrhs=nrhs)
+    Ad = to_dev(tc.pack_lower(A, nb))
+    F = tc.factorize(ctx, Ad, n, nb, cmap=cm)
+    B = si.standard_normal((n, nrhs), seed=si.rhs_seed(3))
+    Bd = to_dev(np.ascontiguousarray(B.T))
+    st = tc.solve_refine(ctx, F, Ad, Bd, max_iter=30, tol=1e-9)
+    X = Bd.cpu().numpy().T
+    rel = np.linalg.norm(B - A @ X, axis=0) / np.linalg.norm(B, axis=0)
+    assert st["converged"] and rel.max() <= 1e-9, (st, rel.max())
+    assert abs(st["rel_residual"] - rel.max()) <= 1e-3 * rel.max() + 1e-15
+    Xo = np.linalg.solve(A, B)
+    assert np.linalg.norm(X - Xo) <= case["kappa"] * 1e-9 * np.linalg.norm(Xo) * 4
+    # the oracle's refinement with the oracle's factor needs a similar count
+    Lo, _ = oracle.mxp_tile_cholesky(A, nb, cm)
+    _, it_o, _ = oracle.refine(A, Lo, B, tol=1e-9)
+    assert abs(st["iterations"] - it_o) <= 2
+
+
+def test_refinement_reports_nonconvergence(tc, case):
+    n, nb, Nt, A = case["n"], case["nb"], case["Nt"], case["A"]
+    cm = tc.precision_map(Nt, case["norms"], case["fro"], 1e-3)
+    ctx = tc.Context(n, nb)
+    Ad = to_dev(tc.pack_lower(A, nb))
+    F = tc.factorize(ctx, Ad, n, nb, cmap=cm)
+    Bd = to_dev(np.ascontiguousarray(si.standard_normal((n, 2), seed=5).T))
+    with pytest.raises(tc.TileCholError) as e:
+        tc.solve_refine(ctx, F, Ad, Bd, max_iter=0, tol=1e-14)
+    assert e.value.status == tc.TC_ENOTCONV
+    st = tc.solve_refine(ctx, F, Ad, Bd, max_iter=0, tol=1e-14, check=False)
+    assert st["iterations"] == 0 and not st["converged"]
+
+
+def test_fp64_refinement_converges_immediately(tc, case):
+    n, nb, A = case["n"], case["nb"], case["A"]
+    ctx = tc.Context(n, nb)
+    Ad = to_dev(tc.pack_lower(A, nb))
+    F = tc.factorize(ctx, Ad, n, nb)
+    Bd = to_dev(np.ascontiguousarray(si.standard_normal((n, 4), seed=6).T))
+    st = tc.solve_refine(ctx, F, Ad, Bd, tol=1e-12)
+    assert st["iterations"] <= 1 and st["rel_residual"] <= 1e-12

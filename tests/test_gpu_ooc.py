@@ -1,0 +1,103 @@
+"""GPU parity of the out-of-core factorization (Sections III-C, IV-B): the
+matrix and factor in pinned host memory, a device tile cache of a given
+size. Checked against the CPU oracle (same perturbation bound as the
+in-core FP64 path) and for its transfer volume:
+  * with a cache that holds every column's working set, each tile crosses
+    the link exactly once in each direction (A in, L out);
+  * with a cache of 2*Nt tiles the update is chunked, tiles are evicted by
+    the static next use and reloaded from the host copy of L, and the factor
+    is unchanged up to rounding.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import seeded_inputs as si
+
+pytestmark = pytest.mark.gpu
+
+U = 2.0 ** -53
+
+
+@pytest.fixture(scope="module")
+def tc():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2410_09819_amd as tc
+    tc.lib()
+    return tc
+
+
+@pytest.fixture(scope="module")
+def case():
+    n, nb = 2048, 128
+    w = si.WORKLOADS["small"]
+    pts = si.points(n, seed=w["seed"])
+    A = oracle.matern_matrix(pts, w["sigma2"], w["range"], w["nu"], w["nugget"])
+    Lo, info = oracle.tile_cholesky(A, nb, threads=8)
+    assert info == 0
+    return dict(n=n, nb=nb, A=A, Lo=Lo, kappa=np.linalg.cond(A))
+
+
+def pinned(x):
+    import torch
+    t = torch.empty(x.size, dtype=torch.float64, pin_memory=True)
+    t.copy_(torch.from_numpy(x))
+    return t
+
+
+@pytest.mark.parametrize("slots,inplace", [(400, False), (32, False), (40, True)])
+def test_ooc_matches_oracle(tc, case, slots, inplace):
+    import torch
+    n, nb, A, Lo = case["n"], case["nb"], case["A"], case["Lo"]
+    Nt = n // nb
+    ntiles = Nt * (Nt + 1) // 2
+    tbytes = nb * nb * 8
+    Ah = pinned(tc.pack_lower(A, nb))
+    Lh = Ah if inplace else pinned(np.zeros(ntiles * nb * nb))
+    ctx = tc.Context(n, nb)
+    cache = torch.empty(slots * tbytes, dtype=torch.uint8, device="cuda")
+    st = tc.factorize_ooc(ctx, Ah, n, nb, cache, L_host=Lh)
+    assert st["info"] == 0 and st["cache_slots"] == slots
+    L = np.tril(tc.unpack_lower(Lh.numpy(), n, nb))
+    assert np.linalg.norm(L - Lo) <= 4 * case["kappa"] * n * U * np.linalg.norm(Lo)
+    assert oracle.backward_error(A, L) <= 1e-14
+    assert st["bytes_d2h"] == ntiles * tbytes
+    if slots >= Nt * Nt // 4 + Nt:
+        assert st["bytes_h2d"] == ntiles * tbytes and st["tiles_reloaded"] == 0
+        assert st["chunks"] == Nt - 1
+    else:
+        assert st["evictions"] > 0 and st["tiles_reloaded"] > 0
+        assert st["bytes_h2d"] == (ntiles + st["tiles_reloaded"]) * tbytes
+
+
+def test_ooc_matches_in_core(tc, case):
+    import torch
+    n, nb, A = case["n"], case["nb"], case["A"]
+    ctx = tc.Context(n, nb)
+    Ad = torch.from_numpy(tc.pack_lower(A, nb)).cuda()
+    Lin = tc.unpack_lower(tc.export(ctx, tc.factorize(ctx, Ad, n, nb)).cpu().numpy(), n, nb)
+    Ah = pinned(tc.pack_lower(A, nb))
+    cache = torch.empty(400 * nb * nb * 8, dtype=torch.uint8, device="cuda")
+    tc.factorize_ooc(ctx, Ah, n, nb, cache)
+    L = np.tril(tc.unpack_lower(Ah.numpy(), n, nb))
+    assert np.linalg.norm(L - Lin) <= 4 * case["kappa"] * n * U * np.linalg.norm(Lin)
+
+
+def test_ooc_errors(tc, case):
+    import torch
+    n, nb = case["n"], case["nb"]
+    ctx = tc.Context(n, nb)
+    Ah = pinned(np.eye(n)[:1].ravel()[:1].repeat(tc.num_tiles(n, nb) * nb * nb))
+    small = torch.empty(10 * nb * nb * 8, dtype=torch.uint8, device="cuda")
+    with pytest.raises(tc.TileCholError) as e:
+        tc.factorize_ooc(ctx, Ah, n, nb, small)
+    assert e.value.status == tc.TC_ENOMEM
+    bad = np.eye(n) * 3.0
+    bad[700, 700] = -1.0
+    Bh = pinned(tc.pack_lower(bad, nb))
+    cache = torch.empty(64 * nb * nb * 8, dtype=torch.uint8, device="cuda")
+    with pytest.raises(tc.NotPositiveDefinite) as e:
+        tc.factorize_ooc(ctx, Bh, n, nb, cache)
+    assert e.value.info == 701

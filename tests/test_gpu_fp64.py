@@ -148,10 +148,10 @@ def test_errors_are_reported(tc):
     with pytest.raises(tc.TileCholError):
         tc.factorize(ctx, A, 1024, 200)
     cm = np.zeros(10, dtype=np.uint8)
-    cm[1] = tc.FP32
+    cm[0] = tc.FP32  # diagonal tiles must stay FP64
     with pytest.raises(tc.TileCholError) as e:
         tc.factorize(ctx, A, 1024, 256, cmap=cm)
-    assert e.value.status == tc.TC_EUNSUPPORTED
+    assert e.value.status == tc.TC_EINVAL
     small = tc.Context(256, 128)
     with pytest.raises(tc.TileCholError) as e:
         tc.factorize(small, A, 1024, 256)

@@ -222,6 +222,50 @@ tc_status tc_factorize_ooc(tc_ctx *ctx, int64_t n, int32_t nb, const double *A_h
  * storage; otherwise it must be a separate buffer. */
 tc_status tc_factor_export(tc_ctx *ctx, const tc_factor *L, double *L64);
 
+/* ---- Gradient of the Gaussian log-likelihood (Eq. 1) ------------------
+ * The log-likelihood l(theta) = -n/2 log(2 pi) - 1/2 log|Sigma| - 1/2 y^T
+ * Sigma^{-1} y of Eq. 1 is differentiated by reverse mode through the tile
+ * Cholesky: seed dl/dL, run the blocked reverse sweep of the factorization
+ * (Murray, "Differentiation of the Cholesky decomposition", 2016) to get
+ * dl/dA for the lower triangle, then contract it with the derivatives of
+ * the Matern covariance (Eq. 2 plus the nugget). */
+
+/* With z = L^{-1} y and alpha = L^{-T} z: *loglik = -n/2 log(2 pi) -
+ * sum_i log L_ii - 1/2 z^T z (host), and Lbar (device, packed lower tiles
+ * (n, nb), binary64, overwritten, strict upper triangle of the diagonal
+ * tiles zero) receives dl/dL = tril(alpha z^T) - diag(1 / L_ii).
+ * y: device, n binary64. L: an all-FP64 factor (TC_EUNSUPPORTED for a
+ * mixed-precision one). */
+tc_status tc_loglik_seed(tc_ctx *ctx, const tc_factor *L, const double *y, double *Lbar,
+                         double *loglik);
+
+/* Bytes of device scratch tc_factor_adjoint needs (about the size of the
+ * factor plus two tile columns); 0 for an invalid shape. */
+size_t tc_adjoint_bytes(int64_t n, int32_t nb);
+
+/* Reverse sweep of the tile Cholesky. On input Lbar (device, packed lower
+ * tiles, binary64) holds d(phi)/dL for a scalar phi of the factor (lower
+ * triangle; the strict upper triangle of diagonal tiles is ignored). On
+ * output it holds Abar = d(phi)/dA for the lower triangle of A, the only
+ * part the factorization reads: phi changes by sum_{i>=j} Abar_ij dA_ij when
+ * A_ij and A_ji change by dA_ij (strict upper triangle of diagonal tiles set
+ * to zero). L: the all-FP64 factor of A (TC_EUNSUPPORTED otherwise).
+ * scratch: device buffer of at least tc_adjoint_bytes(n, nb) bytes.
+ * stats: NULL or filled (ms_total, flops_total; ms_gemm, gemm_flops and
+ * gemm_launches for the panel GEMMs when the context is timed). */
+tc_status tc_factor_adjoint(tc_ctx *ctx, const tc_factor *L, double *Lbar, void *scratch,
+                            size_t scratch_bytes, tc_stats *stats);
+
+/* Contraction of Abar (device, packed lower tiles (n, nb), binary64, lower
+ * triangle read) with the Matern derivatives, entries regenerated from the
+ * locations (device, n x 2 row-major) and th:
+ *   grad[0] = sum_{i>=j} Abar_ij dSigma_ij/dsigma2   (= C_ij / sigma2),
+ *   grad[1] = sum_{i>=j} Abar_ij dSigma_ij/drange,
+ *   grad[2] = sum_i Abar_ii                           (dSigma/dnugget = I).
+ * grad: host, 3 doubles. Deterministic (fixed reduction order). */
+tc_status tc_matern_grad(tc_ctx *ctx, int64_t n, int32_t nb, const double *locs,
+                         const tc_matern *th, const double *Abar, double grad[3]);
+
 /* Free the handle (not the caller's storage). NULL is accepted. */
 tc_status tc_factor_destroy(tc_factor *L);
 

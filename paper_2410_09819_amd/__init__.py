@@ -116,6 +116,11 @@ def lib():
         "tc_factorize_ooc": (_i32, [_vp, _i64, _i32, _vp, _vp, _vp, _sz, ctypes.POINTER(OocStats)]),
         "tc_factor_export": (_i32, [_vp, _vp, _vp]),
         "tc_factor_destroy": (_i32, [_vp]),
+        "tc_loglik_seed": (_i32, [_vp, _vp, _vp, _vp, ctypes.POINTER(ctypes.c_double)]),
+        "tc_adjoint_bytes": (_sz, [_i64, _i32]),
+        "tc_factor_adjoint": (_i32, [_vp, _vp, _vp, _vp, _sz, ctypes.POINTER(Stats)]),
+        "tc_matern_grad": (_i32, [_vp, _i64, _i32, _vp, ctypes.POINTER(Matern), _vp,
+                                  ctypes.POINTER(ctypes.c_double)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -344,3 +349,98 @@ def export(ctx: Context, F: Factor, out=None):
                           device=F.storage.device)
     _check(lib().tc_factor_export(ctx.handle, F.handle, out.data_ptr()))
     return out
+
+
+# --- log-likelihood gradient (reverse mode through the tile Cholesky) ------
+
+def adjoint_bytes(n: int, nb: int) -> int:
+    return lib().tc_adjoint_bytes(n, nb)
+
+
+def loglik_seed(ctx: Context, F: Factor, y, Lbar) -> float:
+    """Eq. 1's log-likelihood from the factor and y (device float64, n);
+    fills Lbar (device, packed lower tiles) with dl/dL."""
+    assert y.is_contiguous() and y.numel() == F.n
+    out = ctypes.c_double(0.0)
+    _check(lib().tc_loglik_seed(ctx.handle, F.handle, y.data_ptr(), Lbar.data_ptr(),
+                                ctypes.byref(out)))
+    return out.value
+
+
+def factor_adjoint(ctx: Context, F: Factor, Lbar, scratch=None) -> Stats:
+    """In place: Lbar (dphi/dL, packed lower tiles) <- dphi/dA (lower
+    triangle). Returns the sweep's statistics."""
+    import torch
+    nbytes = adjoint_bytes(F.n, F.nb)
+    if scratch is None:
+        scratch = torch.empty(nbytes, dtype=torch.uint8, device=Lbar.device)
+    st = Stats()
+    _check(lib().tc_factor_adjoint(ctx.handle, F.handle, Lbar.data_ptr(), scratch.data_ptr(),
+                                   scratch.numel() * scratch.element_size(), ctypes.byref(st)))
+    return st
+
+
+def matern_grad(ctx: Context, locs, theta, nb: int, Abar):
+    """(sum Abar dSigma/dsigma2, sum Abar dSigma/drange, sum Abar dSigma/dnugget)
+    over the lower triangle; theta = (sigma2, range, nu, nugget)."""
+    assert locs.is_contiguous() and locs.shape[1] == 2
+    th = Matern(*[float(v) for v in theta])
+    g = (ctypes.c_double * 3)()
+    _check(lib().tc_matern_grad(ctx.handle, locs.shape[0], nb, locs.data_ptr(), ctypes.byref(th),
+                                Abar.data_ptr(), g))
+    return np.array(list(g))
+
+
+def _autograd_function():
+    import torch
+
+    class MaternLogLik(torch.autograd.Function):
+        """l(theta) of Eq. 1 for the Matern covariance with nugget, theta =
+        (sigma2, range, nugget) as a float64 tensor, nu fixed. Forward:
+        covariance tiles, tile Cholesky (in place), log-likelihood and the
+        reverse-mode seed. Backward: the blocked reverse sweep and the
+        contraction with the covariance derivatives."""
+
+        @staticmethod
+        def forward(fctx, theta, locs, y, nu, nb, ctx):
+            th = [float(v) for v in theta.detach().cpu().tolist()]
+            n = locs.shape[0]
+            full = (th[0], th[1], float(nu), th[2])
+            A, _, _ = matern_tiles(ctx, locs, full, nb, norms=False)
+            F = factorize(ctx, A, n, nb, inplace=True)
+            Lbar = torch.empty_like(A)
+            ll = loglik_seed(ctx, F, y, Lbar)
+            fctx.state = (ctx, F, Lbar, locs, full, nb)
+            return torch.tensor(ll, dtype=torch.float64, device=theta.device)
+
+        @staticmethod
+        def backward(fctx, gout):
+            ctx, F, Lbar, locs, full, nb = fctx.state
+            fctx.state = None
+            factor_adjoint(ctx, F, Lbar)
+            g = matern_grad(ctx, locs, full, nb, Lbar)
+            F.close()
+            grad = torch.from_numpy(g).to(device=gout.device, dtype=gout.dtype) * gout
+            return grad, None, None, None, None, None
+
+    return MaternLogLik
+
+
+_MLL = None
+
+
+def matern_loglik(theta, locs, y, nu: float, nb: int, ctx: Context):
+    """Differentiable log-likelihood (torch.autograd): see MaternLogLik."""
+    global _MLL
+    if _MLL is None:
+        _MLL = _autograd_function()
+    return _MLL.apply(theta, locs, y, nu, nb, ctx)
+
+
+def __getattr__(name):
+    if name == "MaternLogLik":
+        global _MLL
+        if _MLL is None:
+            _MLL = _autograd_function()
+        return _MLL
+    raise AttributeError(name)

@@ -116,4 +116,46 @@ hipError_t launch_axpy(hipStream_t s, double* Y, int64_t ldy, const double* D, i
 hipError_t launch_copy_cols(hipStream_t s, double* Y, int64_t ldy, const double* X, int64_t ldx,
                             int64_t n, int nrhs);
 
+// Reverse mode (adjoint.hip). AdjMat: element (r, c) of a matrix whose rows
+// come in chunks of `rt` rows placed `rs` doubles apart, each chunk
+// column-major with leading dimension `ld` (rt = nb, rs = nb^2 for a column
+// of tiles; rs = 0 and rt >= rows for a plain column-major matrix).
+struct AdjMat {
+    double* p;
+    int64_t ld, rt, rs;
+    __host__ __device__ int64_t off(int64_t r, int64_t c) const {
+        return (r / rt) * rs + (r % rt) + c * ld;
+    }
+};
+struct AdjGemmPlan {
+    int block;
+    int splits;
+    int64_t nblocks;
+    size_t partial_doubles;
+};
+// Lbar_mn -= sum_{k>n} S_mk L_kn for the tiles below (n, n) (see adjoint.hip).
+hipError_t launch_adj_panel(hipStream_t s, double* Lb, const double* Tt, const double* PL, int Nt,
+                            int nb, int n, int splits, double* partial);
+int64_t adj_panel_blocks(int Nt, int nb, int n);
+int adj_panel_splits(int Nt, int nb, int n);
+// C = A B^T (sub: C -= A B^T); A: M x K, B: N x K, all AdjMat with the same
+// ld; block rows must not straddle chunks. lower: only blocks on or below
+// the diagonal (M == N).
+AdjGemmPlan adj_gemm_plan(int64_t M, int64_t N, int64_t K, bool lower);
+hipError_t launch_adj_gemm(hipStream_t s, const AdjMat& C, const AdjMat& A, const AdjMat& B,
+                           int64_t M, int64_t N, int64_t K, bool sub, bool lower, double* partial);
+hipError_t launch_transpose_tiles(hipStream_t s, const double* src, double* dst, int nb,
+                                  int64_t count, bool tril);
+hipError_t launch_set_identity(hipStream_t s, double* X, int nb);
+hipError_t launch_mirror_lower(hipStream_t s, double* P, int nb);
+hipError_t launch_finish_diag(hipStream_t s, const double* H, double* D, int nb);
+hipError_t launch_loglik_seed(hipStream_t s, const double* L, const double* alpha, const double* z,
+                              double* Lb, int Nt, int nb);
+// sum_{i>=j} Abar_ij (C_ij / sigma2, dC_ij/drange) and sum_i Abar_ii, as 3
+// partial sums per (tile, strip) in `part` (matern.hip).
+hipError_t launch_matern_grad(hipStream_t s, int64_t n, int nb, const double* locs, double sigma2,
+                              double inv_range, double nu, int nu_kind, double norm_const,
+                              const double* Abar, double* part);
+hipError_t launch_sum3(hipStream_t s, const double* part, int64_t count, double* out);
+
 }  // namespace tc

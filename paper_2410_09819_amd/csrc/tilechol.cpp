@@ -72,7 +72,8 @@ Layout layout(int64_t n, int nb, int nrhs) {
     L.info = 0;
     L.big = align_up(sizeof(int) * 64);
     L.small = L.big + align_up(big_bytes(n, nb));
-    size_t small = std::max<size_t>((size_t)ntiles * tc::matern_strips(nb), (size_t)Nt * 16);
+    // Matern strip sums; three per strip for the gradient contraction
+    size_t small = std::max<size_t>((size_t)3 * ntiles * tc::matern_strips(nb) + 8, (size_t)Nt * 16);
     small = std::max<size_t>(small, (size_t)2 * nrhs * tc::colnorm_blocks());
     L.panel = L.small + align_up(small * sizeof(double));
     // two working columns (the out-of-core path prefetches the next one)
@@ -249,8 +250,8 @@ const double* diag_tile(const tc_factor* F, int k) {
 }
 
 // B <- (L L^T)^{-1} B, enqueued on the context stream (no synchronization).
-tc_status solve_enqueue(tc_ctx* ctx, const tc_factor* F, double* B, int64_t ldb, int nrhs,
-                        double* big) {
+// B <- L^{-1} B (forward substitution by tile rows).
+tc_status fwd_enqueue(tc_ctx* ctx, const tc_factor* F, double* B, int64_t ldb, int nrhs) {
     const int Nt = F->Nt, nb = F->nb;
     const tc::TileView V = view_of(F);
     for (int k = 0; k < Nt; ++k) {
@@ -260,6 +261,14 @@ tc_status solve_enqueue(tc_ctx* ctx, const tc_factor* F, double* B, int64_t ldb,
             TC_HIP(tc::launch_fwd_update(ctx->stream, V, k, B + (int64_t)k * nb,
                                          B + (int64_t)(k + 1) * nb, ldb, nrhs));
     }
+    return TC_OK;
+}
+
+// B <- L^{-T} B (back substitution by tile rows).
+tc_status bwd_enqueue(tc_ctx* ctx, const tc_factor* F, double* B, int64_t ldb, int nrhs,
+                      double* big) {
+    const int Nt = F->Nt, nb = F->nb;
+    const tc::TileView V = view_of(F);
     for (int k = Nt - 1; k >= 0; --k) {
         if (k + 1 < Nt) {
             const int64_t rows = (int64_t)(Nt - k - 1) * nb;
@@ -270,6 +279,12 @@ tc_status solve_enqueue(tc_ctx* ctx, const tc_factor* F, double* B, int64_t ldb,
                                     true));
     }
     return TC_OK;
+}
+
+tc_status solve_enqueue(tc_ctx* ctx, const tc_factor* F, double* B, int64_t ldb, int nrhs,
+                        double* big) {
+    if (tc_status s = fwd_enqueue(ctx, F, B, ldb, nrhs)) return s;
+    return bwd_enqueue(ctx, F, B, ldb, nrhs, big);
 }
 
 // Column norms of X (n x nrhs): ||x_j||_2 into out[j] (synchronizes).
@@ -722,6 +737,33 @@ tc_status tc_logdet(tc_ctx* ctx, const tc_factor* F, double* out) {
     double s = 0.0;
     for (double v : h) s += v;
     *out = 2.0 * s;
+    return TC_OK;
+}
+
+tc_status tc_loglik_seed(tc_ctx* ctx, const tc_factor* F, const double* y, double* Lbar,
+                         double* loglik) {
+    if (!ctx || !F || !y || !Lbar || !loglik) return fail(TC_EINVAL, "NULL argument");
+    if (F->info > 0) return fail(TC_EINVAL, "factor is not valid (factorization failed)");
+    if (F->mixed) return fail(TC_EUNSUPPORTED, "the likelihood seed needs an all-FP64 factor");
+    if (tc_status s = check_ws(ctx, F->n, F->nb)) return s;
+    DeviceGuard g(ctx->device);
+    const int64_t n = F->n;
+    const Layout Ly = layout(n, F->nb);
+    double* big = reinterpret_cast<double*>(ctx->ws + Ly.big);
+    double* part = reinterpret_cast<double*>(ctx->ws + Ly.small);
+    double* z = reinterpret_cast<double*>(ctx->ws + Ly.ir);
+    double* alpha = z + n;
+    TC_HIP(tc::launch_copy_cols(ctx->stream, z, n, y, n, n, 1));
+    if (tc_status s = fwd_enqueue(ctx, F, z, n, 1)) return s;
+    TC_HIP(tc::launch_copy_cols(ctx->stream, alpha, n, z, n, n, 1));
+    if (tc_status s = bwd_enqueue(ctx, F, alpha, n, 1, big)) return s;
+    TC_HIP(tc::launch_loglik_seed(ctx->stream, F->tiles, alpha, z, Lbar, F->Nt, F->nb));
+    std::vector<double> zn;
+    if (tc_status s = colnorms(ctx, z, n, n, 1, part, zn)) return s;
+    double ld = 0.0;
+    if (tc_status s = tc_logdet(ctx, F, &ld)) return s;
+    const double pi = 3.14159265358979323846;
+    *loglik = -0.5 * (double)n * std::log(2.0 * pi) - 0.5 * ld - 0.5 * zn[0] * zn[0];
     return TC_OK;
 }
 

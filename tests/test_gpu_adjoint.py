@@ -1,0 +1,236 @@
+"""GPU parity of the log-likelihood gradient: the reverse sweep of the tile
+Cholesky (C-ABI through the Python binding) against the CPU oracle.
+
+What pins what:
+  * Abar for the log-likelihood seed equals, for the lower-triangle
+    convention, 2 dl/dSigma off the diagonal and dl/dSigma on it, where
+    dl/dSigma = (alpha alpha^T - Sigma^{-1}) / 2 is the textbook closed form;
+    the oracle computes alpha and Sigma^{-1} with its own substitutions.
+  * For an arbitrary seed Lbar the sweep is the adjoint of the
+    factorization's derivative: <Lbar, dL> = sum_{i>=j} Abar_ij E_ij for a
+    symmetric direction E, with dL from central differences of the oracle's
+    Cholesky (error O(h^2) + O(u/h), about 1e-9 relative here).
+  * The gradient equals the oracle's trace formula (Eq. 1 differentiated,
+    an independent route) within 1e-8 relative per component, and the
+    log-likelihood equals the oracle's.
+  * At full size (n = 32768, nb = 512, 4000 base points translated), the
+    gradient equals central differences of the GPU log-likelihood within
+    1e-4 relative (step 1e-6 relative: truncation ~1e-12, rounding of l
+    divided by the step ~1e-6 relative).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import seeded_inputs as si
+
+pytestmark = pytest.mark.gpu
+
+U = 2.0 ** -53
+
+
+@pytest.fixture(scope="module")
+def tc():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2410_09819_amd as tc
+    tc.lib()
+    return tc
+
+
+def dev():
+    import torch
+    return torch.device("cuda", 0)
+
+
+def to_dev(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).to(dev())
+
+
+def data(n, nu=0.5, theta0=(1.0, 0.1, 1e-4), base=4000, seed=4):
+    pts = si.translated_points(n, base, seed=seed)
+    A = oracle.matern_matrix(pts, theta0[0], theta0[1], nu, theta0[2])
+    y = np.linalg.cholesky(A) @ si.standard_normal(n, seed=si.rhs_seed(seed))
+    return pts, y
+
+
+def gpu_loglik_grad(tc, pts, y, theta, nu, nb, ctx=None):
+    """(l, grad, Abar as dense lower) through the C-ABI."""
+    import torch
+    n = len(pts)
+    ctx = ctx or tc.Context(n, nb)
+    locs = to_dev(pts)
+    A, _, _ = tc.matern_tiles(ctx, locs, (theta[0], theta[1], nu, theta[2]), nb, norms=False)
+    F = tc.factorize(ctx, A, n, nb, inplace=True)
+    Lbar = torch.empty_like(A)
+    ll = tc.loglik_seed(ctx, F, to_dev(y), Lbar)
+    tc.factor_adjoint(ctx, F, Lbar)
+    g = tc.matern_grad(ctx, locs, (theta[0], theta[1], nu, theta[2]), nb, Lbar)
+    F.close()
+    return ll, g, Lbar
+
+
+@pytest.mark.parametrize("n,nb", [(1024, 256), (1536, 128), (768, 384)])
+def test_abar_matches_closed_form(tc, n, nb):
+    pts, y = data(n)
+    th = (1.2, 0.08, 2e-4)
+    ll, g, Lbar = gpu_loglik_grad(tc, pts, y, th, 0.5, nb)
+    Ab = tc.unpack_lower(Lbar.cpu().numpy(), n, nb)
+    A = oracle.matern_matrix(pts, th[0], th[1], 0.5, th[2])
+    Lo, info = oracle.tile_cholesky(A, nb, threads=8)
+    assert info == 0
+    alpha = oracle.solve(Lo, y)
+    Sinv = oracle.solve(Lo, np.eye(n))
+    G = 0.5 * (np.outer(alpha, alpha) - Sinv)
+    want = np.tril(2.0 * G, -1) + np.diag(np.diag(G))
+    kappa = np.linalg.cond(A)
+    err = np.linalg.norm(Ab - want) / np.linalg.norm(want)
+    assert err <= 4 * kappa * n * U, (err, kappa)
+    assert np.all(np.triu(Ab, 1) == 0.0)
+
+
+@pytest.mark.parametrize("n,nb", [(256, 128), (384, 128), (768, 256)])
+def test_adjoint_identity_random_seed(tc, n, nb):
+    import torch
+    L0 = si.random_factor(n, seed=n)
+    A = L0 @ L0.T
+    ctx = tc.Context(n, nb)
+    F = tc.factorize(ctx, to_dev(tc.pack_lower(A, nb)), n, nb)
+    Lb = np.tril(np.asarray(si.standard_normal((n, n), seed=n + 1)))
+    P = tc.pack_lower(Lb, nb)
+    # garbage in the strict upper triangle of the diagonal tiles is ignored
+    Nt = n // nb
+    for k in range(Nt):
+        t = oracle.tile_index(Nt, k, k)
+        tile = P[t * nb * nb:(t + 1) * nb * nb].reshape(nb, nb).T  # column-major view
+        tile[np.triu_indices(nb, 1)] = 7.0
+    Lbar = to_dev(P)
+    tc.factor_adjoint(ctx, F, Lbar)
+    Ab = tc.unpack_lower(Lbar.cpu().numpy(), n, nb)
+    for d in range(3):
+        E = np.asarray(si.standard_normal((n, n), seed=100 * n + d))
+        E = E + E.T
+        h = 1e-6 * np.linalg.norm(A) / np.linalg.norm(E)
+        Lp, ip = oracle.tile_cholesky(A + h * E, nb, threads=8)
+        Lm, im = oracle.tile_cholesky(A - h * E, nb, threads=8)
+        assert ip == im == 0
+        dL = (Lp - Lm) / (2 * h)
+        lhs = float(np.sum(Lb * dL))
+        rhs = float(np.sum(np.tril(Ab) * np.tril(E)))
+        scale = float(np.sum(np.abs(Lb) * np.abs(dL)))
+        assert abs(lhs - rhs) <= 1e-7 * scale, (lhs, rhs, scale)
+
+
+@pytest.mark.parametrize("nu,n,nb", [(0.5, 1024, 256), (1.5, 1024, 128), (1.0, 1024, 256),
+                                     (0.8, 768, 128), (2.5, 512, 128)])
+def test_gradient_matches_trace_formula(tc, nu, n, nb):
+    pts, y = data(n, nu=nu)
+    th = (1.2, 0.08, 2e-4)
+    ll, g, _ = gpu_loglik_grad(tc, pts, y, th, nu, nb)
+    lo, go = oracle.loglik_grad(pts, y, th[0], th[1], nu, th[2], nb=nb)
+    assert abs(ll - lo) <= 1e-10 * abs(lo), (ll, lo)
+    for p in range(3):
+        assert abs(g[p] - go[p]) <= 1e-8 * abs(go[p]), (p, g[p], go[p])
+
+
+def test_autograd_function(tc):
+    import torch
+    n, nb = 1024, 256
+    pts, y = data(n)
+    ctx = tc.Context(n, nb)
+    theta = torch.tensor([1.2, 0.08, 2e-4], dtype=torch.float64, requires_grad=True)
+    ll = tc.matern_loglik(theta, to_dev(pts), to_dev(y), 0.5, nb, ctx)
+    (2.0 * ll).backward()
+    lo, go = oracle.loglik_grad(pts, y, 1.2, 0.08, 0.5, 2e-4, nb=nb)
+    assert abs(float(ll) - lo) <= 1e-10 * abs(lo)
+    gg = theta.grad.numpy()
+    assert np.all(np.abs(gg - 2 * go) <= 1e-8 * np.abs(2 * go)), (gg, go)
+
+
+def test_errors(tc):
+    import torch
+    n, nb = 512, 128
+    L0 = si.random_factor(n, seed=5)
+    ctx = tc.Context(n, nb)
+    F = tc.factorize(ctx, to_dev(tc.pack_lower(L0 @ L0.T, nb)), n, nb)
+    Lbar = torch.zeros(tc.num_tiles(n, nb) * nb * nb, dtype=torch.float64, device=dev())
+    small = torch.empty(tc.adjoint_bytes(n, nb) - 8, dtype=torch.uint8, device=dev())
+    with pytest.raises(tc.TileCholError) as e:
+        tc.factor_adjoint(ctx, F, Lbar, scratch=small)
+    assert e.value.status == tc.TC_ENOMEM
+    # mixed-precision factors are not differentiated
+    A = to_dev(tc.pack_lower(L0 @ L0.T, nb))
+    cm = np.zeros(tc.num_tiles(n, nb), dtype=np.uint8)
+    cm[1] = tc.FP32
+    Fm = tc.factorize(ctx, A, n, nb, cmap=cm)
+    with pytest.raises(tc.TileCholError) as e:
+        tc.factor_adjoint(ctx, Fm, Lbar)
+    assert e.value.status == tc.TC_EUNSUPPORTED
+    with pytest.raises(tc.TileCholError) as e:
+        tc.loglik_seed(ctx, Fm, torch.zeros(n, dtype=torch.float64, device=dev()), Lbar)
+    assert e.value.status == tc.TC_EUNSUPPORTED
+
+
+def _lower_matvec(tc, L, z, n, nb):
+    """y = L z for packed lower tiles L (device), by tiles (input synthesis)."""
+    import torch
+    Nt = n // nb
+    y = torch.zeros(n, dtype=torch.float64, device=L.device)
+    for j in range(Nt):
+        zj = z[j * nb:(j + 1) * nb]
+        for i in range(j, Nt):
+            t = oracle.tile_index(Nt, i, j)
+            Lij = L[t * nb * nb:(t + 1) * nb * nb].view(nb, nb).t()
+            if i == j:
+                Lij = torch.tril(Lij)
+            y[i * nb:(i + 1) * nb] += Lij @ zj
+    return y
+
+
+def test_full_size_gradient_central_differences(tc):
+    """The gradient workload: n = 32768, nb = 512, 4000 base points
+    translated, data y = L(theta0) z, gradient at theta_eval."""
+    import torch
+    w = si.WORKLOADS["grad"]
+    n, nb, nu = w["n"], w["nb"], w["nu"]
+    pts = si.translated_points(n, w["base_points"], seed=w["seed"])
+    locs = to_dev(pts)
+    ctx = tc.Context(n, nb)
+    A0, _, _ = tc.matern_tiles(ctx, locs, (w["sigma2"], w["range"], nu, w["nugget"]), nb,
+                               norms=False)
+    F0 = tc.factorize(ctx, A0, n, nb, inplace=True)
+    z = to_dev(si.standard_normal(n, seed=si.rhs_seed(w["seed"])))
+    y = _lower_matvec(tc, A0, z, n, nb)
+    F0.close()
+    del A0
+    th = np.array(w["theta_eval"])
+
+    def loglik(t):
+        A, _, _ = tc.matern_tiles(ctx, locs, (t[0], t[1], nu, t[2]), nb, norms=False)
+        F = tc.factorize(ctx, A, n, nb, inplace=True)
+        Lb = torch.empty_like(A)
+        v = tc.loglik_seed(ctx, F, y, Lb)
+        F.close()
+        return v
+
+    A, _, _ = tc.matern_tiles(ctx, locs, (th[0], th[1], nu, th[2]), nb, norms=False)
+    F = tc.factorize(ctx, A, n, nb, inplace=True)
+    Lbar = torch.empty_like(A)
+    l0 = tc.loglik_seed(ctx, F, y, Lbar)
+    st = tc.factor_adjoint(ctx, F, Lbar)
+    g = tc.matern_grad(ctx, locs, (th[0], th[1], nu, th[2]), nb, Lbar)
+    F.close()
+    del A, Lbar
+    torch.cuda.empty_cache()
+    print("l =", l0, "grad =", g, "reverse sweep ms =", st.ms_total, flush=True)
+    assert np.all(np.isfinite(g))
+    for p in range(3):
+        h = 1e-6 * th[p]
+        tp, tm = th.copy(), th.copy()
+        tp[p] += h
+        tm[p] -= h
+        fd = (loglik(tp) - loglik(tm)) / (2 * h)
+        print("p", p, "fd", fd, "adjoint", g[p], flush=True)
+        assert abs(fd - g[p]) <= 1e-4 * abs(g[p]), (p, fd, g[p])

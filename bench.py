@@ -14,7 +14,8 @@ Prints one JSON line. `roofline` is the dominant kernel (the panel GEMM)
 timed with HIP events on the library's compute stream: algorithmic flops of
 all its launches / summed launch time, against the FP64 matrix peak.
 `cpu_baseline` times the CPU oracle on a bounded sample of the same workload
-(the leading 4096 x 4096 principal block, same tile size).
+(the leading 4096 x 4096 principal block, same tile size). `mxp_vs_fp64` and
+`loglik_grad` are the mixed-precision and likelihood-gradient legs.
 """
 from __future__ import annotations
 
@@ -116,6 +117,73 @@ def mxp_comparison(tc, si, dev):
     return out
 
 
+def grad_leg(tc, si, dev):
+    """Log-likelihood and its gradient at n=32768, nb=512 (4000 base points
+    translated, nu=1/2): forward = covariance tiles + factorization +
+    log-likelihood seed; backward = reverse sweep + contraction with the
+    covariance derivatives. The data y = L(theta0) z is made before timing."""
+    import numpy as np
+    import torch
+    w = si.WORKLOADS["grad"]
+    n, nb, nu = w["n"], w["nb"], w["nu"]
+    pts = si.translated_points(n, w["base_points"], seed=w["seed"])
+    locs = torch.from_numpy(pts).to(dev)
+    ctx = tc.Context(n, nb, timed=True)
+    A0, _, _ = tc.matern_tiles(ctx, locs, (w["sigma2"], w["range"], nu, w["nugget"]), nb,
+                               norms=False)
+    F0 = tc.factorize(ctx, A0, n, nb, inplace=True)
+    y = torch.empty(n, dtype=torch.float64, device=dev)
+    # y = L z by tiles: input synthesis, outside the timed region
+    z = torch.from_numpy(np.asarray(si.standard_normal(n, seed=si.rhs_seed(w["seed"])))).to(dev)
+    Nt = n // nb
+    y.zero_()
+    for j in range(Nt):
+        for i in range(j, Nt):
+            t = tc.tile_offset(Nt, i, j)
+            Lij = A0[t * nb * nb:(t + 1) * nb * nb].view(nb, nb).t()
+            if i == j:
+                Lij = torch.tril(Lij)
+            y[i * nb:(i + 1) * nb] += Lij @ z[j * nb:(j + 1) * nb]
+    F0.close()
+    del A0
+    torch.cuda.empty_cache()
+    th = w["theta_eval"]
+    full = (th[0], th[1], nu, th[2])
+    Lbar = torch.empty(tc.num_tiles(n, nb) * nb * nb, dtype=torch.float64, device=dev)
+    scratch = torch.empty(tc.adjoint_bytes(n, nb), dtype=torch.uint8, device=dev)
+    A = torch.empty_like(Lbar)
+
+    def once():
+        tc.matern_tiles(ctx, locs, full, nb, out=A, norms=False)
+        F = tc.factorize(ctx, A, n, nb, inplace=True)
+        ll = tc.loglik_seed(ctx, F, y, Lbar)
+        st = tc.factor_adjoint(ctx, F, Lbar, scratch=scratch)
+        g = tc.matern_grad(ctx, locs, full, nb, Lbar)
+        F.close()
+        return ll, g, st
+
+    once()
+    torch.cuda.synchronize()
+    reps = 3
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ll, g, st = once()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    fwd = n ** 3 / 3.0
+    out = {"workload": "loglik + gradient, n=%d nb=%d, Matern nu=%g, 4000 base points translated, "
+                       "theta=(%g, %g, %g)" % (n, nb, nu, th[0], th[1], th[2]),
+           "s_per_eval": dt, "loglik": ll, "grad": [float(v) for v in g],
+           "reverse_sweep_ms": st.ms_total, "reverse_sweep_flops": st.flops_total,
+           "reverse_sweep_tflops": st.flops_total / (st.ms_total * 1e-3) / 1e12,
+           "reverse_panel_tflops": (st.gemm_flops / (st.ms_gemm * 1e-3) / 1e12
+                                    if st.ms_gemm > 0 else None),
+           "forward_plus_reverse_tflops": (fwd + st.flops_total) / dt / 1e12}
+    del A, Lbar, scratch
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -124,6 +192,11 @@ def main():
     ap.add_argument("--workload", default="fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mxp", action="store_true", help="skip the mixed-precision comparison")
+    ap.add_argument("--no-grad", action="store_true", help="skip the likelihood-gradient leg")
+    ap.add_argument("--mxp-only", action="store_true",
+                    help="only the mixed-precision comparison (for profiling)")
+    ap.add_argument("--grad-only", action="store_true",
+                    help="only the likelihood-gradient leg (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the tile Cholesky here runs on a single MI355X "
@@ -139,10 +212,14 @@ def main():
     if not os.path.exists(tc.LIB_PATH):
         from paper_2410_09819_amd import build
         build.build()
+    dev = torch.device("cuda", 0)
+    if args.mxp_only or args.grad_only:
+        res = mxp_comparison(tc, si, dev) if args.mxp_only else grad_leg(tc, si, dev)
+        print(json.dumps(res), flush=True)
+        return
     w = si.WORKLOADS[args.workload]
     n, nb = w["n"], w["nb"]
     nrhs = 16
-    dev = torch.device("cuda", 0)
     theta = (w["sigma2"], w["range"], w["nu"], w["nugget"])
     pts = torch.from_numpy(si.points(n, seed=w["seed"])).to(dev)
     ctx = tc.Context(n, nb, timed=True)
@@ -218,6 +295,7 @@ def main():
     del storage, A, F
     torch.cuda.empty_cache()
     out["mxp_vs_fp64"] = None if args.no_mxp else mxp_comparison(tc, si, dev)
+    out["loglik_grad"] = None if args.no_grad else grad_leg(tc, si, dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)

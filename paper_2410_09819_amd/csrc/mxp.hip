@@ -8,11 +8,12 @@
 // MFMA on the stored operands, upcast exactly while they are staged into LDS.
 // The low classes use FP32 MFMA with FP32 accumulation on "operand copies":
 // for every tile and every low class it will be multiplied in (known from
-// the static schedule), the finalize step writes Q_p(Lh) in binary32. A
-// product of two values of class <= FP32 is exact in binary32 arithmetic
-// only for FP16/BF16/FP8 operands; for those the FP32 MFMA reproduces the
-// narrow-format MFMA's FP32-accumulated result exactly in kind (same
-// operands, FP32 accumulation). POTRF and TRSM run in FP64 on a working
+// the static schedule), the finalize step writes Q_p(Lh) in binary32. For
+// FP16, BF16 and FP8 operands every product of two operands is exact in
+// binary32 (barring underflow), so this computes what a narrow-format MFMA with FP32
+// accumulation computes (same rounded operands, exact products, binary32
+// sums; only the summation order may differ). For FP32-class tiles the
+// products are rounded to binary32 as usual. POTRF and TRSM run in FP64 on a working
 // copy of the column; finalize rounds each new tile to its class (with its
 // scale) into the factor storage and writes its operand copies.
 #include "formats.hpp"

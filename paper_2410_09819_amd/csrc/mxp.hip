@@ -36,6 +36,13 @@ __device__ __forceinline__ int64_t xcd_remap_m(int64_t hw, int64_t total) {
 
 // ---------------------------------------------------------------------------
 // FP64 main loop over operands stored in any class (upcast while staging).
+//
+// Each thread moves 8 consecutive rows of one column of a 128 x 16 operand
+// slab per stage: one to four 16-byte loads of the stored bits (8 doubles,
+// 8 floats, 8 halves or 8 e4m3 bytes). The raw bits stay in registers while
+// the current stage's MFMAs run and are decoded, scaled by 2^scale (exact)
+// and written to LDS only after them, so the loads overlap the math as in
+// the all-FP64 main loop.
 // ---------------------------------------------------------------------------
 struct MixedTile {
     const char* base;  // tile start
@@ -43,11 +50,98 @@ struct MixedTile {
     int scale;
 };
 
+struct RawSlab {
+    uint4 w[4];
+};
+
+__device__ __forceinline__ void raw_load(const MixedTile& t, int64_t idx, RawSlab& r) {
+    switch (t.cls) {
+        case kFP64: {
+            const uint4* p = reinterpret_cast<const uint4*>(reinterpret_cast<const double*>(t.base) + idx);
+            r.w[0] = p[0];
+            r.w[1] = p[1];
+            r.w[2] = p[2];
+            r.w[3] = p[3];
+            break;
+        }
+        case kFP32: {
+            const uint4* p = reinterpret_cast<const uint4*>(reinterpret_cast<const float*>(t.base) + idx);
+            r.w[0] = p[0];
+            r.w[1] = p[1];
+            break;
+        }
+        case kFP16:
+        case kBF16:
+            r.w[0] = *reinterpret_cast<const uint4*>(reinterpret_cast<const uint16_t*>(t.base) + idx);
+            break;
+        default: {
+            const uint2 v = *reinterpret_cast<const uint2*>(reinterpret_cast<const uint8_t*>(t.base) + idx);
+            r.w[0].x = v.x;
+            r.w[0].y = v.y;
+            break;
+        }
+    }
+}
+
+// OCP e4m3 byte -> float (exact): normal numbers by exponent rebias, the
+// subnormals as m * 2^-9.
+__device__ __forceinline__ float fp8_to_float(uint32_t b) {
+    const uint32_t e = (b >> 3) & 15u, m = b & 7u;
+    const float a = e ? __uint_as_float(((e + 120u) << 23) | (m << 20)) : (float)m * 0x1p-9f;
+    return (b & 0x80u) ? -a : a;
+}
+
+__device__ __forceinline__ void raw_store(const RawSlab& r, int cls, double mul, double* dst) {
+    double v[8];
+    switch (cls) {
+        case kFP64: {
+            const uint32_t* w = reinterpret_cast<const uint32_t*>(r.w);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) v[i] = __hiloint2double((int)w[2 * i + 1], (int)w[2 * i]);
+            break;
+        }
+        case kFP32: {
+            const uint32_t* w = reinterpret_cast<const uint32_t*>(r.w);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) v[i] = (double)__uint_as_float(w[i]);
+            break;
+        }
+        case kFP16: {
+            const uint32_t* w = reinterpret_cast<const uint32_t*>(r.w);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const uint16_t h = (uint16_t)(w[i >> 1] >> (16 * (i & 1)));
+                v[i] = (double)(float)__builtin_bit_cast(_Float16, h);
+            }
+            break;
+        }
+        case kBF16: {
+            const uint32_t* w = reinterpret_cast<const uint32_t*>(r.w);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const uint32_t h = (w[i >> 1] >> (16 * (i & 1))) & 0xFFFFu;
+                v[i] = (double)__uint_as_float(h << 16);
+            }
+            break;
+        }
+        default: {
+            const uint32_t* w = reinterpret_cast<const uint32_t*>(r.w);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) v[i] = (double)fp8_to_float((w[i >> 2] >> (8 * (i & 3))) & 0xFFu);
+            break;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        *reinterpret_cast<d2*>(dst + 2 * i) = d2{v[2 * i] * mul, v[2 * i + 1] * mul};
+}
+
 template <class AOp, class BOp>
 __device__ __forceinline__ void mixed_mainloop(d4 (&acc)[kB / 32][kB / 32], const AOp& aop,
                                                const BOp& bop, int64_t nb, int64_t kbeg,
                                                int64_t kend, double* lds) {
     using T = MfmaTile<kB, kB>;
+    static_assert(kB * T::BK == 8 * kGemmThreads, "one 8-row run per thread per operand");
     if (kbeg >= kend) return;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -55,35 +149,23 @@ __device__ __forceinline__ void mixed_mainloop(d4 (&acc)[kB / 32][kB / 32], cons
     const int wm = wave & 1, wn = wave >> 1;
     double* As = lds;
     double* Bs = lds + 2 * T::BK * T::LDA;
-    int ecol[T::A_LOADS], erow[T::A_LOADS];
-#pragma unroll
-    for (int q = 0; q < T::A_LOADS; ++q) {
-        const int e = (q * kGemmThreads + tid) * 2;
-        ecol[q] = e / kB;
-        erow[q] = e % kB;
-    }
-    d2 ra[T::A_LOADS], rb[T::B_LOADS];
-    auto load2 = [&](const MixedTile& t, int64_t idx) -> d2 {
-        if (t.cls == kFP64) return *reinterpret_cast<const d2*>(reinterpret_cast<const double*>(t.base) + idx);
-        return d2{load_elem(t.base, idx, t.cls, t.scale), load_elem(t.base, idx + 1, t.cls, t.scale)};
-    };
+    const int col = tid >> 4, row0 = (tid & 15) * 8;
+    RawSlab ra, rb;
+    int acls, bcls;
+    double amul, bmul;
     auto gload = [&](int64_t kk) {
         int64_t ia, ib;
         const MixedTile ta = aop(kk, ia), tb = bop(kk, ib);
-#pragma unroll
-        for (int q = 0; q < T::A_LOADS; ++q) ra[q] = load2(ta, ia + (int64_t)ecol[q] * nb + erow[q]);
-#pragma unroll
-        for (int q = 0; q < T::B_LOADS; ++q) rb[q] = load2(tb, ib + (int64_t)ecol[q] * nb + erow[q]);
+        raw_load(ta, ia + (int64_t)col * nb + row0, ra);
+        raw_load(tb, ib + (int64_t)col * nb + row0, rb);
+        acls = ta.cls;
+        bcls = tb.cls;
+        amul = ldexp(1.0, ta.scale);
+        bmul = ldexp(1.0, tb.scale);
     };
     auto sstore = [&](int buf) {
-        double* as = As + buf * T::BK * T::LDA;
-        double* bs = Bs + buf * T::BK * T::LDB;
-#pragma unroll
-        for (int q = 0; q < T::A_LOADS; ++q)
-            *reinterpret_cast<d2*>(as + ecol[q] * T::LDA + erow[q]) = ra[q];
-#pragma unroll
-        for (int q = 0; q < T::B_LOADS; ++q)
-            *reinterpret_cast<d2*>(bs + ecol[q] * T::LDB + erow[q]) = rb[q];
+        raw_store(ra, acls, amul, As + buf * T::BK * T::LDA + col * T::LDA + row0);
+        raw_store(rb, bcls, bmul, Bs + buf * T::BK * T::LDB + col * T::LDB + row0);
     };
     gload(kbeg);
     sstore(0);
@@ -156,18 +238,26 @@ __device__ __forceinline__ void group_block(int64_t b, int T, bool diag, const i
 
 // FP64 group of column k: W[rt] -= sum_n Lh(k+rt, n) Lh(k, n)^T for rt in
 // the diagonal tile (lower blocks, when diag) and the listed row tiles.
+// splits > 1: split s covers K range [s*kchunk, (s+1)*kchunk) and writes its
+// 128 x 128 block to partial[(s * nblocks + b) * 128^2] (column-major).
 __global__ __launch_bounds__(kGemmThreads, 2) void mxp_gemm_f64_kernel(
     double* __restrict__ W, int Nt, int nb, int k, const int* __restrict__ rows, int nrows, int diag,
     const char* __restrict__ storage, const int64_t* __restrict__ toff,
-    const uint8_t* __restrict__ tcls, const int* __restrict__ tscl) {
+    const uint8_t* __restrict__ tcls, const int* __restrict__ tscl, int splits, int64_t kchunk,
+    double* __restrict__ partial) {
     using Tl = MfmaTile<kB, kB>;
     __shared__ double lds[Tl::LDS_DOUBLES];
     const int T = nb / kB;
-    const int64_t total = (diag ? (int64_t)T * (T + 1) / 2 : 0) + (int64_t)nrows * T * T;
-    const int64_t b = xcd_remap_m(blockIdx.x, total);
+    const int64_t nblocks = (diag ? (int64_t)T * (T + 1) / 2 : 0) + (int64_t)nrows * T * T;
+    const int64_t logical = xcd_remap_m(blockIdx.x, nblocks * splits);
+    const int split = (int)(logical / nblocks);
+    const int64_t b = logical - (int64_t)split * nblocks;
     int64_t rt;
     int br, bc;
     group_block(b, T, diag != 0, rows, rt, br, bc);
+    const int64_t K = (int64_t)k * nb;
+    const int64_t kbeg = (int64_t)split * kchunk;
+    const int64_t kend = kbeg + kchunk < K ? kbeg + kchunk : K;
     d4 acc[Tl::MI][Tl::NI];
 #pragma unroll
     for (int mi = 0; mi < Tl::MI; ++mi)
@@ -175,15 +265,50 @@ __global__ __launch_bounds__(kGemmThreads, 2) void mxp_gemm_f64_kernel(
         for (int ni = 0; ni < Tl::NI; ++ni) acc[mi][ni] = d4{0.0, 0.0, 0.0, 0.0};
     const StoredOp aop{storage, toff, tcls, tscl, Nt, nb, k + rt, (int64_t)br * kB};
     const StoredOp bop{storage, toff, tcls, tscl, Nt, nb, k, (int64_t)bc * kB};
-    mixed_mainloop(acc, aop, bop, nb, 0, (int64_t)k * nb, lds);
-    double* out = W + rt * (int64_t)nb * nb + (int64_t)bc * kB * nb + br * kB;
+    mixed_mainloop(acc, aop, bop, nb, kbeg, kend, lds);
+    double* out;
+    int64_t ldo;
+    if (splits == 1) {
+        out = W + rt * (int64_t)nb * nb + (int64_t)bc * kB * nb + br * kB;
+        ldo = nb;
+    } else {
+        out = partial + ((int64_t)split * nblocks + b) * kB * kB;
+        ldo = kB;
+    }
 #pragma unroll
     for (int mi = 0; mi < Tl::MI; ++mi)
 #pragma unroll
         for (int ni = 0; ni < Tl::NI; ++ni)
 #pragma unroll
-            for (int v = 0; v < 4; ++v)
-                out[(int64_t)acc_col<kB, kB>(ni, v) * nb + acc_row<kB, kB>(mi)] -= acc[mi][ni][v];
+            for (int v = 0; v < 4; ++v) {
+                double* p = out + (int64_t)acc_col<kB, kB>(ni, v) * ldo + acc_row<kB, kB>(mi);
+                if (splits == 1)
+                    *p -= acc[mi][ni][v];
+                else
+                    *p = acc[mi][ni][v];
+            }
+}
+
+// W block -= sum over splits of its partial blocks (fixed order).
+__global__ __launch_bounds__(256) void mxp_group_reduce_kernel(double* __restrict__ W, int nb,
+                                                               const int* __restrict__ rows,
+                                                               int diag, int64_t nblocks,
+                                                               int splits,
+                                                               const double* __restrict__ partial) {
+    const int64_t b = blockIdx.x;
+    const int T = nb / kB;
+    int64_t rt;
+    int br, bc;
+    group_block(b, T, diag != 0, rows, rt, br, bc);
+    double* out = W + rt * (int64_t)nb * nb + (int64_t)bc * kB * nb + br * kB;
+    for (int e = threadIdx.x * 2; e < kB * kB; e += 512) {
+        const int c = e / kB, r = e - c * kB;
+        d2 s = *reinterpret_cast<const d2*>(partial + b * kB * kB + e);
+        for (int sp = 1; sp < splits; ++sp)
+            s += *reinterpret_cast<const d2*>(partial + ((int64_t)sp * nblocks + b) * kB * kB + e);
+        d2* o = reinterpret_cast<d2*>(out + (int64_t)c * nb + r);
+        *o = *o - s;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -322,11 +447,21 @@ __global__ __launch_bounds__(kThreads) void tile_amax_kernel(const double* __res
     }
 }
 
+// One workgroup per 64 x 64 block of a new tile: round to the tile's
+// class with its scale into storage (column-major), then write the operand
+// copies: binary32 values column-major for FP32, and for FP16 / BF16 / FP8
+// the class's bits with the copy's own scale, transposed through LDS so the
+// copy is row-major (64 consecutive k per row and block).
+constexpr int kCB = 64;
+constexpr int kCPitch = kCB * 2 + 16;  // bytes per staged copy row
+
 __global__ __launch_bounds__(kThreads) void tile_cast_kernel(
     const double* __restrict__ W, int Nt, int nb, int k, const double* __restrict__ part,
     char* __restrict__ storage, const int64_t* __restrict__ toff, const uint8_t* __restrict__ tcls,
-    int* __restrict__ tscl, const int64_t* __restrict__ shoff) {
-    const int rt = blockIdx.y, strip = blockIdx.x;  // rt: tile k + 1 + rt of column k
+    int* __restrict__ tscl, const int64_t* __restrict__ shoff, int* __restrict__ cscl) {
+    __shared__ __attribute__((aligned(16))) uint8_t stage[3][kCB * kCPitch];
+    const int rt = blockIdx.z;  // tile k + 1 + rt of column k
+    const int r0 = blockIdx.x * kCB, c0 = blockIdx.y * kCB;
     const int64_t t = tile_off(Nt, k + 1 + rt, k);
     double amax = 0.0;
     for (int s = 0; s < kStrips; ++s) amax = fmax(amax, part[rt * kStrips + s]);
@@ -335,38 +470,275 @@ __global__ __launch_bounds__(kThreads) void tile_cast_kernel(
     // largest stored value (rounding is monotone): decides the copies' scales
     const double amax_h = ldexp(fabs(round_to_class(ldexp(amax, -e), c)), e);
     int ce[5];
-    float* copy[5];
+    char* copy[5];
 #pragma unroll
     for (int c2 = 1; c2 <= 4; ++c2) {
         const int64_t o = shoff[t * 4 + (c2 - 1)];
-        copy[c2] = (o >= 0 && !(c2 == kFP32 && c == kFP32)) ? reinterpret_cast<float*>(storage + o)
-                                                            : nullptr;
+        copy[c2] = (o >= 0 && !(c2 == kFP32 && c == kFP32)) ? storage + o : nullptr;
         ce[c2] = class_scale(amax_h, c2);
     }
-    if (strip == 0 && threadIdx.x == 0) tscl[t] = e;
-    const int64_t per = (int64_t)nb * nb / kStrips;
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+        tscl[t] = e;
+        for (int c2 = 1; c2 <= 4; ++c2) cscl[t * 4 + (c2 - 1)] = ce[c2];
+    }
     const double* src = W + (int64_t)(1 + rt) * nb * nb;
     void* dst = storage + toff[t];
-    for (int64_t i = strip * per + threadIdx.x; i < (strip + 1) * per; i += kThreads) {
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int j = 0; j < kCB / 4; ++j) {
+        const int cl = ty + 4 * j;
+        const int64_t i = (int64_t)(c0 + cl) * nb + r0 + tx;
         const double r = round_to_class(ldexp(src[i], -e), c);
         store_elem(dst, i, c, r);
         const double v = ldexp(r, e);  // the stored factor value
-#pragma unroll
-        for (int c2 = 1; c2 <= 4; ++c2)
-            if (copy[c2]) copy[c2][i] = (float)ldexp(round_to_class(ldexp(v, -ce[c2]), c2), ce[c2]);
+        if (copy[kFP32]) reinterpret_cast<float*>(copy[kFP32])[i] = (float)round_to_class(v, kFP32);
+        if (copy[kFP16]) {
+            const uint16_t b = enc_fp16(round_to_class(ldexp(v, -ce[kFP16]), kFP16));
+            *reinterpret_cast<uint16_t*>(&stage[0][tx * kCPitch + 2 * cl]) = b;
+        }
+        if (copy[kBF16]) {
+            const uint16_t b = enc_bf16(round_to_class(ldexp(v, -ce[kBF16]), kBF16));
+            *reinterpret_cast<uint16_t*>(&stage[1][tx * kCPitch + 2 * cl]) = b;
+        }
+        if (copy[kFP8])
+            stage[2][tx * kCPitch + cl] = enc_fp8(round_to_class(ldexp(v, -ce[kFP8]), kFP8));
     }
+    __syncthreads();
+    // row-major copies: row r0 + rr holds k = c0 .. c0 + 63 contiguously
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const int c2 = kFP16 + q;
+        if (!copy[c2]) continue;
+        const int eb = fmt_bytes(c2);
+        const int per_row = kCB * eb / 16;  // 16-byte chunks per row
+        for (int ch = threadIdx.x; ch < kCB * per_row; ch += kThreads) {
+            const int rr = ch / per_row, cc = ch - rr * per_row;
+            const uint4 v = *reinterpret_cast<const uint4*>(&stage[q][rr * kCPitch + cc * 16]);
+            *reinterpret_cast<uint4*>(copy[c2] + ((int64_t)(r0 + rr) * nb + c0) * eb + cc * 16) = v;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Narrow-format MFMA for the FP16, BF16 and FP8 groups. Operands are the
+// row-major copies: a 128-row slab of 128 bytes per row per stage (64 k of
+// FP16/BF16, 128 k of FP8) is staged through LDS; lane l of a wave takes
+// row l % 16 and 8 (16-bit) or 32 (FP8) consecutive k at 8 (l / 16) or
+// 32 (l / 16) — A and B use the same k order, which is all the MFMA needs.
+// v_mfma_f32_16x16x32_{f16,bf16} and v_mfma_scale_f32_16x16x128_f8f6f4
+// (unit scales) accumulate in FP32; lane l holds D[4(l/16) + v][l%16]
+// (checked on the device) and the blocks are computed as C^T = B A^T.
+// The per-tile copy scales 2^(e_a + e_b) are applied when the products of
+// one tile column n are folded into the FP32 accumulator.
+// ---------------------------------------------------------------------------
+typedef _Float16 h8v __attribute__((ext_vector_type(8)));
+typedef __bf16 b8v __attribute__((ext_vector_type(8)));
+typedef int i8v __attribute__((ext_vector_type(8)));
+
+constexpr int kNPitch = 128 + 16;  // bytes per LDS row (bank spread)
+
+struct NarrowOp {
+    const char* storage;
+    const int64_t* shoff;
+    const int* cscl;
+    int cls;
+    int64_t Nt, nb, row_tile, r0;
+    __device__ const uint8_t* rows(int64_t n, int eb) const {
+        const int64_t t = tile_off(Nt, row_tile, n);
+        return reinterpret_cast<const uint8_t*>(storage + shoff[t * 4 + (cls - 1)]) + r0 * nb * eb;
+    }
+    __device__ int scale(int64_t n) const { return cscl[tile_off(Nt, row_tile, n) * 4 + (cls - 1)]; }
+};
+
+typedef unsigned int u4v __attribute__((ext_vector_type(4)));
+struct Quad {
+    u4v v0, v1, v2, v3;
+};
+__device__ __forceinline__ void load_quad(const uint8_t* p, int64_t step, Quad& q) {
+    q.v0 = *reinterpret_cast<const u4v*>(p);
+    q.v1 = *reinterpret_cast<const u4v*>(p + step);
+    q.v2 = *reinterpret_cast<const u4v*>(p + 2 * step);
+    q.v3 = *reinterpret_cast<const u4v*>(p + 3 * step);
+}
+__device__ __forceinline__ void store_quad(uint8_t* p, int step, const Quad& q) {
+    *reinterpret_cast<u4v*>(p) = q.v0;
+    *reinterpret_cast<u4v*>(p + step) = q.v1;
+    *reinterpret_cast<u4v*>(p + 2 * step) = q.v2;
+    *reinterpret_cast<u4v*>(p + 3 * step) = q.v3;
+}
+
+template <int CLS>
+__global__ __launch_bounds__(kGemmThreads, 2) void mxp_gemm_narrow_kernel(
+    double* __restrict__ W, int Nt, int nb, int k, const int* __restrict__ rows, int nrows,
+    const char* __restrict__ storage, const int64_t* __restrict__ shoff,
+    const int* __restrict__ cscl) {
+    constexpr int EB = CLS == kFP8 ? 1 : 2;
+    constexpr int SK = 128 / EB;  // k per stage
+    __shared__ __attribute__((aligned(16))) uint8_t lds[2][2][kB * kNPitch];
+    const int T = nb / kB;
+    const int64_t total = (int64_t)nrows * T * T;
+    const int64_t b = xcd_remap_m(blockIdx.x, total);
+    int64_t rt;
+    int br, bc;
+    group_block(b, T, false, rows, rt, br, bc);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave & 1, wn = wave >> 1;
+    const int li = lane & 15, lg = lane >> 4;
+    const NarrowOp aop{storage, shoff, cscl, CLS, Nt, nb, k + rt, (int64_t)br * kB};
+    const NarrowOp bop{storage, shoff, cscl, CLS, Nt, nb, k, (int64_t)bc * kB};
+    const int spt = nb / SK;  // stages per tile column
+    const int ns = k * spt;
+    // each thread moves 4 x 16 bytes per operand per stage: rows tid / 8 +
+    // 32 q, byte column 16 (tid % 8) of the 128-byte stage row
+    const int lrow = tid >> 3, lcol = (tid & 7) * 16;
+    const int64_t gstep = (int64_t)32 * nb * EB;  // 32 rows further
+    const int64_t lofs = (int64_t)lrow * nb * EB + lcol;
+    Quad ra, rb;
+    f4 acc[4][4], part[4][4];
+#pragma unroll
+    for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 4; ++ni) {
+            acc[mi][ni] = f4{0.f, 0.f, 0.f, 0.f};
+            part[mi][ni] = f4{0.f, 0.f, 0.f, 0.f};
+        }
+    if (ns > 0) {
+        load_quad(aop.rows(0, EB) + lofs, gstep, ra);
+        load_quad(bop.rows(0, EB) + lofs, gstep, rb);
+        store_quad(&lds[0][0][lrow * kNPitch + lcol], 32 * kNPitch, ra);
+        store_quad(&lds[0][1][lrow * kNPitch + lcol], 32 * kNPitch, rb);
+        __syncthreads();
+        int buf = 0;
+        for (int g = 0; g < ns; ++g) {
+            const bool more = g + 1 < ns;
+            if (more) {
+                const int n1 = (g + 1) / spt, st1 = (g + 1) - n1 * spt;
+                const int64_t o = lofs + (int64_t)st1 * SK * EB;
+                load_quad(aop.rows(n1, EB) + o, gstep, ra);
+                load_quad(bop.rows(n1, EB) + o, gstep, rb);
+            }
+            const uint8_t* as = &lds[buf][0][(wm * 64 + li) * kNPitch];
+            const uint8_t* bs = &lds[buf][1][(wn * 64 + li) * kNPitch];
+            if constexpr (CLS == kFP8) {
+                i8v a[4], bq[4];
+#pragma unroll
+                for (int mi = 0; mi < 4; ++mi) {
+                    const u4v* p = reinterpret_cast<const u4v*>(as + mi * 16 * kNPitch + 32 * lg);
+                    const u4v x = p[0], y = p[1];
+                    a[mi] = i8v{(int)x.x, (int)x.y, (int)x.z, (int)x.w, (int)y.x, (int)y.y, (int)y.z, (int)y.w};
+                }
+#pragma unroll
+                for (int ni = 0; ni < 4; ++ni) {
+                    const u4v* p = reinterpret_cast<const u4v*>(bs + ni * 16 * kNPitch + 32 * lg);
+                    const u4v x = p[0], y = p[1];
+                    bq[ni] = i8v{(int)x.x, (int)x.y, (int)x.z, (int)x.w, (int)y.x, (int)y.y, (int)y.z, (int)y.w};
+                }
+#pragma unroll
+                for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+                    for (int ni = 0; ni < 4; ++ni)
+                        part[mi][ni] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
+                            bq[ni], a[mi], part[mi][ni], 0, 0, 0, 127, 0, 127);
+            } else {
+#pragma unroll
+                for (int ks = 0; ks < 2; ++ks) {
+                    u4v a[4], bq[4];
+#pragma unroll
+                    for (int mi = 0; mi < 4; ++mi)
+                        a[mi] = *reinterpret_cast<const u4v*>(as + mi * 16 * kNPitch + ks * 64 + 16 * lg);
+#pragma unroll
+                    for (int ni = 0; ni < 4; ++ni)
+                        bq[ni] = *reinterpret_cast<const u4v*>(bs + ni * 16 * kNPitch + ks * 64 + 16 * lg);
+#pragma unroll
+                    for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+                        for (int ni = 0; ni < 4; ++ni) {
+                            if constexpr (CLS == kFP16)
+                                part[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
+                                    __builtin_bit_cast(h8v, bq[ni]), __builtin_bit_cast(h8v, a[mi]),
+                                    part[mi][ni], 0, 0, 0);
+                            else
+                                part[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                    __builtin_bit_cast(b8v, bq[ni]), __builtin_bit_cast(b8v, a[mi]),
+                                    part[mi][ni], 0, 0, 0);
+                        }
+                }
+            }
+            if ((g + 1) % spt == 0) {  // tile column n done: fold with its scales
+                const int n = g / spt;
+                const float sc = ldexpf(1.0f, aop.scale(n) + bop.scale(n));
+#pragma unroll
+                for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+                    for (int ni = 0; ni < 4; ++ni) {
+                        acc[mi][ni] += part[mi][ni] * sc;
+                        part[mi][ni] = f4{0.f, 0.f, 0.f, 0.f};
+                    }
+            }
+            if (more) {
+                store_quad(&lds[buf ^ 1][0][lrow * kNPitch + lcol], 32 * kNPitch, ra);
+                store_quad(&lds[buf ^ 1][1][lrow * kNPitch + lcol], 32 * kNPitch, rb);
+            }
+            __syncthreads();
+            buf ^= 1;
+        }
+    }
+    double* out = W + rt * (int64_t)nb * nb + (int64_t)bc * kB * nb + br * kB;
+#pragma unroll
+    for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 4; ++ni)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = wm * (kB / 2) + mi * 16 + li;
+                const int col = wn * (kB / 2) + ni * 16 + 4 * lg + v;
+                out[(int64_t)col * nb + row] -= (double)acc[mi][ni][v];
+            }
 }
 
 }  // namespace
 
+// Split count of an FP64 group launch: the forward panel's time model
+// (rounds of 512 resident workgroups at the FP64 MFMA rate, plus the
+// partial blocks' traffic), each split keeping >= 1024 of K and the
+// partials within `cap` doubles.
+static int mxp_f64_splits(int64_t nblocks, int64_t K, size_t cap) {
+    int64_t smax = K / 1024;
+    if (smax > 16) smax = 16;
+    while (smax > 1 && (size_t)smax * nblocks * kB * kB > cap) --smax;
+    if (smax <= 1) return 1;
+    const double slot_flops = 78.6e12 / 512;
+    const double blk_bytes = (double)kB * kB * sizeof(double);
+    double best = 1e300;
+    int bests = 1;
+    for (int64_t s = 1; s <= smax; ++s) {
+        const double rounds = (double)((nblocks * s + 511) / 512);
+        double t = rounds * (2.0 * kB * kB * ((double)K / s)) / slot_flops;
+        if (s > 1) t += 3.0 * s * nblocks * blk_bytes / 5e12;
+        if (t < best * 0.97) {
+            best = t;
+            bests = (int)s;
+        }
+    }
+    return bests;
+}
+
 hipError_t launch_mxp_gemm_f64(hipStream_t s, double* W, int Nt, int nb, int k, const int* rows,
                                int nrows, bool diag, const char* storage, const int64_t* toff,
-                               const uint8_t* tcls, const int* tscl) {
+                               const uint8_t* tcls, const int* tscl, double* partial,
+                               size_t partial_cap) {
     const int64_t T = nb / kB;
     const int64_t total = (diag ? T * (T + 1) / 2 : 0) + (int64_t)nrows * T * T;
     if (total == 0 || k == 0) return hipSuccess;
-    hipLaunchKernelGGL(mxp_gemm_f64_kernel, dim3((unsigned)total), dim3(kGemmThreads), 0, s, W, Nt,
-                       nb, k, rows, nrows, diag ? 1 : 0, storage, toff, tcls, tscl);
+    const int64_t K = (int64_t)k * nb;
+    const int splits = mxp_f64_splits(total, K, partial_cap);
+    const int64_t kchunk = (((K + splits - 1) / splits + 15) / 16) * 16;
+    hipLaunchKernelGGL(mxp_gemm_f64_kernel, dim3((unsigned)(total * splits)), dim3(kGemmThreads), 0,
+                       s, W, Nt, nb, k, rows, nrows, diag ? 1 : 0, storage, toff, tcls, tscl, splits,
+                       kchunk, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || splits == 1) return e;
+    hipLaunchKernelGGL(mxp_group_reduce_kernel, dim3((unsigned)total), dim3(256), 0, s, W, nb, rows,
+                       diag ? 1 : 0, total, splits, partial);
     return hipGetLastError();
 }
 
@@ -380,17 +752,38 @@ hipError_t launch_mxp_gemm_f32(hipStream_t s, double* W, int Nt, int nb, int k, 
     return hipGetLastError();
 }
 
+hipError_t launch_mxp_gemm_narrow(hipStream_t s, double* W, int Nt, int nb, int k, const int* rows,
+                                  int nrows, int cls, const char* storage, const int64_t* shoff,
+                                  const int* cscl) {
+    const int64_t T = nb / kB;
+    const int64_t total = (int64_t)nrows * T * T;
+    if (total == 0 || k == 0) return hipSuccess;
+    const dim3 grid((unsigned)total), block(kGemmThreads);
+    if (cls == kFP16)
+        hipLaunchKernelGGL(mxp_gemm_narrow_kernel<kFP16>, grid, block, 0, s, W, Nt, nb, k, rows, nrows,
+                           storage, shoff, cscl);
+    else if (cls == kBF16)
+        hipLaunchKernelGGL(mxp_gemm_narrow_kernel<kBF16>, grid, block, 0, s, W, Nt, nb, k, rows, nrows,
+                           storage, shoff, cscl);
+    else if (cls == kFP8)
+        hipLaunchKernelGGL(mxp_gemm_narrow_kernel<kFP8>, grid, block, 0, s, W, Nt, nb, k, rows, nrows,
+                           storage, shoff, cscl);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
 hipError_t launch_mxp_finalize(hipStream_t s, const double* W, int Nt, int nb, int k, double* part,
                                char* storage, const int64_t* toff, const uint8_t* tcls, int* tscl,
-                               const int64_t* shoff) {
+                               const int64_t* shoff, int* cscl) {
     const int rows = Nt - k - 1;
     if (rows <= 0) return hipSuccess;
     hipLaunchKernelGGL(tile_amax_kernel, dim3(kStrips, rows), dim3(kThreads), 0, s,
                        W + (int64_t)nb * nb, nb, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(tile_cast_kernel, dim3(kStrips, rows), dim3(kThreads), 0, s, W, Nt, nb, k,
-                       part, storage, toff, tcls, tscl, shoff);
+    hipLaunchKernelGGL(tile_cast_kernel, dim3(nb / kCB, nb / kCB, rows), dim3(kThreads), 0, s, W, Nt,
+                       nb, k, part, storage, toff, tcls, tscl, shoff, cscl);
     return hipGetLastError();
 }
 

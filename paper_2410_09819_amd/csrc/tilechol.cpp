@@ -123,16 +123,19 @@ tc_status check_ws(tc_ctx* ctx, int64_t n, int nb) {
 }
 
 // Storage plan of a mixed-precision factor. Tiles are stored in their class
-// in packed order; then come the binary32 operand copies Q_c(Lh_t) for every
-// tile t and low class c that the static schedule multiplies it in (as the
-// A operand of tile (m, k), class c = class(m, k), n < k < m, or as the B
-// operand of the tiles (m', m), m' > m); then the device tables.
+// in packed order; then come the operand copies Q_c(Lh_t) for every tile t
+// and low class c that the static schedule multiplies it in (as the A
+// operand of tile (m, k), class c = class(m, k), n < k < m, or as the B
+// operand of the tiles (m', m), m' > m): binary32 values, column-major, for
+// FP32; the class's own bits with a per-copy power-of-two scale, row-major
+// (k contiguous, the MFMA operand order), for FP16, BF16 and FP8. Then the
+// device tables.
 struct Plan {
     int Nt = 0, nb = 0;
     int64_t ntiles = 0;
     std::vector<uint8_t> cls;
     std::vector<int64_t> toff, shoff;  // shoff[t * 4 + c - 1], -1 if absent
-    size_t tab_toff = 0, tab_shoff = 0, tab_tscl = 0, tab_tcls = 0, total = 0;
+    size_t tab_toff = 0, tab_shoff = 0, tab_tscl = 0, tab_tcls = 0, tab_cscl = 0, total = 0;
     bool mixed = false;
 };
 
@@ -182,7 +185,7 @@ bool make_plan(int64_t n, int nb, const uint8_t* map, Plan& P) {
                     P.shoff[t * 4 + c - 1] = P.toff[t];  // the stored tile is the copy
                 } else {
                     P.shoff[t * 4 + c - 1] = (int64_t)off;
-                    off += align_up(tb * sizeof(float));
+                    off += align_up(tb * (c == TC_FP32 ? sizeof(float) : (size_t)tc::fmt_bytes(c)));
                 }
             }
         }
@@ -195,6 +198,8 @@ bool make_plan(int64_t n, int nb, const uint8_t* map, Plan& P) {
     off += align_up(P.ntiles * sizeof(int));
     P.tab_tcls = off;
     off += align_up(P.ntiles);
+    P.tab_cscl = off;  // scale exponents of the operand copies, [t * 4 + c - 1]
+    off += align_up(P.ntiles * 4 * sizeof(int));
     P.total = off;
     return true;
 }
@@ -538,11 +543,13 @@ tc_status factorize_mixed(tc_ctx* ctx, int64_t n, int nb, const double* A, const
     double* part = reinterpret_cast<double*>(ctx->ws + Ly.small);
     double* W = reinterpret_cast<double*>(ctx->ws + Ly.panel);
     int* d_lists = reinterpret_cast<int*>(ctx->ws + Ly.lists);
+    const size_t big_cap = Ly.small - Ly.big;
     const int64_t nb2 = (int64_t)nb * nb;
     int64_t* d_toff = reinterpret_cast<int64_t*>(storage + P.tab_toff);
     int64_t* d_shoff = reinterpret_cast<int64_t*>(storage + P.tab_shoff);
     int* d_tscl = reinterpret_cast<int*>(storage + P.tab_tscl);
     uint8_t* d_tcls = reinterpret_cast<uint8_t*>(storage + P.tab_tcls);
+    int* d_cscl = reinterpret_cast<int*>(storage + P.tab_cscl);
 
     // row lists: for column k and class c, rows r >= 1 (tile k + r) of that class
     std::vector<int> lists((size_t)5 * Nt * Nt, 0);
@@ -570,6 +577,9 @@ tc_status factorize_mixed(tc_ctx* ctx, int64_t n, int nb, const double* A, const
     TC_HIP(hipMemcpyAsync(d_tcls, P.cls.data(), P.cls.size(), hipMemcpyHostToDevice, ctx->stream));
     TC_HIP(hipMemcpyAsync(d_tscl, zeros.data(), zeros.size() * sizeof(int), hipMemcpyHostToDevice,
                           ctx->stream));
+    std::vector<int> zeros4((size_t)P.ntiles * 4, 0);
+    TC_HIP(hipMemcpyAsync(d_cscl, zeros4.data(), zeros4.size() * sizeof(int), hipMemcpyHostToDevice,
+                          ctx->stream));
     TC_HIP(tc::launch_zero_info(ctx->stream, d_info));
     for (int k = 0; k < Nt; ++k) {
         TC_HIP(hipMemcpyAsync(W, A + tc::tile_off(Nt, k, k) * nb2, (size_t)(Nt - k) * nb2 * sizeof(double),
@@ -577,13 +587,18 @@ tc_status factorize_mixed(tc_ctx* ctx, int64_t n, int nb, const double* A, const
         if (k > 0) {
             const int* l64 = d_lists + ((size_t)k * 5 + TC_FP64) * Nt;
             TC_HIP(tc::launch_mxp_gemm_f64(ctx->stream, W, Nt, nb, k, l64, lcount[(size_t)k * 5 + TC_FP64],
-                                           true, storage, d_toff, d_tcls, d_tscl));
+                                           true, storage, d_toff, d_tcls, d_tscl, big,
+                                           big_cap / sizeof(double)));
             for (int c = 1; c <= 4; ++c) {
                 const int cnt = lcount[(size_t)k * 5 + c];
                 if (!cnt) continue;
-                TC_HIP(tc::launch_mxp_gemm_f32(ctx->stream, W, Nt, nb, k,
-                                               d_lists + ((size_t)k * 5 + c) * Nt, cnt, c, storage,
-                                               d_shoff));
+                const int* lc = d_lists + ((size_t)k * 5 + c) * Nt;
+                if (c == TC_FP32)
+                    TC_HIP(tc::launch_mxp_gemm_f32(ctx->stream, W, Nt, nb, k, lc, cnt, c, storage,
+                                                   d_shoff));
+                else
+                    TC_HIP(tc::launch_mxp_gemm_narrow(ctx->stream, W, Nt, nb, k, lc, cnt, c, storage,
+                                                      d_shoff, d_cscl));
             }
         }
         if (tc_status s = potrf_rec(ctx, W, nb, 0, nb, (int64_t)k * nb, d_info, big)) return s;
@@ -591,7 +606,7 @@ tc_status factorize_mixed(tc_ctx* ctx, int64_t n, int nb, const double* A, const
         TC_HIP(hipMemcpyAsync(storage + P.toff[tc::tile_off(Nt, k, k)], W, nb2 * sizeof(double),
                               hipMemcpyDeviceToDevice, ctx->stream));
         TC_HIP(tc::launch_mxp_finalize(ctx->stream, W, Nt, nb, k, part, storage, d_toff, d_tcls, d_tscl,
-                                       d_shoff));
+                                       d_shoff, d_cscl));
     }
     TC_HIP(hipEventRecord(ctx->ev1, ctx->stream));
     int info = 0;

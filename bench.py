@@ -14,8 +14,9 @@ Prints one JSON line. `roofline` is the dominant kernel (the panel GEMM)
 timed with HIP events on the library's compute stream: algorithmic flops of
 all its launches / summed launch time, against the FP64 matrix peak.
 `cpu_baseline` times the CPU oracle on a bounded sample of the same workload
-(the leading 4096 x 4096 principal block, same tile size). `mxp_vs_fp64` and
-`loglik_grad` are the mixed-precision and likelihood-gradient legs.
+(the leading 4096 x 4096 principal block, same tile size). `mxp_vs_fp64`,
+`loglik_grad` and `ooc_vs_in_core` are the mixed-precision, likelihood-gradient
+and out-of-core legs.
 """
 from __future__ import annotations
 
@@ -184,6 +185,66 @@ def grad_leg(tc, si, dev):
     return out
 
 
+def ooc_leg(tc, si, dev, n=122880, nb=2048, caches_gib=(40, 16)):
+    """Out-of-core FP64 factorization from pinned host memory against the
+    in-core factorization of the same matrix. The ooc workload's parameters
+    (nu=1, range=0.05, nugget=1e-4) at n=122880, nb=2048: 57.2 GiB of packed
+    lower tiles in one pinned host buffer (the largest size whose pinned
+    allocation succeeds on the test machines). Two HBM tile caches: 40 GiB
+    holds the peak working set (~29 GiB: every tile crosses the link once
+    each way) and 16 GiB does not (operand tiles are evicted and reloaded).
+    Each run starts from a fresh copy of A in the pinned buffer (in place)."""
+    import numpy as np
+    import torch
+    w = si.WORKLOADS["ooc"]
+    theta = (w["sigma2"], w["range"], w["nu"], w["nugget"])
+    pts = torch.from_numpy(si.points(n, seed=w["seed"])).to(dev)
+    ctx = tc.Context(n, nb, timed=True)
+    A, _, _ = tc.matern_tiles(ctx, pts, theta, nb, norms=False)
+    Ah = torch.empty(A.numel(), dtype=torch.float64, pin_memory=True)
+    storage = torch.empty_like(A)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    F = tc.factorize(ctx, A, n, nb, storage=storage)
+    torch.cuda.synchronize()
+    t_in = time.perf_counter() - t0
+    F.close()
+    flops = n ** 3 / 3.0
+    Nt = n // nb
+    nb2 = nb * nb
+    out = {"workload": "ooc FP64 tile Cholesky, n=%d nb=%d, Matern nu=%g range=%g nugget=%g, "
+                       "pinned host tiles" % (n, nb, theta[2], theta[1], theta[3]),
+           "in_core_s": t_in, "in_core_tflops": flops / t_in / 1e12, "runs": []}
+    for gib in caches_gib:
+        Ah.copy_(A)
+        cache = torch.empty(gib << 30, dtype=torch.uint8, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = tc.factorize_ooc(ctx, Ah, n, nb, cache)
+        t_ooc = time.perf_counter() - t0
+        del cache
+        torch.cuda.empty_cache()
+        # sampled agreement with the in-core factor
+        worst = 0.0
+        for (i, j) in [(0, 0), (Nt - 1, 0), (Nt // 2, Nt // 3), (Nt - 1, Nt - 2), (Nt - 1, Nt - 1)]:
+            t = tc.tile_offset(Nt, i, j)
+            a = storage[t * nb2:(t + 1) * nb2].view(nb, nb).t().cpu().numpy()
+            b = Ah[t * nb2:(t + 1) * nb2].view(nb, nb).t().numpy()
+            if i == j:
+                a, b = np.tril(a), np.tril(b)
+            worst = max(worst, float(np.abs(a - b).max() / np.abs(a).max()))
+        out["runs"].append({
+            "cache_gib": gib, "cache_slots": st["cache_slots"], "ooc_s": t_ooc,
+            "ooc_tflops": flops / t_ooc / 1e12, "ooc_over_in_core": t_ooc / t_in,
+            "bytes_h2d": st["bytes_h2d"], "bytes_d2h": st["bytes_d2h"],
+            "h2d_gbps": st["bytes_h2d"] / t_ooc / 1e9, "d2h_gbps": st["bytes_d2h"] / t_ooc / 1e9,
+            "tiles_reloaded": st["tiles_reloaded"], "evictions": st["evictions"],
+            "chunks": st["chunks"], "max_rel_diff_sampled_tiles": worst})
+    del A, storage, Ah
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -197,6 +258,8 @@ def main():
                     help="only the mixed-precision comparison (for profiling)")
     ap.add_argument("--grad-only", action="store_true",
                     help="only the likelihood-gradient leg (for profiling)")
+    ap.add_argument("--no-ooc", action="store_true", help="skip the out-of-core leg")
+    ap.add_argument("--ooc-only", action="store_true", help="only the out-of-core leg")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the tile Cholesky here runs on a single MI355X "
@@ -213,8 +276,13 @@ def main():
         from paper_2410_09819_amd import build
         build.build()
     dev = torch.device("cuda", 0)
-    if args.mxp_only or args.grad_only:
-        res = mxp_comparison(tc, si, dev) if args.mxp_only else grad_leg(tc, si, dev)
+    if args.mxp_only or args.grad_only or args.ooc_only:
+        if args.mxp_only:
+            res = mxp_comparison(tc, si, dev)
+        elif args.grad_only:
+            res = grad_leg(tc, si, dev)
+        else:
+            res = ooc_leg(tc, si, dev)
         print(json.dumps(res), flush=True)
         return
     w = si.WORKLOADS[args.workload]
@@ -278,7 +346,7 @@ def main():
         "factor_tflops": flops / (fact_ms / args.steps * 1e-3) / 1e12,
         "logdet": ld,
         "roofline": {
-            "kernel": "panel_update_kernel (FP64 MFMA panel GEMM+SYRK)",
+            "kernel": "panel_update_kernel<false> (FP64 MFMA panel GEMM+SYRK, bulk of each column)",
             "bound": "mfma",
             "achieved": achieved,
             "peak": FP64_PEAK_TFLOPS,
@@ -296,6 +364,7 @@ def main():
     torch.cuda.empty_cache()
     out["mxp_vs_fp64"] = None if args.no_mxp else mxp_comparison(tc, si, dev)
     out["loglik_grad"] = None if args.no_grad else grad_leg(tc, si, dev)
+    out["ooc_vs_in_core"] = None if args.no_ooc else ooc_leg(tc, si, dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)

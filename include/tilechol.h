@@ -75,9 +75,11 @@ typedef struct {
 
 typedef struct {
     double ms_total;        /* factorization wall time, HIP events on the compute stream */
-    double ms_gemm;         /* summed duration of the panel GEMM/SYRK launches (if timed) */
+    double ms_gemm;         /* summed duration of the bulk panel GEMM/SYRK launches (if timed);
+                               in the FP64 factorization these are the updates of column k+1
+                               from tile columns < k that run ahead of column k's POTRF/TRSM */
     double gemm_flops;      /* algorithmic flops of those launches */
-    int32_t gemm_launches;  /* number of panel GEMM/SYRK launches */
+    int32_t gemm_launches;  /* number of those launches */
     int32_t info;           /* same as the positive return value, or 0 */
     double flops_total;     /* n^3/3, the count the throughput metric uses */
     double class_flops[5];  /* panel-update flops executed per class (tc_prec order) */

@@ -47,16 +47,19 @@ hipError_t launch_tile_norms(hipStream_t s, int64_t ntiles, int strips, const do
 int matern_strips(int nb);
 
 // Panel update for column k (gemm_f64.hip):
-//   C[k.., k] -= L[k.., 0:k] L[k, 0:k]^T, lower blocks only in the diagonal
-// tile. splits > 1 writes partial sums to `partial`; launch_panel_reduce
-// then subtracts their sum (no-op for splits == 1).
-hipError_t launch_panel_update(hipStream_t s, double* L, int Nt, int nb, int k, int splits,
-                               double* partial);
+//   C[k.., k] -= L[k.., nbeg:nend] L[k, nbeg:nend]^T (tile columns), lower
+// blocks only in the diagonal tile. splits > 1 writes partial sums to
+// `partial`; launch_panel_reduce then subtracts their sum (no-op for
+// splits == 1). `tail` selects the kernel instance used for the rank-nb
+// updates of the lookahead schedule (same code, separate trace name).
+hipError_t launch_panel_update(hipStream_t s, double* L, int Nt, int nb, int k, int nbeg, int nend,
+                               int splits, double* partial, bool tail);
 hipError_t launch_panel_reduce(hipStream_t s, double* L, int Nt, int nb, int k, int splits,
                                const double* partial);
 // Number of workgroups of one panel launch (before split-K).
 int64_t panel_blocks(int Nt, int nb, int k);
-int panel_splits(int Nt, int nb, int k);
+// Split count for column k's update over ncols tile columns.
+int panel_splits(int Nt, int nb, int k, int ncols);
 
 // In-tile update for the recursive POTRF (column-major sub-blocks, ld):
 //   C (m x m, lower blocks) -= A A^T, A is m x kdim.

@@ -56,9 +56,12 @@ struct PanelA {
     }
 };
 
+// TAIL only separates the rank-nb launches of the lookahead schedule (K =
+// one tile column) from the bulk launches in kernel traces.
+template <bool TAIL>
 __global__ __launch_bounds__(kGemmThreads, 2) void panel_update_kernel(
-    double* __restrict__ L, int Nt, int nb, int k, int splits, int64_t nblocks, int64_t kchunk,
-    double* __restrict__ partial) {
+    double* __restrict__ L, int Nt, int nb, int k, int nbeg, int nend, int splits, int64_t nblocks,
+    int64_t kchunk, double* __restrict__ partial) {
     using Tl = MfmaTile<kPanelBM, kPanelBM>;
     __shared__ double lds[Tl::LDS_DOUBLES];
     const int64_t logical = xcd_remap(blockIdx.x, nblocks * splits);
@@ -72,9 +75,10 @@ __global__ __launch_bounds__(kGemmThreads, 2) void panel_update_kernel(
     const int64_t r0 = (gb % T) * kPanelBM;       // first row inside that tile
     const int64_t nb2 = (int64_t)nb * nb;
 
-    const int64_t Ktot = (int64_t)k * nb;
-    const int64_t kbeg = (int64_t)split * kchunk;
-    const int64_t kend = kbeg + kchunk < Ktot ? kbeg + kchunk : Ktot;
+    // K range: tile columns [nbeg, nend), as absolute column indices of row k
+    const int64_t Kend = (int64_t)nend * nb;
+    const int64_t kbeg = (int64_t)nbeg * nb + (int64_t)split * kchunk;
+    const int64_t kend = kbeg + kchunk < Kend ? kbeg + kchunk : Kend;
 
     d4 acc[Tl::MI][Tl::NI];
 #pragma unroll
@@ -212,9 +216,9 @@ int64_t panel_blocks(int Nt, int nb, int k) {
 // (2 per CU) times one workgroup's K/S share at the FP64 MFMA rate, plus
 // writing and re-reading the partial sums at HBM speed; fewer splits win
 // unless clearly faster.
-int panel_splits(int Nt, int nb, int k) {
+int panel_splits(int Nt, int nb, int k, int ncols) {
     const int64_t W = panel_blocks(Nt, nb, k);
-    const int64_t K = (int64_t)k * nb;
+    const int64_t K = (int64_t)ncols * nb;
     const double panel_bytes = (double)(Nt - k) * nb * nb * sizeof(double);
     int64_t smax = K / 512;
     if (smax > 32) smax = 32;
@@ -236,13 +240,18 @@ int panel_splits(int Nt, int nb, int k) {
     return bests;
 }
 
-hipError_t launch_panel_update(hipStream_t s, double* L, int Nt, int nb, int k, int splits,
-                               double* partial) {
+hipError_t launch_panel_update(hipStream_t s, double* L, int Nt, int nb, int k, int nbeg, int nend,
+                               int splits, double* partial, bool tail) {
     const int64_t W = panel_blocks(Nt, nb, k);
-    const int64_t K = (int64_t)k * nb;
+    const int64_t K = (int64_t)(nend - nbeg) * nb;
+    if (K <= 0) return hipSuccess;
     const int64_t kchunk = (((K + splits - 1) / splits + 15) / 16) * 16;  // covers K
-    hipLaunchKernelGGL(panel_update_kernel, dim3((unsigned)(W * splits)), dim3(kGemmThreads), 0, s,
-                       L, Nt, nb, k, splits, W, kchunk, partial);
+    if (tail)
+        hipLaunchKernelGGL(panel_update_kernel<true>, dim3((unsigned)(W * splits)), dim3(kGemmThreads),
+                           0, s, L, Nt, nb, k, nbeg, nend, splits, W, kchunk, partial);
+    else
+        hipLaunchKernelGGL(panel_update_kernel<false>, dim3((unsigned)(W * splits)), dim3(kGemmThreads),
+                           0, s, L, Nt, nb, k, nbeg, nend, splits, W, kchunk, partial);
     return hipGetLastError();
 }
 

@@ -19,6 +19,11 @@ struct tc_ctx {
     uint32_t flags = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     std::vector<hipEvent_t> gemm_ev;
+    // two more compute streams (default priority) for independent class
+    // groups of a mixed-precision column, and the events that order them
+    hipStream_t aux[2] = {nullptr, nullptr};
+    hipEvent_t aux_ev[3] = {nullptr, nullptr, nullptr};
+    std::vector<hipEvent_t> la_ev;  // lookahead schedule events
     // out-of-core resources, created on first use
     hipStream_t h2d = nullptr, d2h = nullptr;
     void* pinned = nullptr;
@@ -51,7 +56,7 @@ extern thread_local std::string g_err;
 inline size_t align_up(size_t x) { return (x + 255) / 256 * 256; }
 
 struct Layout {
-    size_t info, big, small, panel, lists, ir, total;
+    size_t info, big, potrf, small, panel, lists, ir, total;
 };
 
 Layout layout(int64_t n, int nb, int nrhs = 16);
@@ -61,6 +66,8 @@ tc_status check_ws(tc_ctx* ctx, int64_t n, int nb);
 // Create the out-of-core streams and a pinned staging buffer of at least
 // `bytes` bytes in the context (once).
 tc_status ctx_ooc_resources(tc_ctx* ctx, size_t bytes);
+// Create the auxiliary compute streams and their events in the context (once).
+tc_status ctx_aux_streams(tc_ctx* ctx);
 // POTRF of the s x s block at offset o of a diagonal tile (leading dim nb),
 // recursive halving down to 128 x 128 leaves; failures set *info.
 tc_status potrf_rec(tc_ctx* ctx, double* T, int nb, int o, int s, int64_t col0, int* info,

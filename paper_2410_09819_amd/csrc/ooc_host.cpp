@@ -93,7 +93,8 @@ extern "C" tc_status tc_factorize_ooc(tc_ctx* ctx, int64_t n, int32_t nb, const 
     const Layout Ly = layout(n, nb);
     int* d_info = reinterpret_cast<int*>(ctx->ws + Ly.info);
     double* big = reinterpret_cast<double*>(ctx->ws + Ly.big);
-    const size_t big_cap = Ly.small - Ly.big;
+    const size_t big_cap = Ly.potrf - Ly.big;
+    double* pot = reinterpret_cast<double*>(ctx->ws + Ly.potrf);
     double* Wb[2] = {reinterpret_cast<double*>(ctx->ws + Ly.panel),
                      reinterpret_cast<double*>(ctx->ws + Ly.panel) + (size_t)Nt * nb2};
     // pointer tables: a ring in device workspace, staged through pinned host memory
@@ -225,7 +226,7 @@ extern "C" tc_status tc_factorize_ooc(tc_ctx* ctx, int64_t n, int32_t nb, const 
                 st.chunks++;
             }
         }
-        if (tc_status s = potrf_rec(ctx, W, nb, 0, nb, (int64_t)k * nb, d_info, big)) return s;
+        if (tc_status s = potrf_rec(ctx, W, nb, 0, nb, (int64_t)k * nb, d_info, pot)) return s;
         if (rows > 1) TC_HIP(tc::launch_trsm(cs, W + nb2, W, nb, (int64_t)(rows - 1) * nb, nb));
         // new off-diagonal tiles into free slots (they are used last in the next column)
         int cached_new = 0;

@@ -39,20 +39,32 @@ tc_status fail(tc_status s, const std::string& msg) {
 
 // Workspace regions (all carved from the caller's buffer):
 //   info   : one int (failure flag)
-//   big    : split-K partial sums of the panel and in-tile updates, and the
+//   big    : split-K partial sums of the panel updates and the
 //            backward-solve partial sums (used one at a time, stream-ordered)
+//   potrf  : split-K partial sums of the in-tile updates of the recursive
+//            POTRF (its own region: POTRF runs concurrently with panel
+//            updates under the lookahead schedule)
 //   small  : Matern strip sums of squares, log-determinant partials, amax
 //            partials of the mixed-precision finalize, column norms
-//   panel  : binary64 working column of the mixed-precision factorization
+//   panel  : binary64 working columns (mixed precision, out of core)
 //   lists  : row-tile lists per column and class (mixed precision)
 //   ir     : refinement vectors (b, r) and residual partial sums
 size_t big_bytes(int64_t n, int nb) {
     const int Nt = (int)(n / nb);
     size_t mx = 0;
     for (int k = 1; k < Nt; ++k) {
-        const int s = tc::panel_splits(Nt, nb, k);
-        if (s > 1) mx = std::max(mx, (size_t)s * (size_t)(Nt - k) * nb * nb * sizeof(double));
+        for (int nc = k - 1; nc <= k; ++nc) {  // lookahead bulk (k-1 columns) or full (k)
+            if (nc <= 0) continue;
+            const int s = tc::panel_splits(Nt, nb, k, nc);
+            if (s > 1) mx = std::max(mx, (size_t)s * (size_t)(Nt - k) * nb * nb * sizeof(double));
+        }
     }
+    mx = std::max(mx, (size_t)64 * nb * 16 * sizeof(double));  // backward-solve partials (<= 64 splits)
+    return mx;
+}
+
+size_t potrf_bytes(int nb) {
+    size_t mx = 256;
     // in-tile recursion (sizes are multiples of 128 below nb)
     for (int m = 128; m < nb; m += 128) {
         for (int kd = 128; kd < nb; kd += 128) {
@@ -60,7 +72,6 @@ size_t big_bytes(int64_t n, int nb) {
             if (s > 1) mx = std::max(mx, (size_t)s * m * m * sizeof(double));
         }
     }
-    mx = std::max(mx, (size_t)64 * nb * 16 * sizeof(double));  // backward-solve partials (<= 64 splits)
     return mx;
 }
 
@@ -71,7 +82,8 @@ Layout layout(int64_t n, int nb, int nrhs) {
     Layout L;
     L.info = 0;
     L.big = align_up(sizeof(int) * 64);
-    L.small = L.big + align_up(big_bytes(n, nb));
+    L.potrf = L.big + align_up(big_bytes(n, nb));
+    L.small = L.potrf + align_up(potrf_bytes(nb));
     // Matern strip sums; three per strip for the gradient contraction
     size_t small = std::max<size_t>((size_t)3 * ntiles * tc::matern_strips(nb) + 8, (size_t)Nt * 16);
     small = std::max<size_t>(small, (size_t)2 * nrhs * tc::colnorm_blocks());
@@ -100,6 +112,14 @@ tc_status ctx_ooc_resources(tc_ctx* ctx, size_t bytes) {
         TC_HIP(hipHostMalloc(&ctx->pinned, bytes, hipHostMallocDefault));
         ctx->pinned_bytes = bytes;
     }
+    return TC_OK;
+}
+
+tc_status ctx_aux_streams(tc_ctx* ctx) {
+    for (int i = 0; i < 2; ++i)
+        if (!ctx->aux[i]) TC_HIP(hipStreamCreateWithFlags(&ctx->aux[i], hipStreamNonBlocking));
+    for (int i = 0; i < 3; ++i)
+        if (!ctx->aux_ev[i]) TC_HIP(hipEventCreateWithFlags(&ctx->aux_ev[i], hipEventDisableTiming));
     return TC_OK;
 }
 
@@ -359,6 +379,7 @@ tc_status tc_ctx_destroy(tc_ctx* ctx) {
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
     for (hipEvent_t e : ctx->gemm_ev) (void)hipEventDestroy(e);
+    for (hipEvent_t e : ctx->la_ev) (void)hipEventDestroy(e);
     if (ctx->h2d) {
         (void)hipStreamSynchronize(ctx->h2d);
         (void)hipStreamDestroy(ctx->h2d);
@@ -368,6 +389,13 @@ tc_status tc_ctx_destroy(tc_ctx* ctx) {
         (void)hipStreamDestroy(ctx->d2h);
     }
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+    for (int i = 0; i < 2; ++i)
+        if (ctx->aux[i]) {
+            (void)hipStreamSynchronize(ctx->aux[i]);
+            (void)hipStreamDestroy(ctx->aux[i]);
+        }
+    for (int i = 0; i < 3; ++i)
+        if (ctx->aux_ev[i]) (void)hipEventDestroy(ctx->aux_ev[i]);
     delete ctx;
     return TC_OK;
 }
@@ -462,35 +490,64 @@ tc_status factorize_fp64(tc_ctx* ctx, int64_t n, int nb, const double* A, double
     const Layout Ly = layout(n, nb);
     int* d_info = reinterpret_cast<int*>(ctx->ws + Ly.info);
     double* big = reinterpret_cast<double*>(ctx->ws + Ly.big);
+    double* pot = reinterpret_cast<double*>(ctx->ws + Ly.potrf);
     const int64_t nb2 = (int64_t)nb * nb;
     const bool timed = (ctx->flags & 1u) != 0;
+    if (tc_status s = ctx_aux_streams(ctx)) return s;
     while (timed && ctx->gemm_ev.size() < (size_t)2 * Nt) {
         hipEvent_t e;
         TC_HIP(hipEventCreate(&e));
         ctx->gemm_ev.push_back(e);
     }
-    TC_HIP(hipEventRecord(ctx->ev0, ctx->stream));
+    while (ctx->la_ev.size() < (size_t)2 * Nt + 1) {
+        hipEvent_t e;
+        TC_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        ctx->la_ev.push_back(e);
+    }
+    // Lookahead schedule on two streams (same column order as Algorithm 1):
+    //   bulk (aux[0]):   P1(k+1) = column k+1 updated from tile columns [0, k)
+    //                    once TRSM(k-1) is done -- concurrent with POTRF(k)
+    //                    and TRSM(k);
+    //   main (stream):   P2(k) = column k updated from tile column k-1 (after
+    //                    P1(k) and TRSM(k-1)), POTRF(k), TRSM(k).
+    // ev_t[k]: TRSM(k) done (main); ev_p[k]: P1(k) done (bulk).
+    hipStream_t sm = ctx->stream, sb = ctx->aux[0];
+    hipEvent_t* ev_t = ctx->la_ev.data();
+    hipEvent_t* ev_p = ctx->la_ev.data() + Nt;
+    hipEvent_t ev_go = ctx->la_ev[2 * Nt];
+    TC_HIP(hipEventRecord(ctx->ev0, sm));
     if ((const void*)L != (const void*)A)
-        TC_HIP(hipMemcpyAsync(L, A, need, hipMemcpyDeviceToDevice, ctx->stream));
-    TC_HIP(tc::launch_zero_info(ctx->stream, d_info));
-    double gemm_flops = 0.0;
+        TC_HIP(hipMemcpyAsync(L, A, need, hipMemcpyDeviceToDevice, sm));
+    TC_HIP(tc::launch_zero_info(sm, d_info));
+    TC_HIP(hipEventRecord(ev_go, sm));
+    TC_HIP(hipStreamWaitEvent(sb, ev_go, 0));
+    double gemm_flops = 0.0, tail_flops = 0.0;
     int launches = 0;
     for (int k = 0; k < Nt; ++k) {
-        if (k > 0) {
-            const int sp = tc::panel_splits(Nt, nb, k);
-            if (timed) TC_HIP(hipEventRecord(ctx->gemm_ev[2 * launches], ctx->stream));
-            TC_HIP(tc::launch_panel_update(ctx->stream, L, Nt, nb, k, sp, big));
-            if (timed) TC_HIP(hipEventRecord(ctx->gemm_ev[2 * launches + 1], ctx->stream));
-            TC_HIP(tc::launch_panel_reduce(ctx->stream, L, Nt, nb, k, sp, big));
+        if (k >= 1 && k + 1 < Nt) {
+            const int c = k + 1;
+            const int sp = tc::panel_splits(Nt, nb, c, k);
+            TC_HIP(hipStreamWaitEvent(sb, ev_t[k - 1], 0));
+            if (timed) TC_HIP(hipEventRecord(ctx->gemm_ev[2 * launches], sb));
+            TC_HIP(tc::launch_panel_update(sb, L, Nt, nb, c, 0, k, sp, big, false));
+            if (timed) TC_HIP(hipEventRecord(ctx->gemm_ev[2 * launches + 1], sb));
+            TC_HIP(tc::launch_panel_reduce(sb, L, Nt, nb, c, sp, big));
+            TC_HIP(hipEventRecord(ev_p[c], sb));
             // algorithmic flops: SYRK nb^2 * K (lower half) + GEMM 2 nb^2 K per tile below
-            gemm_flops += (double)nb * nb * ((double)k * nb) * (1.0 + 2.0 * (Nt - k - 1));
+            gemm_flops += (double)nb * nb * ((double)k * nb) * (1.0 + 2.0 * (Nt - c - 1));
             ++launches;
         }
+        if (k >= 1) {
+            if (k >= 2) TC_HIP(hipStreamWaitEvent(sm, ev_p[k], 0));
+            TC_HIP(tc::launch_panel_update(sm, L, Nt, nb, k, k - 1, k, 1, nullptr, true));
+            tail_flops += (double)nb * nb * (double)nb * (1.0 + 2.0 * (Nt - k - 1));
+        }
         double* Tkk = L + tc::tile_off(Nt, k, k) * nb2;
-        if (tc_status s = potrf_rec(ctx, Tkk, nb, 0, nb, (int64_t)k * nb, d_info, big)) return s;
+        if (tc_status s = potrf_rec(ctx, Tkk, nb, 0, nb, (int64_t)k * nb, d_info, pot)) return s;
         if (k + 1 < Nt)
-            TC_HIP(tc::launch_trsm(ctx->stream, L + tc::tile_off(Nt, k + 1, k) * nb2, Tkk, nb,
+            TC_HIP(tc::launch_trsm(sm, L + tc::tile_off(Nt, k + 1, k) * nb2, Tkk, nb,
                                    (int64_t)(Nt - k - 1) * nb, nb));
+        TC_HIP(hipEventRecord(ev_t[k], sm));
     }
     TC_HIP(hipEventRecord(ctx->ev1, ctx->stream));
     int info = 0;
@@ -524,7 +581,7 @@ tc_status factorize_fp64(tc_ctx* ctx, int64_t n, int nb, const double* A, double
         stats->info = info;
         const double nd = (double)n;
         stats->flops_total = nd * nd * nd / 3.0;
-        stats->class_flops[TC_FP64] = gemm_flops;
+        stats->class_flops[TC_FP64] = gemm_flops + tail_flops;
         stats->class_tiles[TC_FP64] = (int32_t)ntiles;
     }
     return info > 0 ? info : TC_OK;
@@ -543,7 +600,8 @@ tc_status factorize_mixed(tc_ctx* ctx, int64_t n, int nb, const double* A, const
     double* part = reinterpret_cast<double*>(ctx->ws + Ly.small);
     double* W = reinterpret_cast<double*>(ctx->ws + Ly.panel);
     int* d_lists = reinterpret_cast<int*>(ctx->ws + Ly.lists);
-    const size_t big_cap = Ly.small - Ly.big;
+    const size_t big_cap = Ly.potrf - Ly.big;
+    double* pot = reinterpret_cast<double*>(ctx->ws + Ly.potrf);
     const int64_t nb2 = (int64_t)nb * nb;
     int64_t* d_toff = reinterpret_cast<int64_t*>(storage + P.tab_toff);
     int64_t* d_shoff = reinterpret_cast<int64_t*>(storage + P.tab_shoff);
@@ -567,6 +625,7 @@ tc_status factorize_mixed(tc_ctx* ctx, int64_t n, int nb, const double* A, const
         }
     }
     std::vector<int> zeros(P.ntiles, 0);
+    if (tc_status s = ctx_aux_streams(ctx)) return s;
     TC_HIP(hipEventRecord(ctx->ev0, ctx->stream));
     TC_HIP(hipMemcpyAsync(d_lists, lists.data(), lists.size() * sizeof(int), hipMemcpyHostToDevice,
                           ctx->stream));
@@ -585,23 +644,36 @@ tc_status factorize_mixed(tc_ctx* ctx, int64_t n, int nb, const double* A, const
         TC_HIP(hipMemcpyAsync(W, A + tc::tile_off(Nt, k, k) * nb2, (size_t)(Nt - k) * nb2 * sizeof(double),
                               hipMemcpyDeviceToDevice, ctx->stream));
         if (k > 0) {
+            // The class groups write disjoint tiles of W: the FP32 group runs
+            // on aux[0], the narrow groups on aux[1], concurrently with the
+            // FP64 group on the main stream; all join before POTRF.
+            TC_HIP(hipEventRecord(ctx->aux_ev[0], ctx->stream));
+            bool used[2] = {false, false};
+            for (int c = 1; c <= 4; ++c) {
+                const int cnt = lcount[(size_t)k * 5 + c];
+                if (!cnt) continue;
+                const int a = c == TC_FP32 ? 0 : 1;
+                if (!used[a]) TC_HIP(hipStreamWaitEvent(ctx->aux[a], ctx->aux_ev[0], 0));
+                used[a] = true;
+                const int* lc = d_lists + ((size_t)k * 5 + c) * Nt;
+                if (c == TC_FP32)
+                    TC_HIP(tc::launch_mxp_gemm_f32(ctx->aux[a], W, Nt, nb, k, lc, cnt, c, storage,
+                                                   d_shoff));
+                else
+                    TC_HIP(tc::launch_mxp_gemm_narrow(ctx->aux[a], W, Nt, nb, k, lc, cnt, c, storage,
+                                                      d_shoff, d_cscl));
+            }
             const int* l64 = d_lists + ((size_t)k * 5 + TC_FP64) * Nt;
             TC_HIP(tc::launch_mxp_gemm_f64(ctx->stream, W, Nt, nb, k, l64, lcount[(size_t)k * 5 + TC_FP64],
                                            true, storage, d_toff, d_tcls, d_tscl, big,
                                            big_cap / sizeof(double)));
-            for (int c = 1; c <= 4; ++c) {
-                const int cnt = lcount[(size_t)k * 5 + c];
-                if (!cnt) continue;
-                const int* lc = d_lists + ((size_t)k * 5 + c) * Nt;
-                if (c == TC_FP32)
-                    TC_HIP(tc::launch_mxp_gemm_f32(ctx->stream, W, Nt, nb, k, lc, cnt, c, storage,
-                                                   d_shoff));
-                else
-                    TC_HIP(tc::launch_mxp_gemm_narrow(ctx->stream, W, Nt, nb, k, lc, cnt, c, storage,
-                                                      d_shoff, d_cscl));
+            for (int a = 0; a < 2; ++a) {
+                if (!used[a]) continue;
+                TC_HIP(hipEventRecord(ctx->aux_ev[1 + a], ctx->aux[a]));
+                TC_HIP(hipStreamWaitEvent(ctx->stream, ctx->aux_ev[1 + a], 0));
             }
         }
-        if (tc_status s = potrf_rec(ctx, W, nb, 0, nb, (int64_t)k * nb, d_info, big)) return s;
+        if (tc_status s = potrf_rec(ctx, W, nb, 0, nb, (int64_t)k * nb, d_info, pot)) return s;
         if (k + 1 < Nt) TC_HIP(tc::launch_trsm(ctx->stream, W + nb2, W, nb, (int64_t)(Nt - k - 1) * nb, nb));
         TC_HIP(hipMemcpyAsync(storage + P.toff[tc::tile_off(Nt, k, k)], W, nb2 * sizeof(double),
                               hipMemcpyDeviceToDevice, ctx->stream));

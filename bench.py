@@ -259,6 +259,9 @@ def main():
     ap.add_argument("--grad-only", action="store_true",
                     help="only the likelihood-gradient leg (for profiling)")
     ap.add_argument("--no-ooc", action="store_true", help="skip the out-of-core leg")
+    ap.add_argument("--pmc-copy-gib", type=int, default=0,
+                    help="before the steps, copy this many GiB device to device (the calibration "
+                         "copy for HBM byte counters)")
     ap.add_argument("--ooc-only", action="store_true", help="only the out-of-core leg")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -304,6 +307,13 @@ def main():
         tc.solve(ctx, F, B)
         return F, ld
 
+    if args.pmc_copy_gib > 0:
+        src = torch.ones(args.pmc_copy_gib << 27, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        torch.cuda.empty_cache()
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()

@@ -112,7 +112,6 @@ hipError_t launch_mxp_finalize(hipStream_t s, const double* W, int Nt, int nb, i
 hipError_t launch_export(hipStream_t s, const TileView& L, double* out);
 
 // Refinement (ir.hip).
-int symv_chunk();
 size_t residual_partial_doubles(int Nt, int nb, int nrhs);
 hipError_t launch_residual(hipStream_t s, const double* A, int Nt, int nb, const double* X,
                            int64_t ldx, const double* B, int64_t ldb, int nrhs, double* partial,

@@ -30,6 +30,20 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6
+# HBM bytes per bulk panel-GEMM launch from the calibrated FETCH_SIZE and
+# WRITE_SIZE counter passes (profiles/panel_update_fp64_counters_n65536_nb1024.md),
+# valid for the kernel sources they were taken with.
+PANEL_TRAFFIC = {"bytes_per_launch": 3.1966e10,
+                 "sources_sha256": "3eadc1a05943b844d7c744a89ebedd8ead96dfcadddd4121edb5ab5755f45f61"}
+
+
+def panel_traffic():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("gemm_f64.hip", "gemm_f64.hpp"):
+        with open(os.path.join(ROOT, "paper_2410_09819_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return PANEL_TRAFFIC["bytes_per_launch"] if h.hexdigest() == PANEL_TRAFFIC["sources_sha256"] else None
 METRIC = "Cholesky TFLOP/s (n^3/3) + % peak, MxP vs FP64 at stated backward error"
 
 
@@ -362,7 +376,8 @@ def main():
             "peak": FP64_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": (achieved / FP64_PEAK_TFLOPS) if achieved else None,
-            "traffic": None,
+            "traffic": panel_traffic(),
+            "traffic_unit": "HBM bytes per launch (calibrated FETCH_SIZE + WRITE_SIZE)",
             "launches_per_step": gemm_launches / args.steps,
             "avg_launch_ms": gemm_ms / max(gemm_launches, 1),
             "flops_per_launch": gemm_flops / max(gemm_launches, 1),

@@ -180,7 +180,8 @@ tc_status tc_factorize(tc_ctx *ctx, int64_t n, int32_t nb, const double *A, cons
 
 /* Solve Sigma X = B with the factor: B <- L^{-T} L^{-1} B (tiles used as
  * stored, upcast to binary64).
- * B: device, n x nrhs binary64, column-major with leading dimension ldb >= n. */
+ * B: device, n x nrhs binary64, column-major with leading dimension ldb >= n
+ *    (may be NULL when nrhs == 0, which does nothing). */
 tc_status tc_solve(tc_ctx *ctx, const tc_factor *L, double *B, int64_t ldb, int32_t nrhs);
 
 /* Iterative refinement in binary64 (not in the paper; the classic scheme it
@@ -236,14 +237,15 @@ tc_status tc_factor_export(tc_ctx *ctx, const tc_factor *L, double *L64);
  * sum_i log L_ii - 1/2 z^T z (host), and Lbar (device, packed lower tiles
  * (n, nb), binary64, overwritten, strict upper triangle of the diagonal
  * tiles zero) receives dl/dL = tril(alpha z^T) - diag(1 / L_ii).
- * y: device, n binary64. L: an all-FP64 factor (TC_EUNSUPPORTED for a
- * mixed-precision one). */
+ * y: device, n binary64. L: any factor (the solves read mixed-precision
+ * tiles upcast to binary64). */
 tc_status tc_loglik_seed(tc_ctx *ctx, const tc_factor *L, const double *y, double *Lbar,
                          double *loglik);
 
 /* Bytes of device scratch tc_factor_adjoint needs (about the size of the
- * factor plus two tile columns); 0 for an invalid shape. */
-size_t tc_adjoint_bytes(int64_t n, int32_t nb);
+ * factor plus two tile columns; mixed != 0 adds room for the binary64
+ * upcast of a mixed-precision factor); 0 for an invalid shape. */
+size_t tc_adjoint_bytes(int64_t n, int32_t nb, int32_t mixed);
 
 /* Reverse sweep of the tile Cholesky. On input Lbar (device, packed lower
  * tiles, binary64) holds d(phi)/dL for a scalar phi of the factor (lower
@@ -251,8 +253,12 @@ size_t tc_adjoint_bytes(int64_t n, int32_t nb);
  * output it holds Abar = d(phi)/dA for the lower triangle of A, the only
  * part the factorization reads: phi changes by sum_{i>=j} Abar_ij dA_ij when
  * A_ij and A_ji change by dA_ij (strict upper triangle of diagonal tiles set
- * to zero). L: the all-FP64 factor of A (TC_EUNSUPPORTED otherwise).
- * scratch: device buffer of at least tc_adjoint_bytes(n, nb) bytes.
+ * to zero). L: the factor of A; a mixed-precision factor is upcast to
+ * binary64 and the sweep is the exact reverse of the binary64 Cholesky at
+ * that factor (an approximation of the gradient at the accuracy of the
+ * precision map).
+ * scratch: device buffer of at least tc_adjoint_bytes(n, nb, mixed) bytes,
+ * mixed = whether L is a mixed-precision factor.
  * stats: NULL or filled (ms_total, flops_total; ms_gemm, gemm_flops and
  * gemm_launches for the panel GEMMs when the context is timed). */
 tc_status tc_factor_adjoint(tc_ctx *ctx, const tc_factor *L, double *Lbar, void *scratch,

@@ -117,7 +117,7 @@ def lib():
         "tc_factor_export": (_i32, [_vp, _vp, _vp]),
         "tc_factor_destroy": (_i32, [_vp]),
         "tc_loglik_seed": (_i32, [_vp, _vp, _vp, _vp, ctypes.POINTER(ctypes.c_double)]),
-        "tc_adjoint_bytes": (_sz, [_i64, _i32]),
+        "tc_adjoint_bytes": (_sz, [_i64, _i32, _i32]),
         "tc_factor_adjoint": (_i32, [_vp, _vp, _vp, _vp, _sz, ctypes.POINTER(Stats)]),
         "tc_matern_grad": (_i32, [_vp, _i64, _i32, _vp, ctypes.POINTER(Matern), _vp,
                                   ctypes.POINTER(ctypes.c_double)]),
@@ -256,8 +256,9 @@ def matern_tiles(ctx: Context, locs, theta, nb: int, out=None, norms: bool = Tru
 
 
 class Factor:
-    def __init__(self, handle, n, nb, storage, stats: Stats):
+    def __init__(self, handle, n, nb, storage, stats: Stats, mixed: bool = False):
         self.handle, self.n, self.nb, self.storage, self.stats = handle, n, nb, storage, stats
+        self.mixed = mixed
 
     def close(self):
         if getattr(self, "handle", None):
@@ -289,6 +290,8 @@ def factorize(ctx: Context, A, n: int, nb: int, cmap=None, inplace: bool = False
                                 storage.numel() * storage.element_size(), ctypes.byref(h),
                                 ctypes.byref(st))
     F = Factor(h, n, nb, storage, st) if h.value else None
+    if F is not None:
+        F.mixed = m is not None and bool(np.any(m != FP64))
     if status != 0:
         if F is not None:
             F.close()
@@ -353,8 +356,8 @@ def export(ctx: Context, F: Factor, out=None):
 
 # --- log-likelihood gradient (reverse mode through the tile Cholesky) ------
 
-def adjoint_bytes(n: int, nb: int) -> int:
-    return lib().tc_adjoint_bytes(n, nb)
+def adjoint_bytes(n: int, nb: int, mixed: bool = False) -> int:
+    return lib().tc_adjoint_bytes(n, nb, 1 if mixed else 0)
 
 
 def loglik_seed(ctx: Context, F: Factor, y, Lbar) -> float:
@@ -371,7 +374,7 @@ def factor_adjoint(ctx: Context, F: Factor, Lbar, scratch=None) -> Stats:
     """In place: Lbar (dphi/dL, packed lower tiles) <- dphi/dA (lower
     triangle). Returns the sweep's statistics."""
     import torch
-    nbytes = adjoint_bytes(F.n, F.nb)
+    nbytes = adjoint_bytes(F.n, F.nb, F.mixed)
     if scratch is None:
         scratch = torch.empty(nbytes, dtype=torch.uint8, device=Lbar.device)
     st = Stats()
@@ -397,18 +400,26 @@ def _autograd_function():
     class MaternLogLik(torch.autograd.Function):
         """l(theta) of Eq. 1 for the Matern covariance with nugget, theta =
         (sigma2, range, nugget) as a float64 tensor, nu fixed. Forward:
-        covariance tiles, tile Cholesky (in place), log-likelihood and the
-        reverse-mode seed. Backward: the blocked reverse sweep and the
-        contraction with the covariance derivatives."""
+        covariance tiles, tile Cholesky, log-likelihood and the reverse-mode
+        seed. Backward: the blocked reverse sweep and the contraction with
+        the covariance derivatives. With eps set, the factorization uses the
+        {FP64, FP32} precision map at target accuracy eps (Section IV-C) and
+        the gradient is that of the mixed-precision factor."""
 
         @staticmethod
-        def forward(fctx, theta, locs, y, nu, nb, ctx):
+        def forward(fctx, theta, locs, y, nu, nb, ctx, eps=None):
             th = [float(v) for v in theta.detach().cpu().tolist()]
             n = locs.shape[0]
             full = (th[0], th[1], float(nu), th[2])
-            A, _, _ = matern_tiles(ctx, locs, full, nb, norms=False)
-            F = factorize(ctx, A, n, nb, inplace=True)
-            Lbar = torch.empty_like(A)
+            if eps is None:
+                A, _, _ = matern_tiles(ctx, locs, full, nb, norms=False)
+                F = factorize(ctx, A, n, nb, inplace=True)
+            else:
+                A, tf, fro = matern_tiles(ctx, locs, full, nb, norms=True)
+                cm = precision_map(n // nb, tf.cpu().numpy(), fro, eps, allowed=(FP64, FP32))
+                F = factorize(ctx, A, n, nb, cmap=cm)
+                del A
+            Lbar = torch.empty(num_tiles(n, nb) * nb * nb, dtype=torch.float64, device=locs.device)
             ll = loglik_seed(ctx, F, y, Lbar)
             fctx.state = (ctx, F, Lbar, locs, full, nb)
             return torch.tensor(ll, dtype=torch.float64, device=theta.device)
@@ -421,7 +432,7 @@ def _autograd_function():
             g = matern_grad(ctx, locs, full, nb, Lbar)
             F.close()
             grad = torch.from_numpy(g).to(device=gout.device, dtype=gout.dtype) * gout
-            return grad, None, None, None, None, None
+            return grad, None, None, None, None, None, None
 
     return MaternLogLik
 
@@ -429,12 +440,12 @@ def _autograd_function():
 _MLL = None
 
 
-def matern_loglik(theta, locs, y, nu: float, nb: int, ctx: Context):
+def matern_loglik(theta, locs, y, nu: float, nb: int, ctx: Context, eps=None):
     """Differentiable log-likelihood (torch.autograd): see MaternLogLik."""
     global _MLL
     if _MLL is None:
         _MLL = _autograd_function()
-    return _MLL.apply(theta, locs, y, nu, nb, ctx)
+    return _MLL.apply(theta, locs, y, nu, nb, ctx, eps)
 
 
 def __getattr__(name):

@@ -221,7 +221,7 @@ __global__ void finish_diag_kernel(const double* __restrict__ H, double* __restr
 }
 
 // Seed of the log-likelihood: Lbar = tril(alpha z^T) - diag(1 / L_ii).
-__global__ void loglik_seed_kernel(const double* __restrict__ L, const double* __restrict__ alpha,
+__global__ void loglik_seed_kernel(TileView L, const double* __restrict__ alpha,
                                    const double* __restrict__ z, double* __restrict__ Lb,
                                    int64_t Nt, int nb) {
     const int64_t t = blockIdx.y;
@@ -232,7 +232,10 @@ __global__ void loglik_seed_kernel(const double* __restrict__ L, const double* _
     const int c = blockIdx.x;  // one column of the tile per workgroup
     const double zc = z[j * nb + c];
     double* out = Lb + t * nb2 + (int64_t)c * nb;
-    const double* Lt = L + t * nb2 + (int64_t)c * nb;
+    // diagonal tiles are binary64 in every factor layout
+    const double* Lt = reinterpret_cast<const double*>(
+                           L.toff ? L.base + L.toff[t] : L.base + t * nb2 * (int64_t)sizeof(double)) +
+                       (int64_t)c * nb;
     for (int r = threadIdx.x; r < nb; r += blockDim.x) {
         double v = alpha[i * nb + r] * zc;
         if (i == j) {
@@ -360,7 +363,7 @@ hipError_t launch_finish_diag(hipStream_t s, const double* H, double* D, int nb)
     return hipGetLastError();
 }
 
-hipError_t launch_loglik_seed(hipStream_t s, const double* L, const double* alpha, const double* z,
+hipError_t launch_loglik_seed(hipStream_t s, const TileView& L, const double* alpha, const double* z,
                               double* Lb, int Nt, int nb) {
     const int64_t ntiles = (int64_t)Nt * (Nt + 1) / 2;
     hipLaunchKernelGGL(loglik_seed_kernel, dim3(nb, (unsigned)ntiles), dim3(256), 0, s, L, alpha, z,

@@ -24,7 +24,7 @@ using namespace tc::host;
 namespace {
 
 struct AdjLayout {
-    size_t tt, pl, tb, sq, part, total;  // offsets in doubles, total in bytes
+    size_t tt, pl, tb, sq, part, l64, total;  // offsets in doubles, total in bytes
 };
 
 size_t adj_partial_doubles(int Nt, int nb) {
@@ -43,7 +43,7 @@ size_t adj_partial_doubles(int Nt, int nb) {
     return mx;
 }
 
-AdjLayout adj_layout(int64_t n, int nb) {
+AdjLayout adj_layout(int64_t n, int nb, bool mixed) {
     const int64_t Nt = n / nb;
     const int64_t nb2 = (int64_t)nb * nb;
     const int64_t panel = std::max<int64_t>(Nt - 1, 1) * nb2;
@@ -53,7 +53,9 @@ AdjLayout adj_layout(int64_t n, int nb) {
     L.tb = L.pl + panel;
     L.sq = L.tb + panel;
     L.part = L.sq + 5 * nb2;
-    L.total = (L.part + adj_partial_doubles((int)Nt, nb) + 32) * sizeof(double);
+    L.l64 = L.part + adj_partial_doubles((int)Nt, nb) + 32;
+    // a mixed-precision factor is swept in binary64: room for its upcast tiles
+    L.total = (L.l64 + (mixed ? (size_t)(Nt * (Nt + 1) / 2) * nb2 : 0)) * sizeof(double);
     return L;
 }
 
@@ -68,19 +70,18 @@ inline tc::AdjMat plain_mat(double* p, int nb) {  // nb rows, column-major, ld n
 
 extern "C" {
 
-size_t tc_adjoint_bytes(int64_t n, int32_t nb) {
+size_t tc_adjoint_bytes(int64_t n, int32_t nb, int32_t mixed) {
     if (!valid_shape(n, nb)) return 0;
-    return adj_layout(n, nb).total;
+    return adj_layout(n, nb, mixed != 0).total;
 }
 
 tc_status tc_factor_adjoint(tc_ctx* ctx, const tc_factor* F, double* Lbar, void* scratch,
                             size_t scratch_bytes, tc_stats* stats) {
     if (!ctx || !F || !Lbar || !scratch) return fail(TC_EINVAL, "NULL argument");
     if (F->info > 0) return fail(TC_EINVAL, "factor is not valid (factorization failed)");
-    if (F->mixed) return fail(TC_EUNSUPPORTED, "the reverse sweep needs an all-FP64 factor");
     const int64_t n = F->n;
     const int nb = F->nb, Nt = F->Nt;
-    const AdjLayout Ly = adj_layout(n, nb);
+    const AdjLayout Ly = adj_layout(n, nb, F->mixed);
     if (scratch_bytes < Ly.total)
         return fail(TC_ENOMEM, "adjoint scratch too small: need " + std::to_string(Ly.total) +
                                    " bytes, have " + std::to_string(scratch_bytes));
@@ -99,6 +100,11 @@ tc_status tc_factor_adjoint(tc_ctx* ctx, const tc_factor* F, double* Lbar, void*
     double* Y = P + nb2;
     double* part = S + Ly.part;
     const double* L = F->tiles;
+    if (F->mixed) {  // sweep the upcast factor
+        double* L64 = S + Ly.l64;
+        TC_HIP(tc::launch_export(st, factor_view(F), L64));
+        L = L64;
+    }
     const bool timed = (ctx->flags & 1u) != 0;
     while (timed && ctx->gemm_ev.size() < (size_t)2 * Nt) {
         hipEvent_t e;

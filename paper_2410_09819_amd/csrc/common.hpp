@@ -157,7 +157,7 @@ hipError_t launch_transpose_tiles(hipStream_t s, const double* src, double* dst,
 hipError_t launch_set_identity(hipStream_t s, double* X, int nb);
 hipError_t launch_mirror_lower(hipStream_t s, double* P, int nb);
 hipError_t launch_finish_diag(hipStream_t s, const double* H, double* D, int nb);
-hipError_t launch_loglik_seed(hipStream_t s, const double* L, const double* alpha, const double* z,
+hipError_t launch_loglik_seed(hipStream_t s, const TileView& L, const double* alpha, const double* z,
                               double* Lb, int Nt, int nb);
 // sum_{i>=j} Abar_ij (C_ij / sigma2, dC_ij/drange) and sum_i Abar_ii, as 3
 // partial sums per (tile, strip) in `part` (matern.hip).

@@ -68,6 +68,8 @@ tc_status check_ws(tc_ctx* ctx, int64_t n, int nb);
 tc_status ctx_ooc_resources(tc_ctx* ctx, size_t bytes);
 // Create the auxiliary compute streams and their events in the context (once).
 tc_status ctx_aux_streams(tc_ctx* ctx);
+// Read-only device view of a factor's tiles (any precision layout).
+tc::TileView factor_view(const tc_factor* F);
 // POTRF of the s x s block at offset o of a diagonal tile (leading dim nb),
 // recursive halving down to 128 x 128 leaves; failures set *info.
 tc_status potrf_rec(tc_ctx* ctx, double* T, int nb, int o, int s, int64_t col0, int* info,

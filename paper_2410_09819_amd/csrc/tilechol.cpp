@@ -246,27 +246,26 @@ tc_status potrf_rec(tc_ctx* ctx, double* T, int nb, int o, int s, int64_t col0, 
 }  // namespace host
 }  // namespace tc
 
+namespace tc {
+namespace host {
+tc::TileView factor_view(const tc_factor* F) {
+    tc::TileView v;
+    v.Nt = F->Nt;
+    v.nb = F->nb;
+    v.base = F->mixed ? F->storage : reinterpret_cast<const char*>(F->tiles);
+    v.toff = F->mixed ? F->d_toff : nullptr;
+    v.tcls = F->mixed ? F->d_tcls : nullptr;
+    v.tscl = F->mixed ? F->d_tscl : nullptr;
+    return v;
+}
+}  // namespace host
+}  // namespace tc
+
 using namespace tc::host;
 
 namespace {
 
-tc::TileView view_of(const tc_factor* F) {
-    tc::TileView v;
-    v.Nt = F->Nt;
-    v.nb = F->nb;
-    if (F->mixed) {
-        v.base = F->storage;
-        v.toff = F->d_toff;
-        v.tcls = F->d_tcls;
-        v.tscl = F->d_tscl;
-    } else {
-        v.base = reinterpret_cast<const char*>(F->tiles);
-        v.toff = nullptr;
-        v.tcls = nullptr;
-        v.tscl = nullptr;
-    }
-    return v;
-}
+tc::TileView view_of(const tc_factor* F) { return factor_view(F); }
 
 const double* diag_tile(const tc_factor* F, int k) {
     const int64_t t = tc::tile_off(F->Nt, k, k);
@@ -741,10 +740,11 @@ tc_status tc_factorize(tc_ctx* ctx, int64_t n, int32_t nb, const double* A, cons
 }
 
 tc_status tc_solve(tc_ctx* ctx, const tc_factor* F, double* B, int64_t ldb, int32_t nrhs) {
-    if (!ctx || !F || !B) return fail(TC_EINVAL, "NULL argument");
+    if (!ctx || !F) return fail(TC_EINVAL, "NULL argument");
     if (nrhs < 0 || ldb < F->n) return fail(TC_EINVAL, "bad nrhs or ldb");
     if (F->info > 0) return fail(TC_EINVAL, "factor is not valid (factorization failed)");
     if (nrhs == 0) return TC_OK;
+    if (!B) return fail(TC_EINVAL, "NULL right-hand sides");
     if (tc_status s = check_ws(ctx, F->n, F->nb)) return s;
     DeviceGuard g(ctx->device);
     const Layout Ly = layout(F->n, F->nb);
@@ -831,7 +831,6 @@ tc_status tc_loglik_seed(tc_ctx* ctx, const tc_factor* F, const double* y, doubl
                          double* loglik) {
     if (!ctx || !F || !y || !Lbar || !loglik) return fail(TC_EINVAL, "NULL argument");
     if (F->info > 0) return fail(TC_EINVAL, "factor is not valid (factorization failed)");
-    if (F->mixed) return fail(TC_EUNSUPPORTED, "the likelihood seed needs an all-FP64 factor");
     if (tc_status s = check_ws(ctx, F->n, F->nb)) return s;
     DeviceGuard g(ctx->device);
     const int64_t n = F->n;
@@ -844,7 +843,7 @@ tc_status tc_loglik_seed(tc_ctx* ctx, const tc_factor* F, const double* y, doubl
     if (tc_status s = fwd_enqueue(ctx, F, z, n, 1)) return s;
     TC_HIP(tc::launch_copy_cols(ctx->stream, alpha, n, z, n, n, 1));
     if (tc_status s = bwd_enqueue(ctx, F, alpha, n, 1, big)) return s;
-    TC_HIP(tc::launch_loglik_seed(ctx->stream, F->tiles, alpha, z, Lbar, F->Nt, F->nb));
+    TC_HIP(tc::launch_loglik_seed(ctx->stream, view_of(F), alpha, z, Lbar, F->Nt, F->nb));
     std::vector<double> zn;
     if (tc_status s = colnorms(ctx, z, n, n, 1, part, zn)) return s;
     double ld = 0.0;

@@ -65,7 +65,11 @@ def cpu_baseline(w, ns=4096):
                       "(%.1f s)" % (ns, ns, w["nb"], dt)}
 
 
-def mxp_comparison(tc, si, dev):
+def progress(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def mxp_comparison(tc, si, dev, n=None):
     """Time-to-solution at n=131072: FP64 = factorization + 16-RHS solve;
     mixed precision = tile norms already known from generation, precision
     map + factorization + refined 16-RHS solve to 1e-9. Same matrix, same
@@ -73,7 +77,7 @@ def mxp_comparison(tc, si, dev):
     import numpy as np
     import torch
     w = si.WORKLOADS["mxp"]
-    n, nb, nrhs = w["n"], w["nb"], w["nrhs"]
+    n, nb, nrhs = n or w["n"], w["nb"], w["nrhs"]
     theta = (w["sigma2"], w["range"], w["nu"], w["nugget"])
     pts = torch.from_numpy(si.points(n, seed=w["seed"])).to(dev)
     ctx = tc.Context(n, nb, nrhs=nrhs)
@@ -95,6 +99,7 @@ def mxp_comparison(tc, si, dev):
     torch.cuda.synchronize()
     t_fp64 = time.perf_counter() - t0
     ms_f64 = F.stats.ms_total
+    progress("mxp comparison: FP64 factor + solve %.2f s" % t_fp64)
     F.close()
     del storage, F
     torch.cuda.empty_cache()
@@ -108,6 +113,7 @@ def mxp_comparison(tc, si, dev):
     st = tc.solve_refine(ctx, F, A, B, max_iter=30, tol=1e-9)
     torch.cuda.synchronize()
     t_mxp = time.perf_counter() - t0
+    progress("mxp comparison: mixed map + factor + refined solve %.2f s" % t_mxp)
     flops = n ** 3 / 3.0
     cls = list(F.stats.class_tiles)
     cf = list(F.stats.class_flops)
@@ -273,6 +279,8 @@ def main():
     ap.add_argument("--grad-only", action="store_true",
                     help="only the likelihood-gradient leg (for profiling)")
     ap.add_argument("--no-ooc", action="store_true", help="skip the out-of-core leg")
+    ap.add_argument("--mxp-n", type=int, default=0,
+                    help="order of the mixed-precision comparison (default: the mxp workload's)")
     ap.add_argument("--pmc-copy-gib", type=int, default=0,
                     help="before the steps, copy this many GiB device to device (the calibration "
                          "copy for HBM byte counters)")
@@ -295,7 +303,7 @@ def main():
     dev = torch.device("cuda", 0)
     if args.mxp_only or args.grad_only or args.ooc_only:
         if args.mxp_only:
-            res = mxp_comparison(tc, si, dev)
+            res = mxp_comparison(tc, si, dev, args.mxp_n or None)
         elif args.grad_only:
             res = grad_leg(tc, si, dev)
         else:

@@ -83,57 +83,56 @@ __device__ __forceinline__ void raw_load(const MixedTile& t, int64_t idx, RawSla
     }
 }
 
-// OCP e4m3 byte -> float (exact): normal numbers by exponent rebias, the
-// subnormals as m * 2^-9.
-__device__ __forceinline__ float fp8_to_float(uint32_t b) {
-    const uint32_t e = (b >> 3) & 15u, m = b & 7u;
-    const float a = e ? __uint_as_float(((e + 120u) << 23) | (m << 20)) : (float)m * 0x1p-9f;
-    return (b & 0x80u) ? -a : a;
-}
+typedef float f2v __attribute__((ext_vector_type(2)));
 
-__device__ __forceinline__ void raw_store(const RawSlab& r, int cls, double mul, double* dst) {
+// Decode the 8 stored values of a run to binary64 and write them to LDS.
+// Conversions are exact: FP8 (OCP e4m3, which the gfx950 packed conversion
+// implements) and FP16 through binary32, the tile scale applied afterwards
+// with ldexp in binary64, and only for the scaled classes.
+__device__ __forceinline__ void raw_store(const RawSlab& r, int cls, int scale, double* dst) {
     double v[8];
+    const uint32_t* w = reinterpret_cast<const uint32_t*>(r.w);
     switch (cls) {
-        case kFP64: {
-            const uint32_t* w = reinterpret_cast<const uint32_t*>(r.w);
+        case kFP64:
 #pragma unroll
             for (int i = 0; i < 8; ++i) v[i] = __hiloint2double((int)w[2 * i + 1], (int)w[2 * i]);
             break;
-        }
-        case kFP32: {
-            const uint32_t* w = reinterpret_cast<const uint32_t*>(r.w);
+        case kFP32:
 #pragma unroll
             for (int i = 0; i < 8; ++i) v[i] = (double)__uint_as_float(w[i]);
             break;
-        }
-        case kFP16: {
-            const uint32_t* w = reinterpret_cast<const uint32_t*>(r.w);
+        case kFP16:
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
                 const uint16_t h = (uint16_t)(w[i >> 1] >> (16 * (i & 1)));
                 v[i] = (double)(float)__builtin_bit_cast(_Float16, h);
             }
             break;
-        }
-        case kBF16: {
-            const uint32_t* w = reinterpret_cast<const uint32_t*>(r.w);
+        case kBF16:
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
                 const uint32_t h = (w[i >> 1] >> (16 * (i & 1))) & 0xFFFFu;
                 v[i] = (double)__uint_as_float(h << 16);
             }
             break;
-        }
-        default: {
-            const uint32_t* w = reinterpret_cast<const uint32_t*>(r.w);
+        default:
 #pragma unroll
-            for (int i = 0; i < 8; ++i) v[i] = (double)fp8_to_float((w[i >> 2] >> (8 * (i & 3))) & 0xFFu);
+            for (int q = 0; q < 2; ++q) {
+                const f2v lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)w[q], false);
+                const f2v hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)w[q], true);
+                v[4 * q] = lo.x;
+                v[4 * q + 1] = lo.y;
+                v[4 * q + 2] = hi.x;
+                v[4 * q + 3] = hi.y;
+            }
             break;
-        }
+    }
+    if (scale != 0) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[i] = ldexp(v[i], scale);
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-        *reinterpret_cast<d2*>(dst + 2 * i) = d2{v[2 * i] * mul, v[2 * i + 1] * mul};
+    for (int i = 0; i < 4; ++i) *reinterpret_cast<d2*>(dst + 2 * i) = d2{v[2 * i], v[2 * i + 1]};
 }
 
 template <class AOp, class BOp>
@@ -151,8 +150,7 @@ __device__ __forceinline__ void mixed_mainloop(d4 (&acc)[kB / 32][kB / 32], cons
     double* Bs = lds + 2 * T::BK * T::LDA;
     const int col = tid >> 4, row0 = (tid & 15) * 8;
     RawSlab ra, rb;
-    int acls, bcls;
-    double amul, bmul;
+    int acls, bcls, ascl, bscl;
     auto gload = [&](int64_t kk) {
         int64_t ia, ib;
         const MixedTile ta = aop(kk, ia), tb = bop(kk, ib);
@@ -160,12 +158,12 @@ __device__ __forceinline__ void mixed_mainloop(d4 (&acc)[kB / 32][kB / 32], cons
         raw_load(tb, ib + (int64_t)col * nb + row0, rb);
         acls = ta.cls;
         bcls = tb.cls;
-        amul = ldexp(1.0, ta.scale);
-        bmul = ldexp(1.0, tb.scale);
+        ascl = ta.scale;
+        bscl = tb.scale;
     };
     auto sstore = [&](int buf) {
-        raw_store(ra, acls, amul, As + buf * T::BK * T::LDA + col * T::LDA + row0);
-        raw_store(rb, bcls, bmul, Bs + buf * T::BK * T::LDB + col * T::LDB + row0);
+        raw_store(ra, acls, ascl, As + buf * T::BK * T::LDA + col * T::LDA + row0);
+        raw_store(rb, bcls, bscl, Bs + buf * T::BK * T::LDB + col * T::LDB + row0);
     };
     gload(kbeg);
     sstore(0);

@@ -166,7 +166,11 @@ tc_status tc_precision_map(int32_t Nt, const double *tile_fro, double fro_A, dou
  *    factor is stored per tile in its class (FP16 and FP8 tiles with a
  *    power-of-two scale), each update into a tile of class p is computed
  *    from operands rounded to p with FP32 accumulation, POTRF and TRSM run
- *    in FP64 and each new tile is rounded to its class.
+ *    in FP64 and each new tile is rounded to its class. FP32-class updates
+ *    run on the FP16 matrix cores with each binary32 operand split into two
+ *    FP16 terms (three products; at most 3 * 2^-22 relative error per
+ *    product for entries within 2^18 of their tile's largest, before the
+ *    FP32 accumulation).
  * storage: device buffer of tc_factor_bytes(n, nb, map) bytes that receives
  *    the factor (tiles, operand copies for the low-precision updates and the
  *    factor's own tables). It must outlive *L.

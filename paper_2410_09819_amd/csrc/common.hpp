@@ -99,8 +99,10 @@ hipError_t launch_mxp_gemm_f64(hipStream_t s, double* W, int Nt, int nb, int k, 
                                int nrows, bool diag, const char* storage, const int64_t* toff,
                                const uint8_t* tcls, const int* tscl, double* partial,
                                size_t partial_cap);
+// FP32 group: FP16 MFMA over the two-plane (hi, lo) split copies.
 hipError_t launch_mxp_gemm_f32(hipStream_t s, double* W, int Nt, int nb, int k, const int* rows,
-                               int nrows, int cls, const char* storage, const int64_t* shoff);
+                               int nrows, const char* storage, const int64_t* shoff,
+                               const int* cscl);
 // FP16 / BF16 / FP8 group: narrow-format MFMA over the class's operand
 // copies (row-major bits, per-copy scale cscl), FP32 accumulation.
 hipError_t launch_mxp_gemm_narrow(hipStream_t s, double* W, int Nt, int nb, int k, const int* rows,

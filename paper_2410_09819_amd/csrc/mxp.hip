@@ -6,16 +6,22 @@
 // where Lh are the stored factor tiles and Q_p rounds a stored tile to class
 // p with its per-tile scale. Diagonal tiles and FP64-class tiles use FP64
 // MFMA on the stored operands, upcast exactly while they are staged into LDS.
-// The low classes use FP32 MFMA with FP32 accumulation on "operand copies":
-// for every tile and every low class it will be multiplied in (known from
-// the static schedule), the finalize step writes Q_p(Lh) in binary32. For
-// FP16, BF16 and FP8 operands every product of two operands is exact in
-// binary32 (barring underflow), so this computes what a narrow-format MFMA with FP32
-// accumulation computes (same rounded operands, exact products, binary32
-// sums; only the summation order may differ). For FP32-class tiles the
-// products are rounded to binary32 as usual. POTRF and TRSM run in FP64 on a working
-// copy of the column; finalize rounds each new tile to its class (with its
-// scale) into the factor storage and writes its operand copies.
+// The low classes read "operand copies": for every tile and every low class
+// it will be multiplied in (known from the static schedule), the finalize
+// step writes Q_p(Lh) in the MFMA operand order (row-major, k contiguous)
+// with a power-of-two copy scale. FP16, BF16 and FP8 run on the narrow
+// MFMAs with FP32 accumulation. FP32 runs on the FP16 MFMA: each binary32
+// operand x (times its copy scale) is held as hi + lo, hi = fp16(x),
+// lo = fp16(x - hi), and each product as hi_a hi_b + hi_a lo_b + lo_a hi_b
+// (the two-term split of Ootomo and Yokota, 2022). For entries within 2^18
+// of the copy's largest, the representation and the dropped lo_a lo_b cost
+// at most 3 * 2^-22 of |ab| per product; smaller entries (FP16 subnormal
+// lo) are held to 2^-25 absolute in the scaled domain, 2^-40 of the
+// largest. Norm-wise this stays below the FP32 accumulation error of the
+// K >= 1024 terms a column sums over.
+// POTRF and TRSM run in FP64 on a working copy of the column; finalize
+// rounds each new tile to its class (with its scale) into the factor
+// storage and writes its operand copies.
 #include "formats.hpp"
 #include "gemm_f64.hpp"
 
@@ -310,120 +316,6 @@ __global__ __launch_bounds__(256) void mxp_group_reduce_kernel(double* __restric
 }
 
 // ---------------------------------------------------------------------------
-// FP32 MFMA main loop over binary32 operand copies (column-major tiles).
-// v_mfma_f32_16x16x4_f32: lane l supplies X[l%16][l/16], Y[l/16][l%16];
-// accumulator element v of lane l is D[4(l/16) + v][l%16] (checked on the
-// device). Blocks are computed as C^T = B A^T so element v of lane l is
-// C[l%16][4(l/16) + v].
-// ---------------------------------------------------------------------------
-constexpr int kBK32 = 16;
-constexpr int kPad32 = 16;
-constexpr int kLD32 = kB + kPad32;
-constexpr int kLoads32 = kB * kBK32 / 4 / kGemmThreads;  // float4 loads per thread per operand
-
-struct CopyOp {
-    const char* storage;
-    const int64_t* shoff;
-    int cls;
-    int64_t Nt, nb, row_tile, r0;
-    __device__ const float* operator()(int64_t kk) const {
-        const int64_t n = kk / nb;
-        const int64_t t = tile_off(Nt, row_tile, n);
-        return reinterpret_cast<const float*>(storage + shoff[t * 4 + (cls - 1)]) +
-               (kk - n * nb) * nb + r0;
-    }
-};
-
-__global__ __launch_bounds__(kGemmThreads, 2) void mxp_gemm_f32_kernel(
-    double* __restrict__ W, int Nt, int nb, int k, const int* __restrict__ rows, int nrows, int cls,
-    const char* __restrict__ storage, const int64_t* __restrict__ shoff) {
-    __shared__ float As[2 * kBK32 * kLD32];
-    __shared__ float Bs[2 * kBK32 * kLD32];
-    const int T = nb / kB;
-    const int64_t total = (int64_t)nrows * T * T;
-    const int64_t b = xcd_remap_m(blockIdx.x, total);
-    int64_t rt;
-    int br, bc;
-    group_block(b, T, false, rows, rt, br, bc);
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave & 1, wn = wave >> 1;
-    const CopyOp aop{storage, shoff, cls, Nt, nb, k + rt, (int64_t)br * kB};
-    const CopyOp bop{storage, shoff, cls, Nt, nb, k, (int64_t)bc * kB};
-    int ecol[kLoads32], erow[kLoads32];
-#pragma unroll
-    for (int q = 0; q < kLoads32; ++q) {
-        const int e = (q * kGemmThreads + tid) * 4;
-        ecol[q] = e / kB;
-        erow[q] = e % kB;
-    }
-    f4 acc[4][4];
-#pragma unroll
-    for (int mi = 0; mi < 4; ++mi)
-#pragma unroll
-        for (int ni = 0; ni < 4; ++ni) acc[mi][ni] = f4{0.f, 0.f, 0.f, 0.f};
-    f4 ra[kLoads32], rb[kLoads32];
-    auto gload = [&](int64_t kk) {
-        const float* pa = aop(kk);
-        const float* pb = bop(kk);
-#pragma unroll
-        for (int q = 0; q < kLoads32; ++q) {
-            ra[q] = *reinterpret_cast<const f4*>(pa + (int64_t)ecol[q] * nb + erow[q]);
-            rb[q] = *reinterpret_cast<const f4*>(pb + (int64_t)ecol[q] * nb + erow[q]);
-        }
-    };
-    auto sstore = [&](int buf) {
-#pragma unroll
-        for (int q = 0; q < kLoads32; ++q) {
-            *reinterpret_cast<f4*>(As + buf * kBK32 * kLD32 + ecol[q] * kLD32 + erow[q]) = ra[q];
-            *reinterpret_cast<f4*>(Bs + buf * kBK32 * kLD32 + ecol[q] * kLD32 + erow[q]) = rb[q];
-        }
-    };
-    const int64_t K = (int64_t)k * nb;
-    if (K > 0) {
-        gload(0);
-        sstore(0);
-        __syncthreads();
-        int buf = 0;
-        const int li = lane & 15, lk = lane >> 4;
-        for (int64_t kk = 0; kk < K; kk += kBK32) {
-            const bool more = kk + kBK32 < K;
-            if (more) gload(kk + kBK32);
-            const float* as = As + buf * kBK32 * kLD32 + wm * (kB / 2) + li;
-            const float* bs = Bs + buf * kBK32 * kLD32 + wn * (kB / 2) + li;
-#pragma unroll
-            for (int ks = 0; ks < kBK32 / 4; ++ks) {
-                const int kq = ks * 4 + lk;
-                float a[4], bq[4];
-#pragma unroll
-                for (int mi = 0; mi < 4; ++mi) a[mi] = as[kq * kLD32 + mi * 16];
-#pragma unroll
-                for (int ni = 0; ni < 4; ++ni) bq[ni] = bs[kq * kLD32 + ni * 16];
-#pragma unroll
-                for (int mi = 0; mi < 4; ++mi)
-#pragma unroll
-                    for (int ni = 0; ni < 4; ++ni)
-                        acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x4f32(bq[ni], a[mi], acc[mi][ni],
-                                                                          0, 0, 0);
-            }
-            if (more) sstore(buf ^ 1);
-            __syncthreads();
-            buf ^= 1;
-        }
-    }
-    double* out = W + rt * (int64_t)nb * nb + (int64_t)bc * kB * nb + br * kB;
-#pragma unroll
-    for (int mi = 0; mi < 4; ++mi)
-#pragma unroll
-        for (int ni = 0; ni < 4; ++ni)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int row = wm * (kB / 2) + mi * 16 + (lane & 15);
-                const int col = wn * (kB / 2) + ni * 16 + 4 * (lane >> 4) + v;
-                out[(int64_t)col * nb + row] -= (double)acc[mi][ni][v];
-            }
-}
-
-// ---------------------------------------------------------------------------
 // Finalize the tiles below the diagonal of column k: amax, then rounding to
 // the tile's class with its scale, and the operand copies.
 // ---------------------------------------------------------------------------
@@ -447,9 +339,11 @@ __global__ __launch_bounds__(kThreads) void tile_amax_kernel(const double* __res
 
 // One workgroup per 64 x 64 block of a new tile: round to the tile's
 // class with its scale into storage (column-major), then write the operand
-// copies: binary32 values column-major for FP32, and for FP16 / BF16 / FP8
-// the class's bits with the copy's own scale, transposed through LDS so the
-// copy is row-major (64 consecutive k per row and block).
+// copies with the copy's own scale, transposed through LDS so each copy is
+// row-major (64 consecutive k per row and block): the class's bits for
+// FP16 / BF16 / FP8, and for FP32 the binary32 value split into an FP16 hi
+// plane and an FP16 lo plane (the lo plane nb * nb halves after the hi
+// plane; the scale is chosen for FP16's range).
 constexpr int kCB = 64;
 constexpr int kCPitch = kCB * 2 + 16;  // bytes per staged copy row
 
@@ -457,7 +351,7 @@ __global__ __launch_bounds__(kThreads) void tile_cast_kernel(
     const double* __restrict__ W, int Nt, int nb, int k, const double* __restrict__ part,
     char* __restrict__ storage, const int64_t* __restrict__ toff, const uint8_t* __restrict__ tcls,
     int* __restrict__ tscl, const int64_t* __restrict__ shoff, int* __restrict__ cscl) {
-    __shared__ __attribute__((aligned(16))) uint8_t stage[3][kCB * kCPitch];
+    __shared__ __attribute__((aligned(16))) uint8_t stage[5][kCB * kCPitch];
     const int rt = blockIdx.z;  // tile k + 1 + rt of column k
     const int r0 = blockIdx.x * kCB, c0 = blockIdx.y * kCB;
     const int64_t t = tile_off(Nt, k + 1 + rt, k);
@@ -472,8 +366,8 @@ __global__ __launch_bounds__(kThreads) void tile_cast_kernel(
 #pragma unroll
     for (int c2 = 1; c2 <= 4; ++c2) {
         const int64_t o = shoff[t * 4 + (c2 - 1)];
-        copy[c2] = (o >= 0 && !(c2 == kFP32 && c == kFP32)) ? storage + o : nullptr;
-        ce[c2] = class_scale(amax_h, c2);
+        copy[c2] = o >= 0 ? storage + o : nullptr;
+        ce[c2] = class_scale(amax_h, c2 == kFP32 ? kFP16 : c2);
     }
     if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
         tscl[t] = e;
@@ -488,7 +382,14 @@ __global__ __launch_bounds__(kThreads) void tile_cast_kernel(
         const double r = round_to_class(ldexp(src[i], -e), c);
         store_elem(dst, i, c, r);
         const double v = ldexp(r, e);  // the stored factor value
-        if (copy[kFP32]) reinterpret_cast<float*>(copy[kFP32])[i] = (float)round_to_class(v, kFP32);
+        if (copy[kFP32]) {
+            // x - hi is exact in binary64; hi and lo saturate like any FP16 value
+            const double x = ldexp(round_to_class(v, kFP32), -ce[kFP32]);
+            const double hi = round_to_class(x, kFP16);
+            *reinterpret_cast<uint16_t*>(&stage[3][tx * kCPitch + 2 * cl]) = enc_fp16(hi);
+            *reinterpret_cast<uint16_t*>(&stage[4][tx * kCPitch + 2 * cl]) =
+                enc_fp16(round_to_class(x - hi, kFP16));
+        }
         if (copy[kFP16]) {
             const uint16_t b = enc_fp16(round_to_class(ldexp(v, -ce[kFP16]), kFP16));
             *reinterpret_cast<uint16_t*>(&stage[0][tx * kCPitch + 2 * cl]) = b;
@@ -503,15 +404,16 @@ __global__ __launch_bounds__(kThreads) void tile_cast_kernel(
     __syncthreads();
     // row-major copies: row r0 + rr holds k = c0 .. c0 + 63 contiguously
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
-        const int c2 = kFP16 + q;
+    for (int q = 0; q < 5; ++q) {
+        const int c2 = q < 3 ? kFP16 + q : kFP32;
         if (!copy[c2]) continue;
-        const int eb = fmt_bytes(c2);
+        const int eb = q < 3 ? fmt_bytes(c2) : 2;
+        char* dc = copy[c2] + (q == 4 ? (int64_t)nb * nb * 2 : 0);
         const int per_row = kCB * eb / 16;  // 16-byte chunks per row
         for (int ch = threadIdx.x; ch < kCB * per_row; ch += kThreads) {
             const int rr = ch / per_row, cc = ch - rr * per_row;
             const uint4 v = *reinterpret_cast<const uint4*>(&stage[q][rr * kCPitch + cc * 16]);
-            *reinterpret_cast<uint4*>(copy[c2] + ((int64_t)(r0 + rr) * nb + c0) * eb + cc * 16) = v;
+            *reinterpret_cast<uint4*>(dc + ((int64_t)(r0 + rr) * nb + c0) * eb + cc * 16) = v;
         }
     }
 }
@@ -693,6 +595,163 @@ __global__ __launch_bounds__(kGemmThreads, 2) void mxp_gemm_narrow_kernel(
             }
 }
 
+// ---------------------------------------------------------------------------
+// FP32 group on the FP16 MFMA, with the two-term split of each operand
+// (described at the top of this file). Per stage, 32 k of each of the four
+// planes (A hi, A lo, B hi, B lo) are staged through LDS as 128 rows of 64
+// bytes (an 80-byte pitch puts the 16 rows one lane group reads in distinct
+// banks); lane l takes row l % 16 and k = 8 (l / 16) .. 8 (l / 16) + 7.
+// Three v_mfma_f32_16x16x32_f16 per 16 x 16 block and stage; the products of
+// one tile column n are folded into the accumulator with the copies' scales
+// 2^(e_a + e_b) (ldexp per element, so no scale underflows on its own).
+// ---------------------------------------------------------------------------
+constexpr int kSK = 32;           // k per stage
+constexpr int kSPitch = 64 + 16;  // bytes per LDS row
+
+struct Pair {
+    u4v v0, v1;
+};
+__device__ __forceinline__ void load_pair(const uint8_t* p, int64_t step, Pair& q) {
+    q.v0 = *reinterpret_cast<const u4v*>(p);
+    q.v1 = *reinterpret_cast<const u4v*>(p + step);
+}
+__device__ __forceinline__ void store_pair(uint8_t* p, int step, const Pair& q) {
+    *reinterpret_cast<u4v*>(p) = q.v0;
+    *reinterpret_cast<u4v*>(p + step) = q.v1;
+}
+
+__global__ __launch_bounds__(kGemmThreads, 2) void mxp_gemm_split_kernel(
+    double* __restrict__ W, int Nt, int nb, int k, const int* __restrict__ rows, int nrows,
+    const char* __restrict__ storage, const int64_t* __restrict__ shoff,
+    const int* __restrict__ cscl) {
+    __shared__ __attribute__((aligned(16))) uint8_t lds[2][4][kB * kSPitch];
+    const int T = nb / kB;
+    const int64_t total = (int64_t)nrows * T * T;
+    const int64_t b = xcd_remap_m(blockIdx.x, total);
+    int64_t rt;
+    int br, bc;
+    group_block(b, T, false, rows, rt, br, bc);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave & 1, wn = wave >> 1;
+    const int li = lane & 15, lg = lane >> 4;
+    const NarrowOp aop{storage, shoff, cscl, kFP32, Nt, nb, k + rt, (int64_t)br * kB};
+    const NarrowOp bop{storage, shoff, cscl, kFP32, Nt, nb, k, (int64_t)bc * kB};
+    const int spt = nb / kSK;  // stages per tile column
+    const int ns = k * spt;
+    // each thread moves 2 x 16 bytes per plane per stage: rows tid / 4 and
+    // tid / 4 + 64, byte column 16 (tid % 4) of the 64-byte stage row
+    const int lrow = tid >> 2, lcol = (tid & 3) * 16;
+    const int64_t gstep = (int64_t)64 * nb * 2;
+    const int64_t lofs = (int64_t)lrow * nb * 2 + lcol;
+    const int64_t plane = (int64_t)nb * nb * 2;  // lo plane after the hi plane
+    const int so = lrow * kSPitch + lcol;
+    Pair rah, ral, rbh, rbl;
+    f4 acc[4][4], part[4][4];
+#pragma unroll
+    for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 4; ++ni) {
+            acc[mi][ni] = f4{0.f, 0.f, 0.f, 0.f};
+            part[mi][ni] = f4{0.f, 0.f, 0.f, 0.f};
+        }
+    if (ns > 0) {
+        {
+            const uint8_t* pa = aop.rows(0, 2) + lofs;
+            const uint8_t* pb = bop.rows(0, 2) + lofs;
+            load_pair(pa, gstep, rah);
+            load_pair(pa + plane, gstep, ral);
+            load_pair(pb, gstep, rbh);
+            load_pair(pb + plane, gstep, rbl);
+        }
+        store_pair(&lds[0][0][so], 64 * kSPitch, rah);
+        store_pair(&lds[0][1][so], 64 * kSPitch, ral);
+        store_pair(&lds[0][2][so], 64 * kSPitch, rbh);
+        store_pair(&lds[0][3][so], 64 * kSPitch, rbl);
+        __syncthreads();
+        int buf = 0;
+        for (int g = 0; g < ns; ++g) {
+            const bool more = g + 1 < ns;
+            if (more) {
+                const int n1 = (g + 1) / spt, st1 = (g + 1) - n1 * spt;
+                const int64_t o = lofs + (int64_t)st1 * kSK * 2;
+                const uint8_t* pa = aop.rows(n1, 2) + o;
+                const uint8_t* pb = bop.rows(n1, 2) + o;
+                load_pair(pa, gstep, rah);
+                load_pair(pa + plane, gstep, ral);
+                load_pair(pb, gstep, rbh);
+                load_pair(pb + plane, gstep, rbl);
+            }
+            const int ao = (wm * 64 + li) * kSPitch + 16 * lg;
+            const int bo = (wn * 64 + li) * kSPitch + 16 * lg;
+            u4v xa[4], xb[4], ya[4];
+#pragma unroll
+            for (int mi = 0; mi < 4; ++mi)
+                xa[mi] = *reinterpret_cast<const u4v*>(&lds[buf][0][ao + mi * 16 * kSPitch]);
+#pragma unroll
+            for (int ni = 0; ni < 4; ++ni)
+                xb[ni] = *reinterpret_cast<const u4v*>(&lds[buf][2][bo + ni * 16 * kSPitch]);
+#pragma unroll
+            for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+                for (int ni = 0; ni < 4; ++ni)
+                    part[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
+                        __builtin_bit_cast(h8v, xb[ni]), __builtin_bit_cast(h8v, xa[mi]),
+                        part[mi][ni], 0, 0, 0);
+#pragma unroll
+            for (int mi = 0; mi < 4; ++mi)
+                ya[mi] = *reinterpret_cast<const u4v*>(&lds[buf][1][ao + mi * 16 * kSPitch]);
+#pragma unroll
+            for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+                for (int ni = 0; ni < 4; ++ni)
+                    part[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
+                        __builtin_bit_cast(h8v, xb[ni]), __builtin_bit_cast(h8v, ya[mi]),
+                        part[mi][ni], 0, 0, 0);
+#pragma unroll
+            for (int ni = 0; ni < 4; ++ni)
+                xb[ni] = *reinterpret_cast<const u4v*>(&lds[buf][3][bo + ni * 16 * kSPitch]);
+#pragma unroll
+            for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+                for (int ni = 0; ni < 4; ++ni)
+                    part[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
+                        __builtin_bit_cast(h8v, xb[ni]), __builtin_bit_cast(h8v, xa[mi]),
+                        part[mi][ni], 0, 0, 0);
+            if ((g + 1) % spt == 0) {  // tile column n done: fold with its scales
+                const int n = g / spt;
+                const int sc = aop.scale(n) + bop.scale(n);
+#pragma unroll
+                for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+                    for (int ni = 0; ni < 4; ++ni) {
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) acc[mi][ni][v] += ldexpf(part[mi][ni][v], sc);
+                        part[mi][ni] = f4{0.f, 0.f, 0.f, 0.f};
+                    }
+            }
+            if (more) {
+                store_pair(&lds[buf ^ 1][0][so], 64 * kSPitch, rah);
+                store_pair(&lds[buf ^ 1][1][so], 64 * kSPitch, ral);
+                store_pair(&lds[buf ^ 1][2][so], 64 * kSPitch, rbh);
+                store_pair(&lds[buf ^ 1][3][so], 64 * kSPitch, rbl);
+            }
+            __syncthreads();
+            buf ^= 1;
+        }
+    }
+    double* out = W + rt * (int64_t)nb * nb + (int64_t)bc * kB * nb + br * kB;
+#pragma unroll
+    for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 4; ++ni)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = wm * (kB / 2) + mi * 16 + li;
+                const int col = wn * (kB / 2) + ni * 16 + 4 * lg + v;
+                out[(int64_t)col * nb + row] -= (double)acc[mi][ni][v];
+            }
+}
+
 }  // namespace
 
 // Split count of an FP64 group launch: the forward panel's time model
@@ -741,12 +800,13 @@ hipError_t launch_mxp_gemm_f64(hipStream_t s, double* W, int Nt, int nb, int k, 
 }
 
 hipError_t launch_mxp_gemm_f32(hipStream_t s, double* W, int Nt, int nb, int k, const int* rows,
-                               int nrows, int cls, const char* storage, const int64_t* shoff) {
+                               int nrows, const char* storage, const int64_t* shoff,
+                               const int* cscl) {
     const int64_t T = nb / kB;
     const int64_t total = (int64_t)nrows * T * T;
     if (total == 0 || k == 0) return hipSuccess;
-    hipLaunchKernelGGL(mxp_gemm_f32_kernel, dim3((unsigned)total), dim3(kGemmThreads), 0, s, W, Nt,
-                       nb, k, rows, nrows, cls, storage, shoff);
+    hipLaunchKernelGGL(mxp_gemm_split_kernel, dim3((unsigned)total), dim3(kGemmThreads), 0, s, W,
+                       Nt, nb, k, rows, nrows, storage, shoff, cscl);
     return hipGetLastError();
 }
 

@@ -146,10 +146,10 @@ tc_status check_ws(tc_ctx* ctx, int64_t n, int nb) {
 // in packed order; then come the operand copies Q_c(Lh_t) for every tile t
 // and low class c that the static schedule multiplies it in (as the A
 // operand of tile (m, k), class c = class(m, k), n < k < m, or as the B
-// operand of the tiles (m', m), m' > m): binary32 values, column-major, for
-// FP32; the class's own bits with a per-copy power-of-two scale, row-major
-// (k contiguous, the MFMA operand order), for FP16, BF16 and FP8. Then the
-// device tables.
+// operand of the tiles (m', m), m' > m), row-major (k contiguous, the MFMA
+// operand order) with a per-copy power-of-two scale: the class's own bits
+// for FP16, BF16 and FP8, and for FP32 the binary32 value split into two
+// FP16 planes (hi, lo). Then the device tables.
 struct Plan {
     int Nt = 0, nb = 0;
     int64_t ntiles = 0;
@@ -201,12 +201,9 @@ bool make_plan(int64_t n, int nb, const uint8_t* map, Plan& P) {
             const int64_t t = tc::tile_off(Nt, m, n2);
             for (int c = 1; c <= 4; ++c) {
                 if (!(need & (1u << c))) continue;
-                if (c == TC_FP32 && P.cls[t] == TC_FP32) {
-                    P.shoff[t * 4 + c - 1] = P.toff[t];  // the stored tile is the copy
-                } else {
-                    P.shoff[t * 4 + c - 1] = (int64_t)off;
-                    off += align_up(tb * (c == TC_FP32 ? sizeof(float) : (size_t)tc::fmt_bytes(c)));
-                }
+                P.shoff[t * 4 + c - 1] = (int64_t)off;
+                // FP32: two FP16 planes (hi, lo)
+                off += align_up(tb * (c == TC_FP32 ? 4 : (size_t)tc::fmt_bytes(c)));
             }
         }
     }
@@ -338,7 +335,7 @@ int64_t tc_tile_offset(int32_t Nt, int32_t i, int32_t j) {
     return tc::tile_off(Nt, i, j);
 }
 
-const char* tc_version(void) { return "tilechol 0.2 (gfx950, FP64/FP32 MFMA, mixed precision)"; }
+const char* tc_version(void) { return "tilechol 0.3 (gfx950, FP64 MFMA, mixed precision on FP16/BF16/FP8 MFMA)"; }
 
 const char* tc_last_error(void) { return g_err.c_str(); }
 
@@ -656,8 +653,8 @@ tc_status factorize_mixed(tc_ctx* ctx, int64_t n, int nb, const double* A, const
                 used[a] = true;
                 const int* lc = d_lists + ((size_t)k * 5 + c) * Nt;
                 if (c == TC_FP32)
-                    TC_HIP(tc::launch_mxp_gemm_f32(ctx->aux[a], W, Nt, nb, k, lc, cnt, c, storage,
-                                                   d_shoff));
+                    TC_HIP(tc::launch_mxp_gemm_f32(ctx->aux[a], W, Nt, nb, k, lc, cnt, storage,
+                                                   d_shoff, d_cscl));
                 else
                     TC_HIP(tc::launch_mxp_gemm_narrow(ctx->aux[a], W, Nt, nb, k, lc, cnt, c, storage,
                                                       d_shoff, d_cscl));

@@ -93,21 +93,22 @@ int bwd_splits(int64_t rows);
 hipError_t launch_logdet_partials(hipStream_t s, const TileView& L, double* partial);
 
 // Mixed precision (mxp.hip): class-group panel updates into the working
-// column W (binary64, tile-strided rows, W[0] = diagonal tile), and the
-// finalize step that rounds column k's new tiles into storage.
-hipError_t launch_mxp_gemm_f64(hipStream_t s, double* W, int Nt, int nb, int k, const int* rows,
-                               int nrows, bool diag, const char* storage, const int64_t* toff,
-                               const uint8_t* tcls, const int* tscl, double* partial,
-                               size_t partial_cap);
+// column W (binary64, tile-strided rows, W[0] = diagonal tile) over the
+// tile columns n in [nbeg, nend) of column k, and the finalize step that
+// rounds column k's new tiles into storage.
+hipError_t launch_mxp_gemm_f64(hipStream_t s, double* W, int Nt, int nb, int k, int nbeg, int nend,
+                               const int* rows, int nrows, bool diag, const char* storage,
+                               const int64_t* toff, const uint8_t* tcls, const int* tscl,
+                               double* partial, size_t partial_cap);
 // FP32 group: FP16 MFMA over the two-plane (hi, lo) split copies.
-hipError_t launch_mxp_gemm_f32(hipStream_t s, double* W, int Nt, int nb, int k, const int* rows,
-                               int nrows, const char* storage, const int64_t* shoff,
-                               const int* cscl);
+hipError_t launch_mxp_gemm_f32(hipStream_t s, double* W, int Nt, int nb, int k, int nbeg, int nend,
+                               const int* rows, int nrows, const char* storage,
+                               const int64_t* shoff, const int* cscl);
 // FP16 / BF16 / FP8 group: narrow-format MFMA over the class's operand
 // copies (row-major bits, per-copy scale cscl), FP32 accumulation.
-hipError_t launch_mxp_gemm_narrow(hipStream_t s, double* W, int Nt, int nb, int k, const int* rows,
-                                  int nrows, int cls, const char* storage, const int64_t* shoff,
-                                  const int* cscl);
+hipError_t launch_mxp_gemm_narrow(hipStream_t s, double* W, int Nt, int nb, int k, int nbeg,
+                                  int nend, const int* rows, int nrows, int cls,
+                                  const char* storage, const int64_t* shoff, const int* cscl);
 hipError_t launch_mxp_finalize(hipStream_t s, const double* W, int Nt, int nb, int k, double* part,
                                char* storage, const int64_t* toff, const uint8_t* tcls, int* tscl,
                                const int64_t* shoff, int* cscl);

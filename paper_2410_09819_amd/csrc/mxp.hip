@@ -240,15 +240,16 @@ __device__ __forceinline__ void group_block(int64_t b, int T, bool diag, const i
     }
 }
 
-// FP64 group of column k: W[rt] -= sum_n Lh(k+rt, n) Lh(k, n)^T for rt in
-// the diagonal tile (lower blocks, when diag) and the listed row tiles.
-// splits > 1: split s covers K range [s*kchunk, (s+1)*kchunk) and writes its
-// 128 x 128 block to partial[(s * nblocks + b) * 128^2] (column-major).
+// FP64 group of column k: W[rt] -= sum_n Lh(k+rt, n) Lh(k, n)^T over the K
+// range [K0, K1) (tile columns n of the range), for rt in the diagonal tile
+// (lower blocks, when diag) and the listed row tiles. splits > 1: split s
+// covers [K0 + s*kchunk, K0 + (s+1)*kchunk) and writes its 128 x 128 block
+// to partial[(s * nblocks + b) * 128^2] (column-major).
 __global__ __launch_bounds__(kGemmThreads, 2) void mxp_gemm_f64_kernel(
-    double* __restrict__ W, int Nt, int nb, int k, const int* __restrict__ rows, int nrows, int diag,
-    const char* __restrict__ storage, const int64_t* __restrict__ toff,
-    const uint8_t* __restrict__ tcls, const int* __restrict__ tscl, int splits, int64_t kchunk,
-    double* __restrict__ partial) {
+    double* __restrict__ W, int Nt, int nb, int k, int64_t K0, int64_t K1,
+    const int* __restrict__ rows, int nrows, int diag, const char* __restrict__ storage,
+    const int64_t* __restrict__ toff, const uint8_t* __restrict__ tcls,
+    const int* __restrict__ tscl, int splits, int64_t kchunk, double* __restrict__ partial) {
     using Tl = MfmaTile<kB, kB>;
     __shared__ double lds[Tl::LDS_DOUBLES];
     const int T = nb / kB;
@@ -259,9 +260,8 @@ __global__ __launch_bounds__(kGemmThreads, 2) void mxp_gemm_f64_kernel(
     int64_t rt;
     int br, bc;
     group_block(b, T, diag != 0, rows, rt, br, bc);
-    const int64_t K = (int64_t)k * nb;
-    const int64_t kbeg = (int64_t)split * kchunk;
-    const int64_t kend = kbeg + kchunk < K ? kbeg + kchunk : K;
+    const int64_t kbeg = K0 + (int64_t)split * kchunk;
+    const int64_t kend = kbeg + kchunk < K1 ? kbeg + kchunk : K1;
     d4 acc[Tl::MI][Tl::NI];
 #pragma unroll
     for (int mi = 0; mi < Tl::MI; ++mi)
@@ -468,8 +468,8 @@ __device__ __forceinline__ void store_quad(uint8_t* p, int step, const Quad& q) 
 
 template <int CLS>
 __global__ __launch_bounds__(kGemmThreads, 2) void mxp_gemm_narrow_kernel(
-    double* __restrict__ W, int Nt, int nb, int k, const int* __restrict__ rows, int nrows,
-    const char* __restrict__ storage, const int64_t* __restrict__ shoff,
+    double* __restrict__ W, int Nt, int nb, int k, int nbeg, int nend, const int* __restrict__ rows,
+    int nrows, const char* __restrict__ storage, const int64_t* __restrict__ shoff,
     const int* __restrict__ cscl) {
     constexpr int EB = CLS == kFP8 ? 1 : 2;
     constexpr int SK = 128 / EB;  // k per stage
@@ -486,7 +486,7 @@ __global__ __launch_bounds__(kGemmThreads, 2) void mxp_gemm_narrow_kernel(
     const NarrowOp aop{storage, shoff, cscl, CLS, Nt, nb, k + rt, (int64_t)br * kB};
     const NarrowOp bop{storage, shoff, cscl, CLS, Nt, nb, k, (int64_t)bc * kB};
     const int spt = nb / SK;  // stages per tile column
-    const int ns = k * spt;
+    const int g0 = nbeg * spt, g1 = nend * spt;
     // each thread moves 4 x 16 bytes per operand per stage: rows tid / 8 +
     // 32 q, byte column 16 (tid % 8) of the 128-byte stage row
     const int lrow = tid >> 3, lcol = (tid & 7) * 16;
@@ -501,15 +501,15 @@ __global__ __launch_bounds__(kGemmThreads, 2) void mxp_gemm_narrow_kernel(
             acc[mi][ni] = f4{0.f, 0.f, 0.f, 0.f};
             part[mi][ni] = f4{0.f, 0.f, 0.f, 0.f};
         }
-    if (ns > 0) {
-        load_quad(aop.rows(0, EB) + lofs, gstep, ra);
-        load_quad(bop.rows(0, EB) + lofs, gstep, rb);
+    if (g1 > g0) {
+        load_quad(aop.rows(nbeg, EB) + lofs, gstep, ra);
+        load_quad(bop.rows(nbeg, EB) + lofs, gstep, rb);
         store_quad(&lds[0][0][lrow * kNPitch + lcol], 32 * kNPitch, ra);
         store_quad(&lds[0][1][lrow * kNPitch + lcol], 32 * kNPitch, rb);
         __syncthreads();
         int buf = 0;
-        for (int g = 0; g < ns; ++g) {
-            const bool more = g + 1 < ns;
+        for (int g = g0; g < g1; ++g) {
+            const bool more = g + 1 < g1;
             if (more) {
                 const int n1 = (g + 1) / spt, st1 = (g + 1) - n1 * spt;
                 const int64_t o = lofs + (int64_t)st1 * SK * EB;
@@ -621,8 +621,8 @@ __device__ __forceinline__ void store_pair(uint8_t* p, int step, const Pair& q) 
 }
 
 __global__ __launch_bounds__(kGemmThreads, 2) void mxp_gemm_split_kernel(
-    double* __restrict__ W, int Nt, int nb, int k, const int* __restrict__ rows, int nrows,
-    const char* __restrict__ storage, const int64_t* __restrict__ shoff,
+    double* __restrict__ W, int Nt, int nb, int k, int nbeg, int nend, const int* __restrict__ rows,
+    int nrows, const char* __restrict__ storage, const int64_t* __restrict__ shoff,
     const int* __restrict__ cscl) {
     __shared__ __attribute__((aligned(16))) uint8_t lds[2][4][kB * kSPitch];
     const int T = nb / kB;
@@ -637,7 +637,7 @@ __global__ __launch_bounds__(kGemmThreads, 2) void mxp_gemm_split_kernel(
     const NarrowOp aop{storage, shoff, cscl, kFP32, Nt, nb, k + rt, (int64_t)br * kB};
     const NarrowOp bop{storage, shoff, cscl, kFP32, Nt, nb, k, (int64_t)bc * kB};
     const int spt = nb / kSK;  // stages per tile column
-    const int ns = k * spt;
+    const int g0 = nbeg * spt, g1 = nend * spt;
     // each thread moves 2 x 16 bytes per plane per stage: rows tid / 4 and
     // tid / 4 + 64, byte column 16 (tid % 4) of the 64-byte stage row
     const int lrow = tid >> 2, lcol = (tid & 3) * 16;
@@ -654,10 +654,10 @@ __global__ __launch_bounds__(kGemmThreads, 2) void mxp_gemm_split_kernel(
             acc[mi][ni] = f4{0.f, 0.f, 0.f, 0.f};
             part[mi][ni] = f4{0.f, 0.f, 0.f, 0.f};
         }
-    if (ns > 0) {
+    if (g1 > g0) {
         {
-            const uint8_t* pa = aop.rows(0, 2) + lofs;
-            const uint8_t* pb = bop.rows(0, 2) + lofs;
+            const uint8_t* pa = aop.rows(nbeg, 2) + lofs;
+            const uint8_t* pb = bop.rows(nbeg, 2) + lofs;
             load_pair(pa, gstep, rah);
             load_pair(pa + plane, gstep, ral);
             load_pair(pb, gstep, rbh);
@@ -669,8 +669,8 @@ __global__ __launch_bounds__(kGemmThreads, 2) void mxp_gemm_split_kernel(
         store_pair(&lds[0][3][so], 64 * kSPitch, rbl);
         __syncthreads();
         int buf = 0;
-        for (int g = 0; g < ns; ++g) {
-            const bool more = g + 1 < ns;
+        for (int g = g0; g < g1; ++g) {
+            const bool more = g + 1 < g1;
             if (more) {
                 const int n1 = (g + 1) / spt, st1 = (g + 1) - n1 * spt;
                 const int64_t o = lofs + (int64_t)st1 * kSK * 2;
@@ -779,19 +779,19 @@ static int mxp_f64_splits(int64_t nblocks, int64_t K, size_t cap) {
     return bests;
 }
 
-hipError_t launch_mxp_gemm_f64(hipStream_t s, double* W, int Nt, int nb, int k, const int* rows,
-                               int nrows, bool diag, const char* storage, const int64_t* toff,
-                               const uint8_t* tcls, const int* tscl, double* partial,
-                               size_t partial_cap) {
+hipError_t launch_mxp_gemm_f64(hipStream_t s, double* W, int Nt, int nb, int k, int nbeg, int nend,
+                               const int* rows, int nrows, bool diag, const char* storage,
+                               const int64_t* toff, const uint8_t* tcls, const int* tscl,
+                               double* partial, size_t partial_cap) {
     const int64_t T = nb / kB;
     const int64_t total = (diag ? T * (T + 1) / 2 : 0) + (int64_t)nrows * T * T;
-    if (total == 0 || k == 0) return hipSuccess;
-    const int64_t K = (int64_t)k * nb;
+    if (total == 0 || nend <= nbeg) return hipSuccess;
+    const int64_t K0 = (int64_t)nbeg * nb, K1 = (int64_t)nend * nb, K = K1 - K0;
     const int splits = mxp_f64_splits(total, K, partial_cap);
     const int64_t kchunk = (((K + splits - 1) / splits + 15) / 16) * 16;
     hipLaunchKernelGGL(mxp_gemm_f64_kernel, dim3((unsigned)(total * splits)), dim3(kGemmThreads), 0,
-                       s, W, Nt, nb, k, rows, nrows, diag ? 1 : 0, storage, toff, tcls, tscl, splits,
-                       kchunk, partial);
+                       s, W, Nt, nb, k, K0, K1, rows, nrows, diag ? 1 : 0, storage, toff, tcls, tscl,
+                       splits, kchunk, partial);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || splits == 1) return e;
     hipLaunchKernelGGL(mxp_group_reduce_kernel, dim3((unsigned)total), dim3(256), 0, s, W, nb, rows,
@@ -799,33 +799,33 @@ hipError_t launch_mxp_gemm_f64(hipStream_t s, double* W, int Nt, int nb, int k, 
     return hipGetLastError();
 }
 
-hipError_t launch_mxp_gemm_f32(hipStream_t s, double* W, int Nt, int nb, int k, const int* rows,
-                               int nrows, const char* storage, const int64_t* shoff,
-                               const int* cscl) {
+hipError_t launch_mxp_gemm_f32(hipStream_t s, double* W, int Nt, int nb, int k, int nbeg, int nend,
+                               const int* rows, int nrows, const char* storage,
+                               const int64_t* shoff, const int* cscl) {
     const int64_t T = nb / kB;
     const int64_t total = (int64_t)nrows * T * T;
-    if (total == 0 || k == 0) return hipSuccess;
+    if (total == 0 || nend <= nbeg) return hipSuccess;
     hipLaunchKernelGGL(mxp_gemm_split_kernel, dim3((unsigned)total), dim3(kGemmThreads), 0, s, W,
-                       Nt, nb, k, rows, nrows, storage, shoff, cscl);
+                       Nt, nb, k, nbeg, nend, rows, nrows, storage, shoff, cscl);
     return hipGetLastError();
 }
 
-hipError_t launch_mxp_gemm_narrow(hipStream_t s, double* W, int Nt, int nb, int k, const int* rows,
-                                  int nrows, int cls, const char* storage, const int64_t* shoff,
-                                  const int* cscl) {
+hipError_t launch_mxp_gemm_narrow(hipStream_t s, double* W, int Nt, int nb, int k, int nbeg,
+                                  int nend, const int* rows, int nrows, int cls,
+                                  const char* storage, const int64_t* shoff, const int* cscl) {
     const int64_t T = nb / kB;
     const int64_t total = (int64_t)nrows * T * T;
-    if (total == 0 || k == 0) return hipSuccess;
+    if (total == 0 || nend <= nbeg) return hipSuccess;
     const dim3 grid((unsigned)total), block(kGemmThreads);
     if (cls == kFP16)
-        hipLaunchKernelGGL(mxp_gemm_narrow_kernel<kFP16>, grid, block, 0, s, W, Nt, nb, k, rows, nrows,
-                           storage, shoff, cscl);
+        hipLaunchKernelGGL(mxp_gemm_narrow_kernel<kFP16>, grid, block, 0, s, W, Nt, nb, k, nbeg, nend,
+                           rows, nrows, storage, shoff, cscl);
     else if (cls == kBF16)
-        hipLaunchKernelGGL(mxp_gemm_narrow_kernel<kBF16>, grid, block, 0, s, W, Nt, nb, k, rows, nrows,
-                           storage, shoff, cscl);
+        hipLaunchKernelGGL(mxp_gemm_narrow_kernel<kBF16>, grid, block, 0, s, W, Nt, nb, k, nbeg, nend,
+                           rows, nrows, storage, shoff, cscl);
     else if (cls == kFP8)
-        hipLaunchKernelGGL(mxp_gemm_narrow_kernel<kFP8>, grid, block, 0, s, W, Nt, nb, k, rows, nrows,
-                           storage, shoff, cscl);
+        hipLaunchKernelGGL(mxp_gemm_narrow_kernel<kFP8>, grid, block, 0, s, W, Nt, nb, k, nbeg, nend,
+                           rows, nrows, storage, shoff, cscl);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

@@ -622,59 +622,100 @@ tc_status factorize_mixed(tc_ctx* ctx, int64_t n, int nb, const double* A, const
     }
     std::vector<int> zeros(P.ntiles, 0);
     if (tc_status s = ctx_aux_streams(ctx)) return s;
-    TC_HIP(hipEventRecord(ctx->ev0, ctx->stream));
+    while (ctx->la_ev.size() < (size_t)4 * Nt + 1) {
+        hipEvent_t e;
+        TC_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        ctx->la_ev.push_back(e);
+    }
+    // Lookahead schedule on three streams (same column order as Algorithm 1;
+    // the working column of column k is Wb[k % 2]):
+    //   aux[0]: column c's A tiles into Wb[c % 2], then its FP64 group over
+    //           tile columns [0, c-1), once column c-2 is finalized;
+    //   aux[1]: column c's FP32 / FP16 / BF16 / FP8 groups over [0, c-1);
+    //   main:   column k's groups over tile column k-1 (after both bulk
+    //           parts), POTRF, TRSM, store, finalize.
+    // So the bulk of column k+2 overlaps the critical path of column k+1.
+    // ev_f[k]: column k finalized (main); ev_c[c]: Wb filled (aux[0]);
+    // ev_b64[c], ev_blo[c]: bulk groups of column c done.
+    hipStream_t sm = ctx->stream, s64 = ctx->aux[0], slo = ctx->aux[1];
+    hipEvent_t* ev_f = ctx->la_ev.data();
+    hipEvent_t* ev_c = ev_f + Nt;
+    hipEvent_t* ev_b64 = ev_f + 2 * Nt;
+    hipEvent_t* ev_blo = ev_f + 3 * Nt;
+    hipEvent_t ev_go = ctx->la_ev[4 * Nt];
+    double* Wb[2] = {W, W + (int64_t)Nt * nb2};
+    auto col_bytes = [&](int c) { return (size_t)(Nt - c) * nb2 * sizeof(double); };
+    auto list = [&](int c, int cls) { return d_lists + ((size_t)c * 5 + cls) * Nt; };
+    auto count = [&](int c, int cls) { return lcount[(size_t)c * 5 + cls]; };
+    // the low-class groups of column c over tile columns [n0, n1) on stream st
+    auto low_groups = [&](hipStream_t st, int c, int n0, int n1) -> tc_status {
+        double* Wc = Wb[c % 2];
+        for (int cls = 1; cls <= 4; ++cls) {
+            const int cnt = count(c, cls);
+            if (!cnt) continue;
+            if (cls == TC_FP32)
+                TC_HIP(tc::launch_mxp_gemm_f32(st, Wc, Nt, nb, c, n0, n1, list(c, cls), cnt, storage,
+                                               d_shoff, d_cscl));
+            else
+                TC_HIP(tc::launch_mxp_gemm_narrow(st, Wc, Nt, nb, c, n0, n1, list(c, cls), cnt, cls,
+                                                  storage, d_shoff, d_cscl));
+        }
+        return TC_OK;
+    };
+
+    TC_HIP(hipEventRecord(ctx->ev0, sm));
     TC_HIP(hipMemcpyAsync(d_lists, lists.data(), lists.size() * sizeof(int), hipMemcpyHostToDevice,
-                          ctx->stream));
+                          sm));
     TC_HIP(hipMemcpyAsync(d_toff, P.toff.data(), P.toff.size() * sizeof(int64_t),
-                          hipMemcpyHostToDevice, ctx->stream));
+                          hipMemcpyHostToDevice, sm));
     TC_HIP(hipMemcpyAsync(d_shoff, P.shoff.data(), P.shoff.size() * sizeof(int64_t),
-                          hipMemcpyHostToDevice, ctx->stream));
-    TC_HIP(hipMemcpyAsync(d_tcls, P.cls.data(), P.cls.size(), hipMemcpyHostToDevice, ctx->stream));
+                          hipMemcpyHostToDevice, sm));
+    TC_HIP(hipMemcpyAsync(d_tcls, P.cls.data(), P.cls.size(), hipMemcpyHostToDevice, sm));
     TC_HIP(hipMemcpyAsync(d_tscl, zeros.data(), zeros.size() * sizeof(int), hipMemcpyHostToDevice,
-                          ctx->stream));
+                          sm));
     std::vector<int> zeros4((size_t)P.ntiles * 4, 0);
     TC_HIP(hipMemcpyAsync(d_cscl, zeros4.data(), zeros4.size() * sizeof(int), hipMemcpyHostToDevice,
-                          ctx->stream));
-    TC_HIP(tc::launch_zero_info(ctx->stream, d_info));
+                          sm));
+    TC_HIP(tc::launch_zero_info(sm, d_info));
+    for (int c = 0; c < 2 && c < Nt; ++c)
+        TC_HIP(hipMemcpyAsync(Wb[c], A + tc::tile_off(Nt, c, c) * nb2, col_bytes(c),
+                              hipMemcpyDeviceToDevice, sm));
+    TC_HIP(hipEventRecord(ev_go, sm));
+    TC_HIP(hipStreamWaitEvent(s64, ev_go, 0));
+    TC_HIP(hipStreamWaitEvent(slo, ev_go, 0));
     for (int k = 0; k < Nt; ++k) {
-        TC_HIP(hipMemcpyAsync(W, A + tc::tile_off(Nt, k, k) * nb2, (size_t)(Nt - k) * nb2 * sizeof(double),
-                              hipMemcpyDeviceToDevice, ctx->stream));
-        if (k > 0) {
-            // The class groups write disjoint tiles of W: the FP32 group runs
-            // on aux[0], the narrow groups on aux[1], concurrently with the
-            // FP64 group on the main stream; all join before POTRF.
-            TC_HIP(hipEventRecord(ctx->aux_ev[0], ctx->stream));
-            bool used[2] = {false, false};
-            for (int c = 1; c <= 4; ++c) {
-                const int cnt = lcount[(size_t)k * 5 + c];
-                if (!cnt) continue;
-                const int a = c == TC_FP32 ? 0 : 1;
-                if (!used[a]) TC_HIP(hipStreamWaitEvent(ctx->aux[a], ctx->aux_ev[0], 0));
-                used[a] = true;
-                const int* lc = d_lists + ((size_t)k * 5 + c) * Nt;
-                if (c == TC_FP32)
-                    TC_HIP(tc::launch_mxp_gemm_f32(ctx->aux[a], W, Nt, nb, k, lc, cnt, storage,
-                                                   d_shoff, d_cscl));
-                else
-                    TC_HIP(tc::launch_mxp_gemm_narrow(ctx->aux[a], W, Nt, nb, k, lc, cnt, c, storage,
-                                                      d_shoff, d_cscl));
-            }
-            const int* l64 = d_lists + ((size_t)k * 5 + TC_FP64) * Nt;
-            TC_HIP(tc::launch_mxp_gemm_f64(ctx->stream, W, Nt, nb, k, l64, lcount[(size_t)k * 5 + TC_FP64],
-                                           true, storage, d_toff, d_tcls, d_tscl, big,
-                                           big_cap / sizeof(double)));
-            for (int a = 0; a < 2; ++a) {
-                if (!used[a]) continue;
-                TC_HIP(hipEventRecord(ctx->aux_ev[1 + a], ctx->aux[a]));
-                TC_HIP(hipStreamWaitEvent(ctx->stream, ctx->aux_ev[1 + a], 0));
-            }
+        double* Wk = Wb[k % 2];
+        if (k >= 2) {
+            TC_HIP(hipStreamWaitEvent(sm, ev_b64[k], 0));
+            TC_HIP(hipStreamWaitEvent(sm, ev_blo[k], 0));
         }
-        if (tc_status s = potrf_rec(ctx, W, nb, 0, nb, (int64_t)k * nb, d_info, pot)) return s;
-        if (k + 1 < Nt) TC_HIP(tc::launch_trsm(ctx->stream, W + nb2, W, nb, (int64_t)(Nt - k - 1) * nb, nb));
-        TC_HIP(hipMemcpyAsync(storage + P.toff[tc::tile_off(Nt, k, k)], W, nb2 * sizeof(double),
-                              hipMemcpyDeviceToDevice, ctx->stream));
-        TC_HIP(tc::launch_mxp_finalize(ctx->stream, W, Nt, nb, k, part, storage, d_toff, d_tcls, d_tscl,
+        if (k >= 1) {  // tile column k-1 (no split-K: the partials belong to aux[0])
+            TC_HIP(tc::launch_mxp_gemm_f64(sm, Wk, Nt, nb, k, k - 1, k, list(k, TC_FP64),
+                                           count(k, TC_FP64), true, storage, d_toff, d_tcls, d_tscl,
+                                           nullptr, 0));
+            if (tc_status s = low_groups(sm, k, k - 1, k)) return s;
+        }
+        if (tc_status s = potrf_rec(ctx, Wk, nb, 0, nb, (int64_t)k * nb, d_info, pot)) return s;
+        if (k + 1 < Nt) TC_HIP(tc::launch_trsm(sm, Wk + nb2, Wk, nb, (int64_t)(Nt - k - 1) * nb, nb));
+        TC_HIP(hipMemcpyAsync(storage + P.toff[tc::tile_off(Nt, k, k)], Wk, nb2 * sizeof(double),
+                              hipMemcpyDeviceToDevice, sm));
+        TC_HIP(tc::launch_mxp_finalize(sm, Wk, Nt, nb, k, part, storage, d_toff, d_tcls, d_tscl,
                                        d_shoff, d_cscl));
+        TC_HIP(hipEventRecord(ev_f[k], sm));
+        const int c = k + 2;  // bulk of column c over tile columns [0, c-1) = [0, k]
+        if (c < Nt) {
+            TC_HIP(hipStreamWaitEvent(s64, ev_f[k], 0));
+            TC_HIP(hipMemcpyAsync(Wb[c % 2], A + tc::tile_off(Nt, c, c) * nb2, col_bytes(c),
+                                  hipMemcpyDeviceToDevice, s64));
+            TC_HIP(hipEventRecord(ev_c[c], s64));
+            TC_HIP(tc::launch_mxp_gemm_f64(s64, Wb[c % 2], Nt, nb, c, 0, c - 1, list(c, TC_FP64),
+                                           count(c, TC_FP64), true, storage, d_toff, d_tcls, d_tscl,
+                                           big, big_cap / sizeof(double)));
+            TC_HIP(hipEventRecord(ev_b64[c], s64));
+            TC_HIP(hipStreamWaitEvent(slo, ev_c[c], 0));
+            if (tc_status s = low_groups(slo, c, 0, c - 1)) return s;
+            TC_HIP(hipEventRecord(ev_blo[c], slo));
+        }
     }
     TC_HIP(hipEventRecord(ctx->ev1, ctx->stream));
     int info = 0;

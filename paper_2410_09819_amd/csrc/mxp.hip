@@ -421,14 +421,16 @@ __global__ __launch_bounds__(kThreads) void tile_cast_kernel(
 // ---------------------------------------------------------------------------
 // Narrow-format MFMA for the FP16, BF16 and FP8 groups. Operands are the
 // row-major copies: a 128-row slab of 128 bytes per row per stage (64 k of
-// FP16/BF16, 128 k of FP8) is staged through LDS; lane l of a wave takes
-// row l % 16 and 8 (16-bit) or 32 (FP8) consecutive k at 8 (l / 16) or
-// 32 (l / 16) — A and B use the same k order, which is all the MFMA needs.
-// v_mfma_f32_16x16x32_{f16,bf16} and v_mfma_scale_f32_16x16x128_f8f6f4
-// (unit scales) accumulate in FP32; lane l holds D[4(l/16) + v][l%16]
-// (checked on the device) and the blocks are computed as C^T = B A^T.
-// The per-tile copy scales 2^(e_a + e_b) are applied when the products of
-// one tile column n are folded into the FP32 accumulator.
+// FP16/BF16, 128 k of FP8) is staged through LDS in two 64-byte planes;
+// lane l of a wave takes row l % 16 and chunk l / 16 of a plane: 8 k per
+// plane for the 16-bit formats (one MFMA per plane), and the chunk of both
+// planes (32 k) for FP8 -- A and B use the same k order, which is all the
+// MFMA needs. v_mfma_f32_16x16x32_{f16,bf16} and
+// v_mfma_scale_f32_16x16x128_f8f6f4 (unit scales) accumulate in FP32; lane
+// l holds D[4(l/16) + v][l%16] (checked on the device) and the blocks are
+// computed as C^T = B A^T. The per-tile copy scales 2^(e_a + e_b) are
+// applied (ldexp per element) when the products of one tile column n are
+// folded into the FP32 accumulator.
 // ---------------------------------------------------------------------------
 typedef _Float16 h8v __attribute__((ext_vector_type(8)));
 typedef __bf16 b8v __attribute__((ext_vector_type(8)));
@@ -450,20 +452,34 @@ struct NarrowOp {
 };
 
 typedef unsigned int u4v __attribute__((ext_vector_type(4)));
+
+// LDS layout of the narrow and split kernels: an operand's stage rows are
+// held in planes of 128 rows x 64 bytes (no padding), and 16-byte chunk c of
+// row r sits at chunk c ^ ((r >> 1) & 3) of its plane row. Both the MFMA
+// operand reads (16 lanes: 16 rows, one chunk) and the stores of the
+// coalesced loads (4 lanes per row) are then free of bank conflicts on
+// gfx950 (checked with the LDS bank-conflict counter; padded pitches of 80
+// or 144 bytes are not, for the reads).
+constexpr int kPlane = kB * 64;  // bytes per plane
+__device__ __forceinline__ int swz(int r, int c) { return r * 64 + 16 * (c ^ ((r >> 1) & 3)); }
+
 struct Quad {
     u4v v0, v1, v2, v3;
 };
+// A thread's four 16-byte pieces of a 128-byte stage row: rows r and r + 64
+// (step = 64 rows), bytes c and c + 64; in LDS, plane 0 holds bytes 0..63
+// of each row and plane 1 bytes 64..127 (p = the swizzled slot of (r, c)).
 __device__ __forceinline__ void load_quad(const uint8_t* p, int64_t step, Quad& q) {
     q.v0 = *reinterpret_cast<const u4v*>(p);
     q.v1 = *reinterpret_cast<const u4v*>(p + step);
-    q.v2 = *reinterpret_cast<const u4v*>(p + 2 * step);
-    q.v3 = *reinterpret_cast<const u4v*>(p + 3 * step);
+    q.v2 = *reinterpret_cast<const u4v*>(p + 64);
+    q.v3 = *reinterpret_cast<const u4v*>(p + step + 64);
 }
-__device__ __forceinline__ void store_quad(uint8_t* p, int step, const Quad& q) {
+__device__ __forceinline__ void store_quad(uint8_t* p, const Quad& q) {
     *reinterpret_cast<u4v*>(p) = q.v0;
-    *reinterpret_cast<u4v*>(p + step) = q.v1;
-    *reinterpret_cast<u4v*>(p + 2 * step) = q.v2;
-    *reinterpret_cast<u4v*>(p + 3 * step) = q.v3;
+    *reinterpret_cast<u4v*>(p + 64 * 64) = q.v1;
+    *reinterpret_cast<u4v*>(p + kPlane) = q.v2;
+    *reinterpret_cast<u4v*>(p + kPlane + 64 * 64) = q.v3;
 }
 
 template <int CLS>
@@ -473,7 +489,7 @@ __global__ __launch_bounds__(kGemmThreads, 2) void mxp_gemm_narrow_kernel(
     const int* __restrict__ cscl) {
     constexpr int EB = CLS == kFP8 ? 1 : 2;
     constexpr int SK = 128 / EB;  // k per stage
-    __shared__ __attribute__((aligned(16))) uint8_t lds[2][2][kB * kNPitch];
+    __shared__ __attribute__((aligned(16))) uint8_t lds[2][2][2 * kPlane];  // [buf][A, B][plane]
     const int T = nb / kB;
     const int64_t total = (int64_t)nrows * T * T;
     const int64_t b = xcd_remap_m(blockIdx.x, total);
@@ -487,11 +503,14 @@ __global__ __launch_bounds__(kGemmThreads, 2) void mxp_gemm_narrow_kernel(
     const NarrowOp bop{storage, shoff, cscl, CLS, Nt, nb, k, (int64_t)bc * kB};
     const int spt = nb / SK;  // stages per tile column
     const int g0 = nbeg * spt, g1 = nend * spt;
-    // each thread moves 4 x 16 bytes per operand per stage: rows tid / 8 +
-    // 32 q, byte column 16 (tid % 8) of the 128-byte stage row
-    const int lrow = tid >> 3, lcol = (tid & 7) * 16;
-    const int64_t gstep = (int64_t)32 * nb * EB;  // 32 rows further
-    const int64_t lofs = (int64_t)lrow * nb * EB + lcol;
+    // thread t moves rows t / 4 and t / 4 + 64, bytes 16 (t % 4) and 64 more
+    // of the 128-byte stage row (4 lanes read 64 contiguous bytes of a row)
+    const int lrow = tid >> 2, lch = tid & 3;
+    const int64_t gstep = (int64_t)64 * nb * EB;  // 64 rows further
+    const int64_t lofs = (int64_t)lrow * nb * EB + 16 * lch;
+    const int so = swz(lrow, lch);
+    // MFMA operand slot of this lane: row 16 i + l % 16, chunk l / 16
+    const int ro = swz(li, lg);
     Quad ra, rb;
     f4 acc[4][4], part[4][4];
 #pragma unroll
@@ -504,8 +523,8 @@ __global__ __launch_bounds__(kGemmThreads, 2) void mxp_gemm_narrow_kernel(
     if (g1 > g0) {
         load_quad(aop.rows(nbeg, EB) + lofs, gstep, ra);
         load_quad(bop.rows(nbeg, EB) + lofs, gstep, rb);
-        store_quad(&lds[0][0][lrow * kNPitch + lcol], 32 * kNPitch, ra);
-        store_quad(&lds[0][1][lrow * kNPitch + lcol], 32 * kNPitch, rb);
+        store_quad(&lds[0][0][so], ra);
+        store_quad(&lds[0][1][so], rb);
         __syncthreads();
         int buf = 0;
         for (int g = g0; g < g1; ++g) {
@@ -516,20 +535,22 @@ __global__ __launch_bounds__(kGemmThreads, 2) void mxp_gemm_narrow_kernel(
                 load_quad(aop.rows(n1, EB) + o, gstep, ra);
                 load_quad(bop.rows(n1, EB) + o, gstep, rb);
             }
-            const uint8_t* as = &lds[buf][0][(wm * 64 + li) * kNPitch];
-            const uint8_t* bs = &lds[buf][1][(wn * 64 + li) * kNPitch];
+            const uint8_t* as = &lds[buf][0][wm * 64 * 64 + ro];
+            const uint8_t* bs = &lds[buf][1][wn * 64 * 64 + ro];
             if constexpr (CLS == kFP8) {
+                // lane group l / 16 takes chunk l / 16 of both planes (32 k);
+                // A and B use the same k order
                 i8v a[4], bq[4];
 #pragma unroll
                 for (int mi = 0; mi < 4; ++mi) {
-                    const u4v* p = reinterpret_cast<const u4v*>(as + mi * 16 * kNPitch + 32 * lg);
-                    const u4v x = p[0], y = p[1];
+                    const u4v x = *reinterpret_cast<const u4v*>(as + mi * 16 * 64);
+                    const u4v y = *reinterpret_cast<const u4v*>(as + kPlane + mi * 16 * 64);
                     a[mi] = i8v{(int)x.x, (int)x.y, (int)x.z, (int)x.w, (int)y.x, (int)y.y, (int)y.z, (int)y.w};
                 }
 #pragma unroll
                 for (int ni = 0; ni < 4; ++ni) {
-                    const u4v* p = reinterpret_cast<const u4v*>(bs + ni * 16 * kNPitch + 32 * lg);
-                    const u4v x = p[0], y = p[1];
+                    const u4v x = *reinterpret_cast<const u4v*>(bs + ni * 16 * 64);
+                    const u4v y = *reinterpret_cast<const u4v*>(bs + kPlane + ni * 16 * 64);
                     bq[ni] = i8v{(int)x.x, (int)x.y, (int)x.z, (int)x.w, (int)y.x, (int)y.y, (int)y.z, (int)y.w};
                 }
 #pragma unroll
@@ -540,14 +561,14 @@ __global__ __launch_bounds__(kGemmThreads, 2) void mxp_gemm_narrow_kernel(
                             bq[ni], a[mi], part[mi][ni], 0, 0, 0, 127, 0, 127);
             } else {
 #pragma unroll
-                for (int ks = 0; ks < 2; ++ks) {
+                for (int ks = 0; ks < 2; ++ks) {  // plane ks: k 32 ks .. 32 ks + 31
                     u4v a[4], bq[4];
 #pragma unroll
                     for (int mi = 0; mi < 4; ++mi)
-                        a[mi] = *reinterpret_cast<const u4v*>(as + mi * 16 * kNPitch + ks * 64 + 16 * lg);
+                        a[mi] = *reinterpret_cast<const u4v*>(as + ks * kPlane + mi * 16 * 64);
 #pragma unroll
                     for (int ni = 0; ni < 4; ++ni)
-                        bq[ni] = *reinterpret_cast<const u4v*>(bs + ni * 16 * kNPitch + ks * 64 + 16 * lg);
+                        bq[ni] = *reinterpret_cast<const u4v*>(bs + ks * kPlane + ni * 16 * 64);
 #pragma unroll
                     for (int mi = 0; mi < 4; ++mi)
 #pragma unroll
@@ -565,18 +586,19 @@ __global__ __launch_bounds__(kGemmThreads, 2) void mxp_gemm_narrow_kernel(
             }
             if ((g + 1) % spt == 0) {  // tile column n done: fold with its scales
                 const int n = g / spt;
-                const float sc = ldexpf(1.0f, aop.scale(n) + bop.scale(n));
+                const int sc = aop.scale(n) + bop.scale(n);
 #pragma unroll
                 for (int mi = 0; mi < 4; ++mi)
 #pragma unroll
                     for (int ni = 0; ni < 4; ++ni) {
-                        acc[mi][ni] += part[mi][ni] * sc;
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) acc[mi][ni][v] += ldexpf(part[mi][ni][v], sc);
                         part[mi][ni] = f4{0.f, 0.f, 0.f, 0.f};
                     }
             }
             if (more) {
-                store_quad(&lds[buf ^ 1][0][lrow * kNPitch + lcol], 32 * kNPitch, ra);
-                store_quad(&lds[buf ^ 1][1][lrow * kNPitch + lcol], 32 * kNPitch, rb);
+                store_quad(&lds[buf ^ 1][0][so], ra);
+                store_quad(&lds[buf ^ 1][1][so], rb);
             }
             __syncthreads();
             buf ^= 1;
@@ -598,15 +620,13 @@ __global__ __launch_bounds__(kGemmThreads, 2) void mxp_gemm_narrow_kernel(
 // ---------------------------------------------------------------------------
 // FP32 group on the FP16 MFMA, with the two-term split of each operand
 // (described at the top of this file). Per stage, 32 k of each of the four
-// planes (A hi, A lo, B hi, B lo) are staged through LDS as 128 rows of 64
-// bytes (an 80-byte pitch puts the 16 rows one lane group reads in distinct
-// banks); lane l takes row l % 16 and k = 8 (l / 16) .. 8 (l / 16) + 7.
+// copies (A hi, A lo, B hi, B lo) are staged through LDS as one swizzled
+// plane each; lane l takes row l % 16 and k = 8 (l / 16) .. 8 (l / 16) + 7.
 // Three v_mfma_f32_16x16x32_f16 per 16 x 16 block and stage; the products of
 // one tile column n are folded into the accumulator with the copies' scales
 // 2^(e_a + e_b) (ldexp per element, so no scale underflows on its own).
 // ---------------------------------------------------------------------------
-constexpr int kSK = 32;           // k per stage
-constexpr int kSPitch = 64 + 16;  // bytes per LDS row
+constexpr int kSK = 32;  // k per stage
 
 struct Pair {
     u4v v0, v1;
@@ -615,16 +635,16 @@ __device__ __forceinline__ void load_pair(const uint8_t* p, int64_t step, Pair& 
     q.v0 = *reinterpret_cast<const u4v*>(p);
     q.v1 = *reinterpret_cast<const u4v*>(p + step);
 }
-__device__ __forceinline__ void store_pair(uint8_t* p, int step, const Pair& q) {
+__device__ __forceinline__ void store_pair(uint8_t* p, const Pair& q) {
     *reinterpret_cast<u4v*>(p) = q.v0;
-    *reinterpret_cast<u4v*>(p + step) = q.v1;
+    *reinterpret_cast<u4v*>(p + 64 * 64) = q.v1;  // row + 64: same swizzle
 }
 
 __global__ __launch_bounds__(kGemmThreads, 2) void mxp_gemm_split_kernel(
     double* __restrict__ W, int Nt, int nb, int k, int nbeg, int nend, const int* __restrict__ rows,
     int nrows, const char* __restrict__ storage, const int64_t* __restrict__ shoff,
     const int* __restrict__ cscl) {
-    __shared__ __attribute__((aligned(16))) uint8_t lds[2][4][kB * kSPitch];
+    __shared__ __attribute__((aligned(16))) uint8_t lds[2][4][kPlane];
     const int T = nb / kB;
     const int64_t total = (int64_t)nrows * T * T;
     const int64_t b = xcd_remap_m(blockIdx.x, total);
@@ -638,13 +658,14 @@ __global__ __launch_bounds__(kGemmThreads, 2) void mxp_gemm_split_kernel(
     const NarrowOp bop{storage, shoff, cscl, kFP32, Nt, nb, k, (int64_t)bc * kB};
     const int spt = nb / kSK;  // stages per tile column
     const int g0 = nbeg * spt, g1 = nend * spt;
-    // each thread moves 2 x 16 bytes per plane per stage: rows tid / 4 and
-    // tid / 4 + 64, byte column 16 (tid % 4) of the 64-byte stage row
-    const int lrow = tid >> 2, lcol = (tid & 3) * 16;
+    // thread t moves rows t / 4 and t / 4 + 64, bytes 16 (t % 4) of the
+    // 64-byte stage row of each copy
+    const int lrow = tid >> 2, lch = tid & 3;
     const int64_t gstep = (int64_t)64 * nb * 2;
-    const int64_t lofs = (int64_t)lrow * nb * 2 + lcol;
-    const int64_t plane = (int64_t)nb * nb * 2;  // lo plane after the hi plane
-    const int so = lrow * kSPitch + lcol;
+    const int64_t lofs = (int64_t)lrow * nb * 2 + 16 * lch;
+    const int64_t plane = (int64_t)nb * nb * 2;  // lo copy after the hi copy
+    const int so = swz(lrow, lch);
+    const int ro = swz(li, lg);  // MFMA operand slot: row 16 i + l % 16, chunk l / 16
     Pair rah, ral, rbh, rbl;
     f4 acc[4][4], part[4][4];
 #pragma unroll
@@ -663,10 +684,10 @@ __global__ __launch_bounds__(kGemmThreads, 2) void mxp_gemm_split_kernel(
             load_pair(pb, gstep, rbh);
             load_pair(pb + plane, gstep, rbl);
         }
-        store_pair(&lds[0][0][so], 64 * kSPitch, rah);
-        store_pair(&lds[0][1][so], 64 * kSPitch, ral);
-        store_pair(&lds[0][2][so], 64 * kSPitch, rbh);
-        store_pair(&lds[0][3][so], 64 * kSPitch, rbl);
+        store_pair(&lds[0][0][so], rah);
+        store_pair(&lds[0][1][so], ral);
+        store_pair(&lds[0][2][so], rbh);
+        store_pair(&lds[0][3][so], rbl);
         __syncthreads();
         int buf = 0;
         for (int g = g0; g < g1; ++g) {
@@ -681,15 +702,15 @@ __global__ __launch_bounds__(kGemmThreads, 2) void mxp_gemm_split_kernel(
                 load_pair(pb, gstep, rbh);
                 load_pair(pb + plane, gstep, rbl);
             }
-            const int ao = (wm * 64 + li) * kSPitch + 16 * lg;
-            const int bo = (wn * 64 + li) * kSPitch + 16 * lg;
+            const int ao = wm * 64 * 64 + ro;
+            const int bo = wn * 64 * 64 + ro;
             u4v xa[4], xb[4], ya[4];
 #pragma unroll
             for (int mi = 0; mi < 4; ++mi)
-                xa[mi] = *reinterpret_cast<const u4v*>(&lds[buf][0][ao + mi * 16 * kSPitch]);
+                xa[mi] = *reinterpret_cast<const u4v*>(&lds[buf][0][ao + mi * 16 * 64]);
 #pragma unroll
             for (int ni = 0; ni < 4; ++ni)
-                xb[ni] = *reinterpret_cast<const u4v*>(&lds[buf][2][bo + ni * 16 * kSPitch]);
+                xb[ni] = *reinterpret_cast<const u4v*>(&lds[buf][2][bo + ni * 16 * 64]);
 #pragma unroll
             for (int mi = 0; mi < 4; ++mi)
 #pragma unroll
@@ -699,7 +720,7 @@ __global__ __launch_bounds__(kGemmThreads, 2) void mxp_gemm_split_kernel(
                         part[mi][ni], 0, 0, 0);
 #pragma unroll
             for (int mi = 0; mi < 4; ++mi)
-                ya[mi] = *reinterpret_cast<const u4v*>(&lds[buf][1][ao + mi * 16 * kSPitch]);
+                ya[mi] = *reinterpret_cast<const u4v*>(&lds[buf][1][ao + mi * 16 * 64]);
 #pragma unroll
             for (int mi = 0; mi < 4; ++mi)
 #pragma unroll
@@ -709,7 +730,7 @@ __global__ __launch_bounds__(kGemmThreads, 2) void mxp_gemm_split_kernel(
                         part[mi][ni], 0, 0, 0);
 #pragma unroll
             for (int ni = 0; ni < 4; ++ni)
-                xb[ni] = *reinterpret_cast<const u4v*>(&lds[buf][3][bo + ni * 16 * kSPitch]);
+                xb[ni] = *reinterpret_cast<const u4v*>(&lds[buf][3][bo + ni * 16 * 64]);
 #pragma unroll
             for (int mi = 0; mi < 4; ++mi)
 #pragma unroll
@@ -730,10 +751,10 @@ __global__ __launch_bounds__(kGemmThreads, 2) void mxp_gemm_split_kernel(
                     }
             }
             if (more) {
-                store_pair(&lds[buf ^ 1][0][so], 64 * kSPitch, rah);
-                store_pair(&lds[buf ^ 1][1][so], 64 * kSPitch, ral);
-                store_pair(&lds[buf ^ 1][2][so], 64 * kSPitch, rbh);
-                store_pair(&lds[buf ^ 1][3][so], 64 * kSPitch, rbl);
+                store_pair(&lds[buf ^ 1][0][so], rah);
+                store_pair(&lds[buf ^ 1][1][so], ral);
+                store_pair(&lds[buf ^ 1][2][so], rbh);
+                store_pair(&lds[buf ^ 1][3][so], rbl);
             }
             __syncthreads();
             buf ^= 1;

@@ -223,6 +223,41 @@ tc_status tc_logdet(tc_ctx *ctx, const tc_factor *L, double *out);
 tc_status tc_factorize_ooc(tc_ctx *ctx, int64_t n, int32_t nb, const double *A_host,
                            double *L_host, void *cache, size_t cache_bytes, tc_ooc_stats *stats);
 
+/* Bytes of host memory receiving an out-of-core mixed-precision factor:
+ * every tile in its class (8/4/2/2/1 bytes per entry; FP16 and FP8 tiles
+ * hold x * 2^-e), packed lower order, each tile starting on a 256-byte
+ * boundary (tile t at the sum of the rounded-up sizes of the tiles before
+ * it), then one int32 scale exponent e per tile in packed order (value =
+ * stored value * 2^e). 0 if the shape or the map is invalid. */
+size_t tc_ooc_mixed_host_bytes(int64_t n, int32_t nb, const uint8_t *map);
+
+/* Device cache bytes tc_factorize_ooc_mixed needs to hold `slots` tile
+ * slots (plus its tables and the staging of one column); at least
+ * 2 * Nt slots are required. 0 if the shape or the map is invalid. */
+size_t tc_ooc_mixed_cache_bytes(int64_t n, int32_t nb, const uint8_t *map, int64_t slots);
+
+/* Out-of-core mixed-precision tile Cholesky (Sections III-C, IV-B, IV-C):
+ * the schedule of tc_factorize_ooc with the precision map of tc_factorize,
+ * the factor crossing the link in its classes' bytes.
+ * A_host: pinned host memory, packed lower tiles (n, nb), binary64, read.
+ * map: host, Nt(Nt+1)/2 tc_prec codes, diagonal tiles TC_FP64.
+ * L_host: pinned host memory of L_host_bytes >= tc_ooc_mixed_host_bytes
+ *    bytes receiving the factor image described there.
+ * cache: device buffer of cache_bytes bytes holding the device tables, a
+ *    staging area for one column of new tiles, and fixed-size slots (one
+ *    tile in its class plus the operand copies it is multiplied in, rebuilt
+ *    on the device when the tile is loaded); at least 2 * Nt slots, else
+ *    TC_ENOMEM with the required size in tc_last_error(). The two working
+ *    columns come from the context workspace.
+ * Updates into a tile of class p are computed as in tc_factorize (same
+ * kernels; the summation is split at the chunk boundaries, so results
+ * agree with the in-core factor up to rounding). Runs on the compute stream
+ * and the two library copy streams, default priority; returns after
+ * everything has completed (no tc_factor handle). */
+tc_status tc_factorize_ooc_mixed(tc_ctx *ctx, int64_t n, int32_t nb, const double *A_host,
+                                 const uint8_t *map, void *L_host, size_t L_host_bytes,
+                                 void *cache, size_t cache_bytes, tc_ooc_stats *stats);
+
 /* Copy the factor into L64 (device, packed lower tiles, binary64; each tile
  * upcast from its class) with the strict upper triangle of every diagonal
  * tile set to zero. For an all-FP64 factor L64 may be the factor's own

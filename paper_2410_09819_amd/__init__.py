@@ -114,6 +114,10 @@ def lib():
                                     _i32, _vp]),
         "tc_logdet": (_i32, [_vp, _vp, ctypes.POINTER(ctypes.c_double)]),
         "tc_factorize_ooc": (_i32, [_vp, _i64, _i32, _vp, _vp, _vp, _sz, ctypes.POINTER(OocStats)]),
+        "tc_ooc_mixed_host_bytes": (_sz, [_i64, _i32, _vp]),
+        "tc_ooc_mixed_cache_bytes": (_sz, [_i64, _i32, _vp, _i64]),
+        "tc_factorize_ooc_mixed": (_i32, [_vp, _i64, _i32, _vp, _vp, _vp, _sz, _vp, _sz,
+                                          ctypes.POINTER(OocStats)]),
         "tc_factor_export": (_i32, [_vp, _vp, _vp]),
         "tc_factor_destroy": (_i32, [_vp]),
         "tc_loglik_seed": (_i32, [_vp, _vp, _vp, _vp, ctypes.POINTER(ctypes.c_double)]),
@@ -336,6 +340,46 @@ def factorize_ooc(ctx: Context, A_host, n: int, nb: int, cache, L_host=None) -> 
                                   cache.data_ptr(), cache.numel() * cache.element_size(),
                                   ctypes.byref(st)))
     return st.as_dict()
+
+
+def ooc_mixed_host_bytes(n: int, nb: int, cmap) -> int:
+    """Bytes of the host image of an out-of-core mixed-precision factor
+    (tiles in their classes, then one int32 scale exponent per tile)."""
+    m = np.ascontiguousarray(cmap, dtype=np.uint8)
+    b = lib().tc_ooc_mixed_host_bytes(n, nb, m.ctypes.data)
+    if b == 0:
+        raise TileCholError(TC_EINVAL, "invalid shape or precision map")
+    return b
+
+
+def ooc_mixed_cache_bytes(n: int, nb: int, cmap, slots: int) -> int:
+    """Device cache bytes of factorize_ooc_mixed with `slots` tile slots."""
+    m = np.ascontiguousarray(cmap, dtype=np.uint8)
+    b = lib().tc_ooc_mixed_cache_bytes(n, nb, m.ctypes.data, slots)
+    if b == 0:
+        raise TileCholError(TC_EINVAL, "invalid shape or precision map")
+    return b
+
+
+def factorize_ooc_mixed(ctx: Context, A_host, n: int, nb: int, cmap, cache, L_host=None):
+    """Out-of-core mixed-precision factorization: A_host (pinned CPU float64
+    tensor, packed lower tiles) streams through the device cache `cache`;
+    the factor image (tiles in their classes, then the tile scale exponents)
+    goes to L_host (pinned CPU uint8 tensor, allocated if None). Returns
+    (transfer statistics, L_host). Raises NotPositiveDefinite."""
+    import torch
+    assert A_host.device.type == "cpu" and A_host.is_pinned()
+    m = np.ascontiguousarray(cmap, dtype=np.uint8)
+    nbytes = ooc_mixed_host_bytes(n, nb, m)
+    if L_host is None:
+        L_host = torch.empty(nbytes, dtype=torch.uint8, pin_memory=True)
+    assert L_host.device.type == "cpu" and L_host.is_pinned()
+    st = OocStats()
+    _check(lib().tc_factorize_ooc_mixed(ctx.handle, n, nb, A_host.data_ptr(), m.ctypes.data,
+                                        L_host.data_ptr(), L_host.numel() * L_host.element_size(),
+                                        cache.data_ptr(), cache.numel() * cache.element_size(),
+                                        ctypes.byref(st)))
+    return st.as_dict(), L_host
 
 
 def logdet(ctx: Context, F: Factor) -> float:

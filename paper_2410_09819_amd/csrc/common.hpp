@@ -109,6 +109,15 @@ hipError_t launch_mxp_gemm_f32(hipStream_t s, double* W, int Nt, int nb, int k, 
 hipError_t launch_mxp_gemm_narrow(hipStream_t s, double* W, int Nt, int nb, int k, int nbeg,
                                   int nend, const int* rows, int nrows, int cls,
                                   const char* storage, const int64_t* shoff, const int* cscl);
+// Operand copies of the stored tiles list[0..count) (out of core: tiles
+// loaded into cache slots), from their stored bits and recorded scales.
+hipError_t launch_mxp_copies(hipStream_t s, int nb, const int* list, int count, char* storage,
+                             const int64_t* toff, const uint8_t* tcls, const int* tscl,
+                             const int64_t* shoff, const int* cscl);
+// Point the tile and copy offset tables of tiles upd[2i] at slot offsets
+// upd[2i + 1] (copy class c at + coff[c - 1] when bit c of need[t] is set).
+hipError_t launch_slot_tables(hipStream_t s, const int64_t* upd, int count, const uint8_t* need,
+                              const int64_t* coff, int64_t* toff, int64_t* shoff);
 hipError_t launch_mxp_finalize(hipStream_t s, const double* W, int Nt, int nb, int k, double* part,
                                char* storage, const int64_t* toff, const uint8_t* tcls, int* tscl,
                                const int64_t* shoff, int* cscl);

@@ -68,6 +68,23 @@ tc_status check_ws(tc_ctx* ctx, int64_t n, int nb);
 tc_status ctx_ooc_resources(tc_ctx* ctx, size_t bytes);
 // Create the auxiliary compute streams and their events in the context (once).
 tc_status ctx_aux_streams(tc_ctx* ctx);
+// Storage plan of a mixed-precision factor (tiles per class in packed order,
+// then the operand copies, then the device tables); see make_plan.
+struct Plan {
+    int Nt = 0, nb = 0;
+    int64_t ntiles = 0;
+    std::vector<uint8_t> cls;
+    std::vector<int64_t> toff, shoff;  // shoff[t * 4 + c - 1], -1 if absent
+    size_t tab_toff = 0, tab_shoff = 0, tab_tscl = 0, tab_tcls = 0, tab_cscl = 0, total = 0;
+    bool mixed = false;
+};
+// Fills P for map (NULL: all FP64); false if the map is invalid.
+bool make_plan(int64_t n, int nb, const uint8_t* map, Plan& P);
+// Row lists of a mixed factorization: for column k and class c, the rows
+// r >= 1 (tile k + r) of that class at lists[(k * 5 + c) * Nt + i],
+// i < count[k * 5 + c]; flops per class (diagonal SYRK counted as FP64).
+void class_lists(const Plan& P, std::vector<int>& lists, std::vector<int>& count,
+                 double* cflops, int* ctiles);
 // Read-only device view of a factor's tiles (any precision layout).
 tc::TileView factor_view(const tc_factor* F);
 // POTRF of the s x s block at offset o of a diagonal tile (leading dim nb),

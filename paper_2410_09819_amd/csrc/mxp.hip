@@ -347,41 +347,16 @@ __global__ __launch_bounds__(kThreads) void tile_amax_kernel(const double* __res
 constexpr int kCB = 64;
 constexpr int kCPitch = kCB * 2 + 16;  // bytes per staged copy row
 
-__global__ __launch_bounds__(kThreads) void tile_cast_kernel(
-    const double* __restrict__ W, int Nt, int nb, int k, const double* __restrict__ part,
-    char* __restrict__ storage, const int64_t* __restrict__ toff, const uint8_t* __restrict__ tcls,
-    int* __restrict__ tscl, const int64_t* __restrict__ shoff, int* __restrict__ cscl) {
-    __shared__ __attribute__((aligned(16))) uint8_t stage[5][kCB * kCPitch];
-    const int rt = blockIdx.z;  // tile k + 1 + rt of column k
-    const int r0 = blockIdx.x * kCB, c0 = blockIdx.y * kCB;
-    const int64_t t = tile_off(Nt, k + 1 + rt, k);
-    double amax = 0.0;
-    for (int s = 0; s < kStrips; ++s) amax = fmax(amax, part[rt * kStrips + s]);
-    const int c = tcls[t];
-    const int e = class_scale(amax, c);
-    // largest stored value (rounding is monotone): decides the copies' scales
-    const double amax_h = ldexp(fabs(round_to_class(ldexp(amax, -e), c)), e);
-    int ce[5];
-    char* copy[5];
-#pragma unroll
-    for (int c2 = 1; c2 <= 4; ++c2) {
-        const int64_t o = shoff[t * 4 + (c2 - 1)];
-        copy[c2] = o >= 0 ? storage + o : nullptr;
-        ce[c2] = class_scale(amax_h, c2 == kFP32 ? kFP16 : c2);
-    }
-    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
-        tscl[t] = e;
-        for (int c2 = 1; c2 <= 4; ++c2) cscl[t * 4 + (c2 - 1)] = ce[c2];
-    }
-    const double* src = W + (int64_t)(1 + rt) * nb * nb;
-    void* dst = storage + toff[t];
+// Rounding of one 64 x 64 block into the operand copies (LDS staging, then
+// row-major writes). v(i) gives the stored factor value of element i.
+template <class V>
+__device__ __forceinline__ void write_copies(const V& val, int nb, int r0, int c0, char* const* copy,
+                                             const int* ce, uint8_t (*stage)[kCB * kCPitch]) {
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
     for (int j = 0; j < kCB / 4; ++j) {
         const int cl = ty + 4 * j;
         const int64_t i = (int64_t)(c0 + cl) * nb + r0 + tx;
-        const double r = round_to_class(ldexp(src[i], -e), c);
-        store_elem(dst, i, c, r);
-        const double v = ldexp(r, e);  // the stored factor value
+        const double v = val(i);
         if (copy[kFP32]) {
             // x - hi is exact in binary64; hi and lo saturate like any FP16 value
             const double x = ldexp(round_to_class(v, kFP32), -ce[kFP32]);
@@ -416,6 +391,83 @@ __global__ __launch_bounds__(kThreads) void tile_cast_kernel(
             *reinterpret_cast<uint4*>(dc + ((int64_t)(r0 + rr) * nb + c0) * eb + cc * 16) = v;
         }
     }
+}
+
+__global__ __launch_bounds__(kThreads) void tile_cast_kernel(
+    const double* __restrict__ W, int Nt, int nb, int k, const double* __restrict__ part,
+    char* __restrict__ storage, const int64_t* __restrict__ toff, const uint8_t* __restrict__ tcls,
+    int* __restrict__ tscl, const int64_t* __restrict__ shoff, int* __restrict__ cscl) {
+    __shared__ __attribute__((aligned(16))) uint8_t stage[5][kCB * kCPitch];
+    const int rt = blockIdx.z;  // tile k + 1 + rt of column k
+    const int r0 = blockIdx.x * kCB, c0 = blockIdx.y * kCB;
+    const int64_t t = tile_off(Nt, k + 1 + rt, k);
+    double amax = 0.0;
+    for (int s = 0; s < kStrips; ++s) amax = fmax(amax, part[rt * kStrips + s]);
+    const int c = tcls[t];
+    const int e = class_scale(amax, c);
+    // largest stored value (rounding is monotone): decides the copies' scales
+    const double amax_h = ldexp(fabs(round_to_class(ldexp(amax, -e), c)), e);
+    int ce[5];
+    char* copy[5];
+#pragma unroll
+    for (int c2 = 1; c2 <= 4; ++c2) {
+        const int64_t o = shoff[t * 4 + (c2 - 1)];
+        copy[c2] = o >= 0 ? storage + o : nullptr;
+        ce[c2] = class_scale(amax_h, c2 == kFP32 ? kFP16 : c2);
+    }
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+        tscl[t] = e;
+        for (int c2 = 1; c2 <= 4; ++c2) cscl[t * 4 + (c2 - 1)] = ce[c2];
+    }
+    const double* src = W + (int64_t)(1 + rt) * nb * nb;
+    void* dst = storage + toff[t];
+    auto val = [=](int64_t i) {
+        const double r = round_to_class(ldexp(src[i], -e), c);
+        store_elem(dst, i, c, r);
+        return ldexp(r, e);  // the stored factor value
+    };
+    write_copies(val, nb, r0, c0, copy, ce, stage);
+}
+
+// Operand copies of stored tiles list[z] (tiles already in storage, their
+// scales in tscl / cscl): the same values tile_cast_kernel wrote when the
+// tiles were finalized, rebuilt from the stored bits.
+__global__ __launch_bounds__(kThreads) void tile_copies_kernel(
+    int nb, const int* __restrict__ list, char* __restrict__ storage,
+    const int64_t* __restrict__ toff, const uint8_t* __restrict__ tcls,
+    const int* __restrict__ tscl, const int64_t* __restrict__ shoff,
+    const int* __restrict__ cscl) {
+    __shared__ __attribute__((aligned(16))) uint8_t stage[5][kCB * kCPitch];
+    const int64_t t = list[blockIdx.z];
+    const int r0 = blockIdx.x * kCB, c0 = blockIdx.y * kCB;
+    const int c = tcls[t], e = tscl[t];
+    int ce[5];
+    char* copy[5];
+#pragma unroll
+    for (int c2 = 1; c2 <= 4; ++c2) {
+        const int64_t o = shoff[t * 4 + (c2 - 1)];
+        copy[c2] = o >= 0 ? storage + o : nullptr;
+        ce[c2] = cscl[t * 4 + (c2 - 1)];
+    }
+    const void* src = storage + toff[t];
+    auto val = [=](int64_t i) { return load_elem(src, i, c, e); };
+    write_copies(val, nb, r0, c0, copy, ce, stage);
+}
+
+// Tables of an out-of-core mixed factor: upd[2i] = tile t, upd[2i + 1] =
+// byte offset of its slot (stored tile first, then the copy areas at
+// coff[c - 1] for the copy classes the tile needs: bit c of need[t]).
+__global__ void slot_tables_kernel(const int64_t* __restrict__ upd, int count,
+                                   const uint8_t* __restrict__ need, int64_t c1, int64_t c2,
+                                   int64_t c3, int64_t c4, int64_t* __restrict__ toff,
+                                   int64_t* __restrict__ shoff) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const int64_t t = upd[2 * i], base = upd[2 * i + 1];
+    const int64_t coff[4] = {c1, c2, c3, c4};
+    toff[t] = base;
+    for (int c = 1; c <= 4; ++c)
+        shoff[t * 4 + (c - 1)] = (need[t] >> c) & 1 ? base + coff[c - 1] : -1;
 }
 
 // ---------------------------------------------------------------------------
@@ -849,6 +901,23 @@ hipError_t launch_mxp_gemm_narrow(hipStream_t s, double* W, int Nt, int nb, int 
                            rows, nrows, storage, shoff, cscl);
     else
         return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_mxp_copies(hipStream_t s, int nb, const int* list, int count, char* storage,
+                             const int64_t* toff, const uint8_t* tcls, const int* tscl,
+                             const int64_t* shoff, const int* cscl) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(tile_copies_kernel, dim3(nb / kCB, nb / kCB, count), dim3(kThreads), 0, s, nb,
+                       list, storage, toff, tcls, tscl, shoff, cscl);
+    return hipGetLastError();
+}
+
+hipError_t launch_slot_tables(hipStream_t s, const int64_t* upd, int count, const uint8_t* need,
+                              const int64_t* coff, int64_t* toff, int64_t* shoff) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(slot_tables_kernel, dim3((count + 255) / 256), dim3(256), 0, s, upd, count,
+                       need, coff[0], coff[1], coff[2], coff[3], toff, shoff);
     return hipGetLastError();
 }
 

@@ -150,15 +150,6 @@ tc_status check_ws(tc_ctx* ctx, int64_t n, int nb) {
 // operand order) with a per-copy power-of-two scale: the class's own bits
 // for FP16, BF16 and FP8, and for FP32 the binary32 value split into two
 // FP16 planes (hi, lo). Then the device tables.
-struct Plan {
-    int Nt = 0, nb = 0;
-    int64_t ntiles = 0;
-    std::vector<uint8_t> cls;
-    std::vector<int64_t> toff, shoff;  // shoff[t * 4 + c - 1], -1 if absent
-    size_t tab_toff = 0, tab_shoff = 0, tab_tscl = 0, tab_tcls = 0, tab_cscl = 0, total = 0;
-    bool mixed = false;
-};
-
 bool make_plan(int64_t n, int nb, const uint8_t* map, Plan& P) {
     P.Nt = (int)(n / nb);
     P.nb = nb;
@@ -219,6 +210,28 @@ bool make_plan(int64_t n, int nb, const uint8_t* map, Plan& P) {
     off += align_up(P.ntiles * 4 * sizeof(int));
     P.total = off;
     return true;
+}
+
+void class_lists(const Plan& P, std::vector<int>& lists, std::vector<int>& count,
+                 double* cflops, int* ctiles) {
+    const int Nt = P.Nt;
+    const double nb2 = (double)P.nb * P.nb;
+    lists.assign((size_t)5 * Nt * Nt, 0);
+    count.assign((size_t)5 * Nt, 0);
+    for (int c = 0; c < 5; ++c) {
+        cflops[c] = 0.0;
+        ctiles[c] = 0;
+    }
+    for (int64_t t = 0; t < P.ntiles; ++t) ctiles[P.cls[t]]++;
+    for (int k = 0; k < Nt; ++k) {
+        const double K = (double)k * P.nb;
+        cflops[TC_FP64] += nb2 * K;  // diagonal SYRK (lower half)
+        for (int r = 1; r < Nt - k; ++r) {
+            const int c = P.cls[tc::tile_off(Nt, k + r, k)];
+            lists[((size_t)k * 5 + c) * Nt + count[(size_t)k * 5 + c]++] = r;
+            cflops[c] += 2.0 * nb2 * K;
+        }
+    }
 }
 
 // Recursive POTRF of the s x s block at offset o of a diagonal tile.
@@ -605,21 +618,10 @@ tc_status factorize_mixed(tc_ctx* ctx, int64_t n, int nb, const double* A, const
     uint8_t* d_tcls = reinterpret_cast<uint8_t*>(storage + P.tab_tcls);
     int* d_cscl = reinterpret_cast<int*>(storage + P.tab_cscl);
 
-    // row lists: for column k and class c, rows r >= 1 (tile k + r) of that class
-    std::vector<int> lists((size_t)5 * Nt * Nt, 0);
-    std::vector<int> lcount((size_t)5 * Nt, 0);
-    double cflops[5] = {0, 0, 0, 0, 0};
-    int ctiles[5] = {0, 0, 0, 0, 0};
-    for (int64_t t = 0; t < P.ntiles; ++t) ctiles[P.cls[t]]++;
-    for (int k = 0; k < Nt; ++k) {
-        const double K = (double)k * nb;
-        cflops[TC_FP64] += (double)nb2 * K;  // diagonal SYRK (lower half)
-        for (int r = 1; r < Nt - k; ++r) {
-            const int c = P.cls[tc::tile_off(Nt, k + r, k)];
-            lists[((size_t)k * 5 + c) * Nt + lcount[(size_t)k * 5 + c]++] = r;
-            cflops[c] += 2.0 * nb2 * K;
-        }
-    }
+    std::vector<int> lists, lcount;
+    double cflops[5];
+    int ctiles[5];
+    class_lists(P, lists, lcount, cflops, ctiles);
     std::vector<int> zeros(P.ntiles, 0);
     if (tc_status s = ctx_aux_streams(ctx)) return s;
     while (ctx->la_ev.size() < (size_t)4 * Nt + 1) {

@@ -1,0 +1,154 @@
+"""GPU parity of the out-of-core mixed-precision factorization (Sections
+III-C, IV-B, IV-C): the matrix in pinned host memory, the factor written
+back to host memory in its tiles' classes, a device cache of a given number
+of slots. Checked:
+  * the host image, decoded here from its documented format (tile bits in
+    the class times 2^scale), holds tiles exactly representable in their
+    classes;
+  * its backward error is at most the target accuracy and within 10x of the
+    oracle's emulation of the same map, and it agrees with the in-core
+    mixed factor of the same map within the perturbation bound of two exact
+    factors of nearby matrices (the chunked summation rounds differently);
+  * transfer volume: A crosses the link once (binary64) and the factor once
+    in its classes' bytes; with the minimal cache, tiles are evicted and
+    reloaded in their classes' bytes.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import seeded_inputs as si
+
+pytestmark = pytest.mark.gpu
+
+BYTES = {0: 8, 1: 4, 2: 2, 3: 2, 4: 1}
+
+
+@pytest.fixture(scope="module")
+def tc():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2410_09819_amd as tc
+    tc.lib()
+    return tc
+
+
+@pytest.fixture(scope="module")
+def case():
+    n, nb = 2048, 128
+    pts = si.points(n, seed=3)
+    A = oracle.matern_matrix(pts, 1.0, 0.03, 0.5, 1e-4)
+    Nt = n // nb
+    norms = oracle.tile_norms(A, nb)
+    return dict(n=n, nb=nb, Nt=Nt, A=A, norms=norms, fro=oracle.fro_norm(norms, Nt),
+                kappa=np.linalg.cond(A))
+
+
+def e4m3_table():
+    """OCP E4M3 decode table from the format's definition (bias 7, 3
+    fraction bits, subnormals m * 2^-9)."""
+    tab = np.zeros(256)
+    for b in range(256):
+        e, m = (b >> 3) & 15, b & 7
+        v = m * 2.0 ** -9 if e == 0 else (1 + m / 8.0) * 2.0 ** (e - 7)
+        tab[b] = -v if b & 0x80 else v
+    return tab
+
+
+def decode_image(img, n, nb, cm):
+    """Packed binary64 tiles from the host image: tile t at the sum of the
+    256-byte-rounded sizes of the tiles before it, then int32 exponents."""
+    import torch
+    raw = img.numpy()
+    nb2 = nb * nb
+    off, offs = 0, []
+    for c in cm:
+        offs.append(off)
+        off += (nb2 * BYTES[int(c)] + 255) // 256 * 256
+    scales = raw[(off + 255) // 256 * 256:][:4 * len(cm)].view(np.int32)
+    fp8 = e4m3_table()
+    out = np.empty(len(cm) * nb2)
+    for t, c in enumerate(cm):
+        b = raw[offs[t]:offs[t] + nb2 * BYTES[int(c)]]
+        if c == 0:
+            v = b.view(np.float64)
+        elif c == 1:
+            v = b.view(np.float32).astype(np.float64)
+        elif c == 2:
+            v = b.view(np.float16).astype(np.float64)
+        elif c == 3:
+            v = (b.view(np.uint16).astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+        else:
+            v = fp8[b]
+        out[t * nb2:(t + 1) * nb2] = np.ldexp(v, int(scales[t]))
+    return out
+
+
+def pinned(x):
+    import torch
+    t = torch.empty(x.size, dtype=torch.float64, pin_memory=True)
+    t.copy_(torch.from_numpy(x))
+    return t
+
+
+@pytest.mark.parametrize("eps,slots", [(1e-9, 200), (1e-6, 200), (1e-9, 32)])
+def test_ooc_mixed_matches_in_core_and_oracle(tc, case, eps, slots):
+    import torch
+    n, nb, Nt, A = case["n"], case["nb"], case["Nt"], case["A"]
+    cm = tc.precision_map(Nt, case["norms"], case["fro"], eps)
+    assert len(set(cm.tolist())) >= 3
+    ctx = tc.Context(n, nb)
+    Ah = pinned(tc.pack_lower(A, nb))
+    cache = torch.empty(tc.ooc_mixed_cache_bytes(n, nb, cm, slots), dtype=torch.uint8, device="cuda")
+    st, img = tc.factorize_ooc_mixed(ctx, Ah, n, nb, cm, cache)
+    assert st["info"] == 0 and st["cache_slots"] == slots
+    L = np.tril(tc.unpack_lower(decode_image(img, n, nb, cm), n, nb))
+    for j in range(Nt):
+        for i in range(j + 1, Nt):
+            t = L[i * nb:(i + 1) * nb, j * nb:(j + 1) * nb]
+            c = int(cm[oracle.tile_index(Nt, i, j)])
+            assert np.array_equal(oracle.round_tile(t, c)[0], t), (i, j, c)
+    # in-core factor of the same map
+    Ad = torch.from_numpy(tc.pack_lower(A, nb)).cuda()
+    Lin = tc.unpack_lower(tc.export(ctx, tc.factorize(ctx, Ad, n, nb, cmap=cm)).cpu().numpy(), n, nb)
+    Lo, info = oracle.mxp_tile_cholesky(A, nb, cm)
+    assert info == 0
+    be, be_in, be_o = (oracle.backward_error(A, X) for X in (L, Lin, Lo))
+    assert be <= eps and be <= 10 * be_o, (be, be_o)
+    diff = np.linalg.norm(L - Lin) / np.linalg.norm(Lin)
+    assert diff <= 4 * case["kappa"] * (be + be_in) + 1e-13, diff
+    # transfer volume
+    nb2 = nb * nb
+    ntiles = Nt * (Nt + 1) // 2
+    cls_bytes = sum(nb2 * BYTES[int(c)] for c in cm)
+    assert st["bytes_d2h"] == cls_bytes
+    if slots >= Nt * Nt // 4 + Nt:
+        assert st["tiles_reloaded"] == 0 and st["bytes_h2d"] == ntiles * nb2 * 8
+    else:
+        assert st["evictions"] > 0 and st["tiles_reloaded"] > 0
+        assert st["bytes_h2d"] > ntiles * nb2 * 8
+
+
+def test_ooc_mixed_errors(tc, case):
+    import torch
+    n, nb, Nt, A = case["n"], case["nb"], case["Nt"], case["A"]
+    cm = tc.precision_map(Nt, case["norms"], case["fro"], 1e-9)
+    ctx = tc.Context(n, nb)
+    Ah = pinned(tc.pack_lower(A, nb))
+    small = torch.empty(tc.ooc_mixed_cache_bytes(n, nb, cm, 2 * Nt - 1), dtype=torch.uint8,
+                        device="cuda")
+    with pytest.raises(tc.TileCholError) as e:
+        tc.factorize_ooc_mixed(ctx, Ah, n, nb, cm, small)
+    assert e.value.status == tc.TC_ENOMEM
+    bad_map = cm.copy()
+    bad_map[0] = tc.FP16  # diagonal tile
+    with pytest.raises(tc.TileCholError):
+        tc.ooc_mixed_host_bytes(n, nb, bad_map)
+    bad = np.eye(n) * 3.0
+    bad[700, 700] = -1.0
+    Bh = pinned(tc.pack_lower(bad, nb))
+    cache = torch.empty(tc.ooc_mixed_cache_bytes(n, nb, cm, 64), dtype=torch.uint8, device="cuda")
+    with pytest.raises(tc.NotPositiveDefinite) as e:
+        tc.factorize_ooc_mixed(ctx, Bh, n, nb, cm, cache)
+    assert e.value.info == 701

@@ -262,6 +262,117 @@ def ooc_leg(tc, si, dev, n=122880, nb=2048, caches_gib=(40, 16)):
             "chunks": st["chunks"], "max_rel_diff_sampled_tiles": worst})
     del A, storage, Ah
     torch.cuda.empty_cache()
+    torch._C._host_emptyCache()
+    return out
+
+
+IMAGE_BYTES = {0: 8, 1: 4, 2: 2, 3: 2, 4: 1}
+
+
+def decode_image_tile(img, cm, nb, t):
+    """Tile t (binary64, column-major nb x nb) of an out-of-core mixed
+    factor's host image: tiles in their classes on 256-byte boundaries,
+    then one int32 scale exponent per tile."""
+    import numpy as np
+    nb2 = nb * nb
+    sizes = [(nb2 * IMAGE_BYTES[int(c)] + 255) // 256 * 256 for c in cm]
+    off = sum(sizes[:t])
+    end = sum(sizes)
+    raw = img.numpy()
+    e = int(raw[end:end + 4 * len(cm)].view(np.int32)[t])
+    c = int(cm[t])
+    b = raw[off:off + nb2 * IMAGE_BYTES[c]]
+    if c == 0:
+        v = b.view(np.float64)
+    elif c == 1:
+        v = b.view(np.float32).astype(np.float64)
+    elif c == 2:
+        v = b.view(np.float16).astype(np.float64)
+    elif c == 3:
+        v = (b.view(np.uint16).astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+    else:
+        ex, m = (b >> 3) & 15, (b & 7).astype(np.float64)
+        v = np.where(ex == 0, m * 2.0 ** -9, (1 + m / 8) * np.ldexp(1.0, ex.astype(np.int64) - 7))
+        v = np.where(b & 0x80, -v, v)
+    return np.ldexp(v, e).reshape(nb, nb).T
+
+
+def ooc_mixed_leg(tc, si, dev, n=90112, nb=2048, eps=1e-9, caches_gib=(40, 20)):
+    """Out-of-core mixed-precision factorization against the in-core mixed
+    factorization of the same matrix and map. The ooc workload's parameters
+    (nu=1, range=0.05, nugget=1e-4) at n=90112, nb=2048, target 1e-9: A in
+    one exact-size pinned host buffer (30.9 GiB, binary64), the factor image
+    (tiles in their classes) in another; together they stay below the ~64
+    GiB of pinned host memory the test machines grant one process. Two HBM
+    caches: 40 GiB holds the peak working set of tile bundles, 20 GiB does
+    not (the minimum at this size is 15.1 GiB)."""
+    import numpy as np
+    import torch
+    w = si.WORKLOADS["ooc"]
+    theta = (w["sigma2"], w["range"], w["nu"], w["nugget"])
+    pts = torch.from_numpy(si.points(n, seed=w["seed"])).to(dev)
+    ctx = tc.Context(n, nb, timed=True)
+    A, norms, fro = tc.matern_tiles(ctx, pts, theta, nb, norms=True)
+    Nt = n // nb
+    cm = tc.precision_map(Nt, norms.cpu().numpy(), fro, eps)
+    storage = torch.empty(tc.factor_bytes(n, nb, cm) // 8, dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    F = tc.factorize(ctx, A, n, nb, cmap=cm, storage=storage)
+    torch.cuda.synchronize()
+    t_in = time.perf_counter() - t0
+    progress("ooc mixed: in-core mixed factorization %.2f s" % t_in)
+    samples = [(Nt - 1, 0), (Nt // 2, Nt // 3), (Nt - 1, Nt - 2), (Nt // 3, Nt // 3 - 1), (Nt - 1, Nt - 1)]
+    nb2 = nb * nb
+    L64 = torch.empty_like(A)
+    tc.export(ctx, F, out=L64)
+    ref = {ij: L64[tc.tile_offset(Nt, *ij) * nb2:(tc.tile_offset(Nt, *ij) + 1) * nb2].view(nb, nb).t().cpu().numpy()
+           for ij in samples}
+    F.close()
+    del F, storage, L64
+    torch.cuda.empty_cache()
+    flops = n ** 3 / 3.0
+    cls_bytes = {c: int(np.sum(cm == c)) * nb2 * IMAGE_BYTES[c] for c in IMAGE_BYTES}
+    out = {"workload": "ooc mixed-precision tile Cholesky, n=%d nb=%d, Matern nu=%g range=%g "
+                       "nugget=%g, target %g, pinned host tiles" % (n, nb, theta[2], theta[1], theta[3], eps),
+           "class_tiles": {k: int(np.sum(cm == c)) for k, c in (("fp64", 0), ("fp32", 1), ("fp16", 2),
+                                                              ("bf16", 3), ("fp8", 4))},
+           "factor_host_bytes": sum(cls_bytes.values()), "factor_fp64_bytes": len(cm) * nb2 * 8,
+           "in_core_s": t_in, "in_core_tflops_fp64_equivalent": flops / t_in / 1e12, "runs": []}
+    torch._C._host_emptyCache()  # pinned blocks torch keeps cached from earlier legs
+    Abuf = tc.PinnedBuffer(A.numel() * 8)
+    Ah = Abuf.view(torch.float64)
+    Ah.copy_(A)
+    del A
+    torch.cuda.empty_cache()
+    Ibuf = tc.PinnedBuffer(tc.ooc_mixed_host_bytes(n, nb, cm))
+    img = Ibuf.tensor
+    for gib in caches_gib:
+        cache = torch.empty(gib << 30, dtype=torch.uint8, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, _ = tc.factorize_ooc_mixed(ctx, Ah, n, nb, cm, cache, L_host=img)
+        t_ooc = time.perf_counter() - t0
+        del cache
+        torch.cuda.empty_cache()
+        progress("ooc mixed: %d GiB cache %.2f s" % (gib, t_ooc))
+        worst = 0.0
+        for ij in samples:
+            a = ref[ij]
+            b = decode_image_tile(img, cm, nb, tc.tile_offset(Nt, *ij))
+            if ij[0] == ij[1]:
+                a, b = np.tril(a), np.tril(b)
+            worst = max(worst, float(np.abs(a - b).max() / np.abs(a).max()))
+        out["runs"].append({
+            "cache_gib": gib, "cache_slots": st["cache_slots"], "ooc_s": t_ooc,
+            "ooc_tflops_fp64_equivalent": flops / t_ooc / 1e12, "ooc_over_in_core": t_ooc / t_in,
+            "bytes_h2d": st["bytes_h2d"], "bytes_d2h": st["bytes_d2h"],
+            "h2d_gbps": st["bytes_h2d"] / t_ooc / 1e9, "d2h_gbps": st["bytes_d2h"] / t_ooc / 1e9,
+            "tiles_reloaded": st["tiles_reloaded"], "evictions": st["evictions"],
+            "chunks": st["chunks"], "max_rel_diff_sampled_tiles_vs_in_core": worst})
+    del Ah, img
+    Abuf.close()
+    Ibuf.close()
     return out
 
 
@@ -285,6 +396,10 @@ def main():
                     help="before the steps, copy this many GiB device to device (the calibration "
                          "copy for HBM byte counters)")
     ap.add_argument("--ooc-only", action="store_true", help="only the out-of-core leg")
+    ap.add_argument("--ooc-mixed-only", action="store_true",
+                    help="only the out-of-core mixed-precision leg")
+    ap.add_argument("--no-ooc-mixed", action="store_true",
+                    help="skip the out-of-core mixed-precision leg")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the tile Cholesky here runs on a single MI355X "
@@ -301,13 +416,15 @@ def main():
         from paper_2410_09819_amd import build
         build.build()
     dev = torch.device("cuda", 0)
-    if args.mxp_only or args.grad_only or args.ooc_only:
+    if args.mxp_only or args.grad_only or args.ooc_only or args.ooc_mixed_only:
         if args.mxp_only:
             res = mxp_comparison(tc, si, dev, args.mxp_n or None)
         elif args.grad_only:
             res = grad_leg(tc, si, dev)
-        else:
+        elif args.ooc_only:
             res = ooc_leg(tc, si, dev)
+        else:
+            res = ooc_mixed_leg(tc, si, dev)
         print(json.dumps(res), flush=True)
         return
     w = si.WORKLOADS[args.workload]
@@ -398,6 +515,7 @@ def main():
     out["mxp_vs_fp64"] = None if args.no_mxp else mxp_comparison(tc, si, dev)
     out["loglik_grad"] = None if args.no_grad else grad_leg(tc, si, dev)
     out["ooc_vs_in_core"] = None if args.no_ooc else ooc_leg(tc, si, dev)
+    out["ooc_mixed_vs_in_core"] = None if args.no_ooc_mixed else ooc_mixed_leg(tc, si, dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)

@@ -112,6 +112,12 @@ typedef struct {
  * j*Nt - j*(j-1)/2 + (i-j). Returns -1 if the indices are out of range. */
 int64_t tc_tile_offset(int32_t Nt, int32_t i, int32_t j);
 
+/* Pinned (page-locked) host memory of exactly `bytes` bytes for the
+ * out-of-core entry points' host buffers (hipHostMalloc); *out = NULL and
+ * TC_ENOMEM when the system refuses. Free with tc_host_free. */
+tc_status tc_host_alloc(size_t bytes, void **out);
+tc_status tc_host_free(void *p);
+
 /* Library version string (static storage). */
 const char *tc_version(void);
 
@@ -232,7 +238,7 @@ tc_status tc_factorize_ooc(tc_ctx *ctx, int64_t n, int32_t nb, const double *A_h
 size_t tc_ooc_mixed_host_bytes(int64_t n, int32_t nb, const uint8_t *map);
 
 /* Device cache bytes tc_factorize_ooc_mixed needs to hold `slots` tile
- * slots (plus its tables and the staging of one column); at least
+ * slots (plus its tables and the staging of new tiles); at least
  * 2 * Nt slots are required. 0 if the shape or the map is invalid. */
 size_t tc_ooc_mixed_cache_bytes(int64_t n, int32_t nb, const uint8_t *map, int64_t slots);
 
@@ -244,11 +250,12 @@ size_t tc_ooc_mixed_cache_bytes(int64_t n, int32_t nb, const uint8_t *map, int64
  * L_host: pinned host memory of L_host_bytes >= tc_ooc_mixed_host_bytes
  *    bytes receiving the factor image described there.
  * cache: device buffer of cache_bytes bytes holding the device tables, a
- *    staging area for one column of new tiles, and fixed-size slots (one
- *    tile in its class plus the operand copies it is multiplied in, rebuilt
- *    on the device when the tile is loaded); at least 2 * Nt slots, else
- *    TC_ENOMEM with the required size in tc_last_error(). The two working
- *    columns come from the context workspace.
+ *    staging area for new tiles (two columns' worth), four binary64
+ *    working columns (A is prefetched up to three columns ahead) and
+ *    fixed-size slots (one tile in its class plus the operand copies it is
+ *    multiplied in, rebuilt on the device when the tile is loaded); at
+ *    least 2 * Nt slots, else TC_ENOMEM with the required size in
+ *    tc_last_error().
  * Updates into a tile of class p are computed as in tc_factorize (same
  * kernels; the summation is split at the chunk boundaries, so results
  * agree with the in-core factor up to rounding). Runs on the compute stream

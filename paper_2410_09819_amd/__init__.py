@@ -115,6 +115,8 @@ def lib():
         "tc_logdet": (_i32, [_vp, _vp, ctypes.POINTER(ctypes.c_double)]),
         "tc_factorize_ooc": (_i32, [_vp, _i64, _i32, _vp, _vp, _vp, _sz, ctypes.POINTER(OocStats)]),
         "tc_ooc_mixed_host_bytes": (_sz, [_i64, _i32, _vp]),
+        "tc_host_alloc": (_i32, [_sz, ctypes.POINTER(_vp)]),
+        "tc_host_free": (_i32, [_vp]),
         "tc_ooc_mixed_cache_bytes": (_sz, [_i64, _i32, _vp, _i64]),
         "tc_factorize_ooc_mixed": (_i32, [_vp, _i64, _i32, _vp, _vp, _vp, _sz, _vp, _sz,
                                           ctypes.POINTER(OocStats)]),
@@ -340,6 +342,36 @@ def factorize_ooc(ctx: Context, A_host, n: int, nb: int, cache, L_host=None) -> 
                                   cache.data_ptr(), cache.numel() * cache.element_size(),
                                   ctypes.byref(st)))
     return st.as_dict()
+
+
+class PinnedBuffer:
+    """Pinned host memory of an exact size (tc_host_alloc), exposed as a CPU
+    uint8 tensor (`.tensor`, or typed views through `.view(dtype)`); freed
+    by close() or when the object is collected. Views must not outlive it."""
+
+    def __init__(self, nbytes: int):
+        import torch
+        p = _vp()
+        _check(lib().tc_host_alloc(nbytes, ctypes.byref(p)))
+        self._ptr = p
+        self.nbytes = nbytes
+        raw = (ctypes.c_uint8 * nbytes).from_address(p.value)
+        self.tensor = torch.frombuffer(raw, dtype=torch.uint8)
+
+    def view(self, dtype):
+        return self.tensor.view(dtype)
+
+    def close(self):
+        if self._ptr is not None and self._ptr.value:
+            self.tensor = None
+            lib().tc_host_free(self._ptr)
+        self._ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def ooc_mixed_host_bytes(n: int, nb: int, cmap) -> int:

@@ -5,9 +5,10 @@
 // Host memory: A (binary64 packed lower tiles, read) and the factor image
 // (every tile in its class, packed order, followed by the tile scale
 // exponents), so each factor tile crosses the link in its class's bytes.
-// HBM: two binary64 working columns (the context workspace), the device
-// tables of the mixed factor, a staging area for one column of new tiles,
-// and fixed-size cache slots. A slot holds one tile "bundle": the stored
+// HBM (the caller's cache buffer): the device tables of the mixed factor,
+// staging for new tiles, four binary64 working columns (A's columns are
+// prefetched up to three columns ahead, so the link keeps busy while the
+// early, short columns compute), and fixed-size cache slots. A slot holds one tile "bundle": the stored
 // tile, then the operand copies the tile is multiplied in (the same copies
 // the in-core path keeps), rebuilt on the device from the stored bits when
 // a tile is loaded. The class-group kernels of the in-core path run
@@ -19,9 +20,12 @@
 // group and the low-class groups of the chunk); (2) POTRF and TRSM on the
 // working column; (3) finalize rounds the new tiles into their classes,
 // straight into free slots (they are used again in the next column) or into
-// the staging area; (4) the diagonal tile and the new tiles are written back
-// in their classes. Eviction is the farthest next use under the static
-// schedule, as in the FP64 path; row k's tiles are dead after column k.
+// a staging area (two halves, alternating by column); (4) the diagonal tile
+// (copied out of the working column first) and the new tiles are written
+// back in their classes. The low-class groups of a chunk run on a side stream,
+// concurrently with its FP64 group. Eviction is the farthest next use under
+// the static schedule, as in the FP64 path; row k's tiles are dead after
+// column k.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -96,6 +100,7 @@ struct Tables {
 };
 
 constexpr int kRing = 16;
+constexpr int kWork = 4;  // working columns: A is prefetched up to kWork - 1 columns ahead
 
 Tables tables_of(const Plan& P, size_t ring_entries) {
     Tables T;
@@ -136,7 +141,10 @@ extern "C" size_t tc_ooc_mixed_cache_bytes(int64_t n, int32_t nb, const uint8_t*
     const int Nt = P.Nt;
     const Bundle B = bundle_of(P);
     const Tables T = tables_of(P, (size_t)Nt * Nt + 2 * (size_t)Nt);
-    return T.total + (size_t)(Nt > 1 ? Nt - 1 : 1) * B.bytes + (size_t)slots * B.bytes;
+    const size_t half = (size_t)(Nt > 1 ? Nt - 1 : 1) * B.bytes;
+    const size_t dbytes = align_up((size_t)P.nb * P.nb * sizeof(double));
+    const size_t colmax = align_up((size_t)Nt * P.nb * P.nb * sizeof(double));
+    return T.total + 2 * half + 2 * dbytes + kWork * colmax + (size_t)slots * B.bytes;
 }
 
 extern "C" tc_status tc_factorize_ooc_mixed(tc_ctx* ctx, int64_t n, int32_t nb, const double* A_host,
@@ -157,8 +165,13 @@ extern "C" tc_status tc_factorize_ooc_mixed(tc_ctx* ctx, int64_t n, int32_t nb, 
     // slots: what is left after the tables and the staging of one column
     const size_t ring_entries = (size_t)Nt * Nt + 2 * (size_t)Nt;
     const Tables T = tables_of(P, ring_entries);
-    const size_t staging = (size_t)(Nt > 1 ? Nt - 1 : 1) * B.bytes;
-    const size_t fixed = T.total + staging;
+    // staging: two halves (columns alternate) of Nt - 1 bundles, then two
+    // binary64 buffers for the diagonal tile's write-back
+    const size_t half = (size_t)(Nt > 1 ? Nt - 1 : 1) * B.bytes;
+    const size_t dbytes = align_up((size_t)nb2 * sizeof(double));
+    const size_t staging = 2 * half + 2 * dbytes;
+    const size_t colmax = align_up((size_t)Nt * nb2 * sizeof(double));
+    const size_t fixed = T.total + staging + kWork * colmax;
     const int64_t slots = cache_bytes > fixed ? (int64_t)((cache_bytes - fixed) / B.bytes) : 0;
     if (slots < 2 * (int64_t)Nt)
         return fail(TC_ENOMEM, "tile cache too small: need at least " +
@@ -172,8 +185,6 @@ extern "C" tc_status tc_factorize_ooc_mixed(tc_ctx* ctx, int64_t n, int32_t nb, 
     const size_t big_cap = Ly.potrf - Ly.big;
     double* pot = reinterpret_cast<double*>(ctx->ws + Ly.potrf);
     double* part = reinterpret_cast<double*>(ctx->ws + Ly.small);
-    double* Wb[2] = {reinterpret_cast<double*>(ctx->ws + Ly.panel),
-                     reinterpret_cast<double*>(ctx->ws + Ly.panel) + (size_t)Nt * nb2};
     char* cbase = static_cast<char*>(cache);
     int64_t* d_toff = reinterpret_cast<int64_t*>(cbase + T.toff);
     int64_t* d_shoff = reinterpret_cast<int64_t*>(cbase + T.shoff);
@@ -184,12 +195,18 @@ extern "C" tc_status tc_factorize_ooc_mixed(tc_ctx* ctx, int64_t n, int32_t nb, 
     int* d_lists = reinterpret_cast<int*>(cbase + T.lists);
     char* d_ring = cbase + T.ring;
     const size_t ring_bytes = align_up(ring_entries * (2 * sizeof(int64_t) + sizeof(int)));
-    const size_t stage0 = T.total;          // staging bundles
-    const size_t slot0 = T.total + staging;  // slot s at slot0 + s * B.bytes
+    const size_t stage0 = T.total;          // staging bundles, half h at stage0 + h * half
+    const size_t diag0 = T.total + 2 * half;  // diagonal write-back buffer d at diag0 + d * dbytes
+    const size_t work0 = T.total + staging;  // working column of column k at work0 + (k % kWork) * colmax
+    const size_t slot0 = work0 + kWork * colmax;  // slot s at slot0 + s * B.bytes
+    auto work = [&](int c) { return reinterpret_cast<double*>(cbase + work0 + (size_t)(c % kWork) * colmax); };
     if (tc_status s = ctx_ooc_resources(ctx, (size_t)kRing * ring_bytes)) return s;
     char* h_ring = static_cast<char*>(ctx->pinned);
     char* Lh = static_cast<char*>(L_host);
-    hipStream_t cs = ctx->stream, hs = ctx->h2d, ds = ctx->d2h;
+    if (tc_status s = ctx_aux_streams(ctx)) return s;
+    // sa: prefetch of A's columns (host -> device), apart from the operand
+    // reloads on hs so that a column of A never queues ahead of them
+    hipStream_t cs = ctx->stream, hs = ctx->h2d, ds = ctx->d2h, sl = ctx->aux[1], sa = ctx->aux[0];
 
     std::vector<int> lists, lcount;
     double cflops[5];
@@ -213,7 +230,8 @@ extern "C" tc_status tc_factorize_ooc_mixed(tc_ctx* ctx, int64_t n, int32_t nb, 
     for (int64_t s = slots - 1; s >= 0; --s) free_slots.push_back((int)s);
     std::set<std::pair<int, int>> cached;  // (n, m) of cached tiles
     std::vector<int> col_d2h(Nt, -1), col_done(Nt, -1);
-    int evW[2] = {-1, -1};
+    int stage_last[2] = {-1, -1};  // last column whose new tiles used staging half h
+    std::vector<int> evW(Nt, -1);
     tc_ooc_stats st;
     std::memset(&st, 0, sizeof(st));
 
@@ -291,18 +309,26 @@ extern "C" tc_status tc_factorize_ooc_mixed(tc_ctx* ctx, int64_t n, int32_t nb, 
     TC_HIP(hipEventRecord(E.ev[e0], cs));
     TC_HIP(hipStreamWaitEvent(hs, E.ev[e0], 0));
     TC_HIP(hipStreamWaitEvent(ds, E.ev[e0], 0));
-    // accumulators of column 0
-    TC_HIP(hipMemcpyAsync(Wb[0], A_host, (size_t)Nt * nb2 * sizeof(double), hipMemcpyHostToDevice, hs));
-    st.bytes_h2d += (uint64_t)Nt * nb2 * sizeof(double);
-    if (tc_status s = E.get(evW[0])) return s;
-    TC_HIP(hipEventRecord(E.ev[evW[0]], hs));
+    TC_HIP(hipStreamWaitEvent(sa, E.ev[e0], 0));
+    // A's column c into working column c % kWork (after column c - kWork is finalized)
+    auto prefetch = [&](int c) -> tc_status {
+        if (c >= kWork) TC_HIP(hipStreamWaitEvent(sa, E.ev[col_done[c - kWork]], 0));
+        const size_t bytes = (size_t)(Nt - c) * nb2 * sizeof(double);
+        TC_HIP(hipMemcpyAsync(work(c), A_host + tc::tile_off(Nt, c, c) * nb2, bytes, hipMemcpyHostToDevice, sa));
+        st.bytes_h2d += bytes;
+        if (tc_status s = E.get(evW[c])) return s;
+        TC_HIP(hipEventRecord(E.ev[evW[c]], sa));
+        return TC_OK;
+    };
+    for (int c = 0; c < kWork && c < Nt; ++c)
+        if (tc_status s = prefetch(c)) return s;
 
     std::vector<int64_t> upd;
     std::vector<int> rebuild;
     for (int k = 0; k < Nt; ++k) {
-        double* W = Wb[k & 1];
+        double* W = work(k);
         const int rows = Nt - k;
-        TC_HIP(hipStreamWaitEvent(cs, E.ev[evW[k & 1]], 0));
+        TC_HIP(hipStreamWaitEvent(cs, E.ev[evW[k]], 0));
         if (k > 0) {
             int nc = k;
             if ((int64_t)rows * k > slots) nc = (int)std::max<int64_t>(1, slots / (2 * (int64_t)rows));
@@ -339,18 +365,34 @@ extern "C" tc_status tc_factorize_ooc_mixed(tc_ctx* ctx, int64_t n, int32_t nb, 
                     TC_HIP(hipStreamWaitEvent(cs, E.ev[el], 0));
                     if (tc_status r = apply(upd, rebuild)) return r;
                 }
+                // the low-class groups (disjoint tiles of W) run on a side
+                // stream, concurrently with the FP64 group; both join here
+                bool low = false;
+                for (int cls = 1; cls <= 4; ++cls) low = low || count(k, cls) > 0;
+                if (low) {
+                    int ef;
+                    if (tc_status r = E.get(ef)) return r;
+                    TC_HIP(hipEventRecord(E.ev[ef], cs));
+                    TC_HIP(hipStreamWaitEvent(sl, E.ev[ef], 0));
+                    for (int cls = 1; cls <= 4; ++cls) {
+                        const int cnt = count(k, cls);
+                        if (!cnt) continue;
+                        if (cls == TC_FP32)
+                            TC_HIP(tc::launch_mxp_gemm_f32(sl, W, Nt, nb, k, n0, n1, list(k, cls), cnt, cbase,
+                                                           d_shoff, d_cscl));
+                        else
+                            TC_HIP(tc::launch_mxp_gemm_narrow(sl, W, Nt, nb, k, n0, n1, list(k, cls), cnt,
+                                                              cls, cbase, d_shoff, d_cscl));
+                    }
+                }
                 TC_HIP(tc::launch_mxp_gemm_f64(cs, W, Nt, nb, k, n0, n1, list(k, TC_FP64),
                                                count(k, TC_FP64), true, cbase, d_toff, d_tcls, d_tscl,
                                                big, big_cap / sizeof(double)));
-                for (int cls = 1; cls <= 4; ++cls) {
-                    const int cnt = count(k, cls);
-                    if (!cnt) continue;
-                    if (cls == TC_FP32)
-                        TC_HIP(tc::launch_mxp_gemm_f32(cs, W, Nt, nb, k, n0, n1, list(k, cls), cnt, cbase,
-                                                       d_shoff, d_cscl));
-                    else
-                        TC_HIP(tc::launch_mxp_gemm_narrow(cs, W, Nt, nb, k, n0, n1, list(k, cls), cnt, cls,
-                                                          cbase, d_shoff, d_cscl));
+                if (low) {
+                    int ej;
+                    if (tc_status r = E.get(ej)) return r;
+                    TC_HIP(hipEventRecord(E.ev[ej], sl));
+                    TC_HIP(hipStreamWaitEvent(cs, E.ev[ej], 0));
                 }
                 int er;
                 if (tc_status r = E.get(er)) return r;
@@ -366,7 +408,9 @@ extern "C" tc_status tc_factorize_ooc_mixed(tc_ctx* ctx, int64_t n, int32_t nb, 
         if (tc_status s = potrf_rec(ctx, W, nb, 0, nb, (int64_t)k * nb, d_info, pot)) return s;
         if (rows > 1) TC_HIP(tc::launch_trsm(cs, W + nb2, W, nb, (int64_t)(rows - 1) * nb, nb));
         // new tiles: free slots (used again in the next column) or staging
-        if (k >= 1) TC_HIP(hipStreamWaitEvent(cs, E.ev[col_d2h[k - 1]], 0));  // staging free
+        // half k & 1, free once the column that last used it is written back
+        const int h = k & 1;
+        bool staged = false;
         upd.clear();
         rebuild.clear();
         std::vector<size_t> where(rows, 0);
@@ -384,13 +428,21 @@ extern "C" tc_status tc_factorize_ooc_mixed(tc_ctx* ctx, int64_t n, int32_t nb, 
                 cached.insert({k, m});
                 new_slot[m - k] = s;
             } else {
-                o = stage0 + (size_t)(m - k - 1) * B.bytes;
+                o = stage0 + (size_t)h * half + (size_t)(m - k - 1) * B.bytes;
+                staged = true;
             }
             where[m - k] = o;
             upd.push_back(t);
             upd.push_back((int64_t)o);
         }
+        if (staged && stage_last[h] >= 0) TC_HIP(hipStreamWaitEvent(cs, E.ev[col_d2h[stage_last[h]]], 0));
+        if (staged) stage_last[h] = k;
         if (tc_status r = apply(upd, rebuild)) return r;
+        // the diagonal tile leaves the working column on the device, so the
+        // next prefetch into it does not wait for the write-back
+        if (k >= 2) TC_HIP(hipStreamWaitEvent(cs, E.ev[col_d2h[k - 2]], 0));
+        TC_HIP(hipMemcpyAsync(cbase + diag0 + (size_t)h * dbytes, W, (size_t)nb2 * sizeof(double),
+                              hipMemcpyDeviceToDevice, cs));
         TC_HIP(tc::launch_mxp_finalize(cs, W, Nt, nb, k, part, cbase, d_toff, d_tcls, d_tscl, d_shoff,
                                        d_cscl));
         if (tc_status s = E.get(col_done[k])) return s;
@@ -399,7 +451,8 @@ extern "C" tc_status tc_factorize_ooc_mixed(tc_ctx* ctx, int64_t n, int32_t nb, 
         // the others from their slots or the staging area
         TC_HIP(hipStreamWaitEvent(ds, E.ev[col_done[k]], 0));
         const int64_t tkk = tc::tile_off(Nt, k, k);
-        TC_HIP(hipMemcpyAsync(Lh + P.toff[tkk], W, (size_t)nb2 * sizeof(double), hipMemcpyDeviceToHost, ds));
+        TC_HIP(hipMemcpyAsync(Lh + P.toff[tkk], cbase + diag0 + (size_t)h * dbytes,
+                              (size_t)nb2 * sizeof(double), hipMemcpyDeviceToHost, ds));
         st.bytes_d2h += (uint64_t)nb2 * sizeof(double);
         for (int m = k + 1; m < Nt; ++m) {
             const int64_t t = tc::tile_off(Nt, m, k);
@@ -414,19 +467,9 @@ extern "C" tc_status tc_factorize_ooc_mixed(tc_ctx* ctx, int64_t n, int32_t nb, 
                 slot_reader[new_slot[m - k]] = col_done[k];
                 slot_d2h[new_slot[m - k]] = col_d2h[k];
             }
-        // prefetch the accumulators of column k+1 into the other working column
-        if (k + 1 < Nt) {
-            double* Wn = Wb[(k + 1) & 1];
-            if (k >= 1) {
-                TC_HIP(hipStreamWaitEvent(hs, E.ev[col_done[k - 1]], 0));
-                TC_HIP(hipStreamWaitEvent(hs, E.ev[col_d2h[k - 1]], 0));
-            }
-            TC_HIP(hipMemcpyAsync(Wn, A_host + tc::tile_off(Nt, k + 1, k + 1) * nb2,
-                                  (size_t)(rows - 1) * nb2 * sizeof(double), hipMemcpyHostToDevice, hs));
-            st.bytes_h2d += (uint64_t)(rows - 1) * nb2 * sizeof(double);
-            if (tc_status s = E.get(evW[(k + 1) & 1])) return s;
-            TC_HIP(hipEventRecord(E.ev[evW[(k + 1) & 1]], hs));
-        }
+        // A's column k + kWork into the working column column k just released
+        if (k + kWork < Nt)
+            if (tc_status s = prefetch(k + kWork)) return s;
     }
     TC_HIP(hipStreamWaitEvent(cs, E.ev[col_d2h[Nt - 1]], 0));
     TC_HIP(hipEventRecord(ctx->ev1, cs));

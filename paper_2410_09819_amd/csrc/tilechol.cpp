@@ -348,6 +348,24 @@ int64_t tc_tile_offset(int32_t Nt, int32_t i, int32_t j) {
     return tc::tile_off(Nt, i, j);
 }
 
+tc_status tc_host_alloc(size_t bytes, void** out) {
+    if (!out || bytes == 0) return fail(TC_EINVAL, "bad argument");
+    *out = nullptr;
+    hipError_t e = hipHostMalloc(out, bytes, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        *out = nullptr;
+        return fail(TC_ENOMEM, "pinned host allocation of " + std::to_string(bytes) +
+                                   " bytes failed: " + hipGetErrorString(e));
+    }
+    return TC_OK;
+}
+
+tc_status tc_host_free(void* p) {
+    if (!p) return TC_OK;
+    TC_HIP(hipHostFree(p));
+    return TC_OK;
+}
+
 const char* tc_version(void) { return "tilechol 0.3 (gfx950, FP64 MFMA, mixed precision on FP16/BF16/FP8 MFMA)"; }
 
 const char* tc_last_error(void) { return g_err.c_str(); }

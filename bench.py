@@ -376,6 +376,61 @@ def ooc_mixed_leg(tc, si, dev, n=90112, nb=2048, eps=1e-9, caches_gib=(40, 20)):
     return out
 
 
+def kl_sweep(tc, si, dev, ns=(32768, 65536), nb=1024, betas=(0.02627, 0.078809, 0.210158),
+             eps_list=(1e-5, 1e-6, 1e-7, 1e-8), nugget=1e-4, seed=3):
+    """The paper's mixed-precision study (Section V): for the Matern fields
+    theta = (1, beta, 1/2) at the three correlation levels and the target
+    accuracies of its figures, the KL divergence of Eq. 3 at y = 0,
+    D = l_0 - l_a = (log|Sigma_a| - log|Sigma_0|) / 2, with Sigma_0 factored
+    in FP64 and Sigma_a in mixed precision, and the factorization rates
+    (FP64-equivalent TFLOP/s, n^3/3 over the factorization time). A nugget
+    of 1e-4 is added on the diagonal (the map is computed from the tile
+    norms of the same matrix)."""
+    import numpy as np
+    import torch
+    out = {"workload": "Matern nu=1/2 sigma2=1 nugget=%g, nb=%d, Z-ordered seeded points (seed %d)" % (nugget, nb, seed),
+           "rows": []}
+    for n in ns:
+        Nt = n // nb
+        pts = torch.from_numpy(si.points(n, seed=seed)).to(dev)
+        ctx = tc.Context(n, nb)
+        for beta in betas:
+            A, tf, fro = tc.matern_tiles(ctx, pts, (1.0, beta, 0.5, nugget), nb)
+            tf_h = tf.cpu().numpy()
+            storage = torch.empty(tc.factor_bytes(n, nb) // 8, dtype=torch.float64, device=dev)
+            F = tc.factorize(ctx, A, n, nb, storage=storage)
+            ld0, ms0 = tc.logdet(ctx, F), F.stats.ms_total
+            F.close()
+            del storage, F
+            torch.cuda.empty_cache()
+            for eps in eps_list:
+                cm = tc.precision_map(Nt, tf_h, fro, eps)
+                storage = torch.empty(tc.factor_bytes(n, nb, cm) // 8, dtype=torch.float64, device=dev)
+                row = {"n": n, "beta": beta, "eps": eps, "fp64_factor_ms": ms0,
+                       "fp64_tflops": n ** 3 / 3.0 / ms0 / 1e9}
+                try:
+                    F = tc.factorize(ctx, A, n, nb, cmap=cm, storage=storage)
+                    ld = tc.logdet(ctx, F)
+                    ms = F.stats.ms_total
+                    cf = list(F.stats.class_flops)
+                    tot = sum(cf)
+                    row.update({"kl": 0.5 * (ld - ld0), "mxp_factor_ms": ms,
+                                "mxp_tflops_fp64_equivalent": n ** 3 / 3.0 / ms / 1e9,
+                                "speedup_factor": ms0 / ms,
+                                "flop_share": {k: cf[i] / tot for i, k in enumerate(("fp64", "fp32", "fp16", "bf16", "fp8"))}})
+                    F.close()
+                    del F
+                except tc.NotPositiveDefinite as e:
+                    row.update({"kl": None, "breakdown_column": e.info})
+                del storage
+                torch.cuda.empty_cache()
+                out["rows"].append(row)
+                progress("kl sweep: n=%d beta=%g eps=%g kl=%s" % (n, beta, eps, row.get("kl")))
+            del A, tf
+            torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -400,6 +455,8 @@ def main():
                     help="only the out-of-core mixed-precision leg")
     ap.add_argument("--no-ooc-mixed", action="store_true",
                     help="skip the out-of-core mixed-precision leg")
+    ap.add_argument("--kl-sweep", action="store_true",
+                    help="only the KL-divergence / rate sweep over beta and the target accuracy")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the tile Cholesky here runs on a single MI355X "
@@ -416,8 +473,10 @@ def main():
         from paper_2410_09819_amd import build
         build.build()
     dev = torch.device("cuda", 0)
-    if args.mxp_only or args.grad_only or args.ooc_only or args.ooc_mixed_only:
-        if args.mxp_only:
+    if args.mxp_only or args.grad_only or args.ooc_only or args.ooc_mixed_only or args.kl_sweep:
+        if args.kl_sweep:
+            res = kl_sweep(tc, si, dev)
+        elif args.mxp_only:
             res = mxp_comparison(tc, si, dev, args.mxp_n or None)
         elif args.grad_only:
             res = grad_leg(tc, si, dev)

@@ -83,13 +83,22 @@ hipError_t launch_zero_upper(hipStream_t s, double* L, int Nt, int nb);
 // Solves with the factor (solve.hip). Lkk is the (binary64) diagonal tile.
 hipError_t launch_trsv_diag(hipStream_t s, const double* Lkk, int nb, double* B, int64_t ldb,
                             int nrhs, bool transpose);
-// B rows below tile k -= L[k+1.., k] Y_k (Y_k = B rows of tile k).
-hipError_t launch_fwd_update(hipStream_t s, const TileView& L, int k, const double* Yk,
-                             double* Bbelow, int64_t ldb, int nrhs);
-// Y_k -= sum_{m>k} L_mk^T X_m (X = B rows below tile k).
-hipError_t launch_bwd_update(hipStream_t s, const TileView& L, int k, const double* Xbelow,
-                             double* Yk, int64_t ldb, int nrhs, double* partial, int splits);
+// B rows of tiles m = k+1+t0 .. k+t0+tcount -= L[m, k] Y_k (Y_k = B rows of
+// tile k; Bbelow = B rows of tile k+1+t0).
+hipError_t launch_fwd_update(hipStream_t s, const TileView& L, int k, int t0, int tcount,
+                             const double* Yk, double* Bbelow, int64_t ldb, int nrhs);
+// Y_k -= sum L_mk^T X_m over m = k+1+t0 .. k+t0+tcount (Xbelow = B rows of
+// tile k+1+t0); partial: bwd_partial_doubles(nb) doubles of workspace.
+hipError_t launch_bwd_update(hipStream_t s, const TileView& L, int k, int t0, int tcount,
+                             const double* Xbelow, double* Yk, int64_t ldb, int nrhs,
+                             double* partial);
 int bwd_splits(int64_t rows);
+inline int64_t bwd_partial_doubles(int nb) { return (int64_t)64 * nb * 16; }
+// Y -= op(T) X for the single tile T = (ti, tj) of a factor view (op = T or
+// T^T), split over nb / 64 inner blocks (partial: nb / 64 * nb * 16 doubles,
+// <= bwd_partial_doubles(nb)) and reduced in a fixed order.
+hipError_t launch_tile_update(hipStream_t s, const TileView& L, int ti, int tj, bool transpose,
+                              const double* X, double* Y, int64_t ldb, int nrhs, double* partial);
 hipError_t launch_logdet_partials(hipStream_t s, const TileView& L, double* partial);
 
 // Mixed precision (mxp.hip): class-group panel updates into the working

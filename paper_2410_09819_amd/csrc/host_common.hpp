@@ -23,7 +23,8 @@ struct tc_ctx {
     // groups of a mixed-precision column, and the events that order them
     hipStream_t aux[2] = {nullptr, nullptr};
     hipEvent_t aux_ev[3] = {nullptr, nullptr, nullptr};
-    std::vector<hipEvent_t> la_ev;  // lookahead schedule events
+    std::vector<hipEvent_t> la_ev;     // lookahead schedule events
+    std::vector<hipEvent_t> solve_ev;  // triangular-solve lookahead events
     // out-of-core resources, created on first use
     hipStream_t h2d = nullptr, d2h = nullptr;
     void* pinned = nullptr;

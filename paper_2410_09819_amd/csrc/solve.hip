@@ -76,12 +76,12 @@ __global__ __launch_bounds__(1024) void trsv_diag_kernel(const double* __restric
             for (int i = jb + kDB + tid; i < nb; i += 1024) {
                 double s[kDR] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll 1
-                for (int l0 = 0; l0 < kDB; l0 += 16) {
-                    double lv[16];
+                for (int l0 = 0; l0 < kDB; l0 += 32) {
+                    double lv[32];
 #pragma unroll
-                    for (int u = 0; u < 16; ++u) lv[u] = Lkk[(int64_t)(jb + l0 + u) * nb + i];
+                    for (int u = 0; u < 32; ++u) lv[u] = Lkk[(int64_t)(jb + l0 + u) * nb + i];
 #pragma unroll
-                    for (int u = 0; u < 16; ++u)
+                    for (int u = 0; u < 32; ++u)
 #pragma unroll
                         for (int c = 0; c < kDR; ++c) s[c] += lv[u] * X[(l0 + u) * kDR + c];
                 }
@@ -94,12 +94,12 @@ __global__ __launch_bounds__(1024) void trsv_diag_kernel(const double* __restric
                 const d2* li = reinterpret_cast<const d2*>(Lkk + (int64_t)i * nb + jb);  // L[jb + l][i]
                 double s[kDR] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll 1
-                for (int l0 = 0; l0 < kDB / 2; l0 += 8) {
-                    d2 lv[8];
+                for (int l0 = 0; l0 < kDB / 2; l0 += 16) {
+                    d2 lv[16];
 #pragma unroll
-                    for (int u = 0; u < 8; ++u) lv[u] = li[l0 + u];
+                    for (int u = 0; u < 16; ++u) lv[u] = li[l0 + u];
 #pragma unroll
-                    for (int u = 0; u < 8; ++u)
+                    for (int u = 0; u < 16; ++u)
 #pragma unroll
                         for (int c = 0; c < kDR; ++c)
                             s[c] += lv[u].x * X[(2 * (l0 + u)) * kDR + c] +
@@ -167,7 +167,7 @@ __device__ __forceinline__ void fwd_row(double (&acc)[kNR], const char* tile, in
 // combine their partial sums in LDS in a fixed order. Y entries are uniform
 // across a wave.
 constexpr int kFwdRows = 64;
-__global__ __launch_bounds__(256) void fwd_update_kernel(TileView L, int k,
+__global__ __launch_bounds__(256) void fwd_update_kernel(TileView L, int k, int t0,
                                                          const double* __restrict__ Y,
                                                          double* __restrict__ Bb, int64_t ldb,
                                                          int nrhs) {
@@ -180,7 +180,7 @@ __global__ __launch_bounds__(256) void fwd_update_kernel(TileView L, int k,
     const int nr = nrhs - c0 < kNR ? nrhs - c0 : kNR;
     const int64_t r0 = (int64_t)blockIdx.x * kFwdRows;
     int cls, scale;
-    const char* tile = view_tile(L, k + 1 + (int)(r0 / nb), k, cls, scale);
+    const char* tile = view_tile(L, k + 1 + t0 + (int)(r0 / nb), k, cls, scale);
     const int row = (int)(r0 % nb) + lane;
     const double* Yc = Y + (int64_t)c0 * ldb;
     double acc[kNR];
@@ -216,7 +216,7 @@ __global__ __launch_bounds__(256) void fwd_update_kernel(TileView L, int k,
 // X[r][c] for the 64 columns j of this workgroup's strip.
 constexpr int kBwdStrip = 64;
 constexpr int kBwdSub = 64;
-__global__ __launch_bounds__(256) void bwd_partial_kernel(TileView L, int k, int64_t rows_per_split,
+__global__ __launch_bounds__(256) void bwd_partial_kernel(TileView L, int k, int t0, int64_t rows_per_split,
                                                           const double* __restrict__ X,
                                                           int64_t ldb, int nrhs, int rhs0,
                                                           double* __restrict__ partial) {
@@ -233,7 +233,7 @@ __global__ __launch_bounds__(256) void bwd_partial_kernel(TileView L, int k, int
     for (int64_t rb = rbeg; rb < rbeg + rows_per_split; rb += kBwdSub) {
         __syncthreads();
         int cls, scale;
-        const char* tile = view_tile(L, k + 1 + (int)(rb / nb), k, cls, scale);
+        const char* tile = view_tile(L, k + 1 + t0 + (int)(rb / nb), k, cls, scale);
         const int rr = (int)(rb % nb);
         for (int e = tid; e < kBwdStrip * kBwdSub; e += 256) {
             const int j = e / kBwdSub, r = e % kBwdSub;
@@ -264,6 +264,65 @@ __global__ void bwd_reduce_kernel(double* __restrict__ Y, int nb, int64_t ldb, i
     double s = 0.0;
     for (int sp = 0; sp < splits; ++sp) s += partial[(int64_t)sp * nb * kNR + e];
     Y[(int64_t)(rhs0 + c) * ldb + j] -= s;
+}
+
+// One tile's contribution to a block of right-hand sides, split for
+// parallelism: Y (nb x nr) -= op(T) X, op(T) = T (forward, T = L_{k+1,k}
+// ... any tile of a factor view) or T^T (backward), X = nb rows of B.
+// Workgroup (i, s) takes output rows 64 i .. 64 i + 63 and the 64 inner
+// indices 64 s .. 64 s + 63: the 64 x 64 block of op(T) (decoded from its
+// class) and the X rows go through LDS, each thread forms 4 (row, rhs)
+// sums, and writes its partial to part[s][row][rhs]; tile_update_reduce
+// subtracts the nb / 64 partials in a fixed order.
+constexpr int kTU = 64;
+__global__ __launch_bounds__(256) void tile_update_kernel(TileView L, int ti, int tj, int transpose,
+                                                          const double* __restrict__ X, int64_t ldb,
+                                                          int nrhs, int rhs0,
+                                                          double* __restrict__ part) {
+    __shared__ double Ts[kTU * (kTU + 1)];  // Ts[q * 65 + r] = op(T)[r0 + r][q0 + q]
+    __shared__ double Xs[kTU * kNR];
+    const int nb = L.nb;
+    const int tid = threadIdx.x;
+    const int r0 = blockIdx.x * kTU, q0 = blockIdx.y * kTU;
+    const int nr = nrhs - rhs0 < kNR ? nrhs - rhs0 : kNR;
+    int cls, scale;
+    const char* tile = view_tile(L, ti, tj, cls, scale);
+    for (int e = tid; e < kTU * kTU; e += 256) {
+        // consecutive threads read consecutive elements of a stored column
+        const int a = e % kTU, b = e / kTU;
+        if (!transpose) {  // T[r0 + a][q0 + b]: column q0 + b, row r0 + a
+            Ts[b * (kTU + 1) + a] = load_elem(tile, (int64_t)(q0 + b) * nb + r0 + a, cls, scale);
+        } else {  // T^T[r0 + b][q0 + a] = T[q0 + a][r0 + b]: column r0 + b, row q0 + a
+            Ts[a * (kTU + 1) + b] = load_elem(tile, (int64_t)(r0 + b) * nb + q0 + a, cls, scale);
+        }
+    }
+    for (int e = tid; e < kTU * kNR; e += 256) {
+        const int q = e % kTU, c = e / kTU;
+        Xs[q * kNR + c] = c < nr ? X[(int64_t)(rhs0 + c) * ldb + q0 + q] : 0.0;
+    }
+    __syncthreads();
+    const int r = tid & 63, cg = tid >> 6;  // row, group of 4 right-hand sides
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int q = 0; q < kTU; ++q) {
+        const double t = Ts[q * (kTU + 1) + r];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc[u] += t * Xs[q * kNR + cg * 4 + u];
+    }
+    double* p = part + ((int64_t)blockIdx.y * nb + r0 + r) * kNR + cg * 4;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) p[u] = acc[u];
+}
+
+__global__ void tile_update_reduce_kernel(double* __restrict__ Y, int nb, int64_t ldb, int nrhs,
+                                          int rhs0, const double* __restrict__ part) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nb * kNR) return;
+    const int row = e / kNR, c = e % kNR;
+    if (rhs0 + c >= nrhs) return;
+    const int splits = nb / kTU;
+    double s = 0.0;
+    for (int sp = 0; sp < splits; ++sp) s += part[(int64_t)sp * nb * kNR + e];
+    Y[(int64_t)(rhs0 + c) * ldb + row] -= s;
 }
 
 __global__ __launch_bounds__(256) void logdet_kernel(TileView L, double* __restrict__ partial) {
@@ -308,13 +367,14 @@ hipError_t launch_trsv_diag(hipStream_t s, const double* Lkk, int nb, double* B,
     return hipGetLastError();
 }
 
-hipError_t launch_fwd_update(hipStream_t s, const TileView& L, int k, const double* Yk,
-                             double* Bbelow, int64_t ldb, int nrhs) {
-    const int64_t rows = (int64_t)(L.Nt - k - 1) * L.nb;
-    if (rows <= 0) return hipSuccess;
+hipError_t launch_fwd_update(hipStream_t s, const TileView& L, int k, int t0, int tcount,
+                             const double* Yk, double* Bbelow, int64_t ldb, int nrhs) {
+    if (tcount <= 0) return hipSuccess;
+    if (t0 < 0 || k + 1 + t0 + tcount > L.Nt) return hipErrorInvalidValue;
+    const int64_t rows = (int64_t)tcount * L.nb;
     if (rows % kFwdRows != 0 || L.nb % 32 != 0) return hipErrorInvalidValue;
     dim3 grid((unsigned)(rows / kFwdRows), (nrhs + kNR - 1) / kNR);
-    hipLaunchKernelGGL(fwd_update_kernel, grid, dim3(256), 0, s, L, k, Yk, Bbelow, ldb, nrhs);
+    hipLaunchKernelGGL(fwd_update_kernel, grid, dim3(256), 0, s, L, k, t0, Yk, Bbelow, ldb, nrhs);
     return hipGetLastError();
 }
 
@@ -327,18 +387,37 @@ int bwd_splits(int64_t rows) {
     return s < 1 ? 1 : (int)s;
 }
 
-hipError_t launch_bwd_update(hipStream_t s, const TileView& L, int k, const double* Xbelow,
-                             double* Yk, int64_t ldb, int nrhs, double* partial, int splits) {
-    const int64_t rows = (int64_t)(L.Nt - k - 1) * L.nb;
-    if (rows <= 0) return hipSuccess;
+hipError_t launch_bwd_update(hipStream_t s, const TileView& L, int k, int t0, int tcount,
+                             const double* Xbelow, double* Yk, int64_t ldb, int nrhs,
+                             double* partial) {
+    if (tcount <= 0) return hipSuccess;
+    if (t0 < 0 || k + 1 + t0 + tcount > L.Nt) return hipErrorInvalidValue;
+    const int64_t rows = (int64_t)tcount * L.nb;
+    const int splits = bwd_splits(rows);
     for (int rhs0 = 0; rhs0 < nrhs; rhs0 += kNR) {
         dim3 grid(L.nb / kBwdStrip, splits);
-        hipLaunchKernelGGL(bwd_partial_kernel, grid, dim3(256), 0, s, L, k, rows / splits, Xbelow,
+        hipLaunchKernelGGL(bwd_partial_kernel, grid, dim3(256), 0, s, L, k, t0, rows / splits, Xbelow,
                            ldb, nrhs, rhs0, partial);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(bwd_reduce_kernel, dim3((L.nb * kNR + 255) / 256), dim3(256), 0, s, Yk,
                            L.nb, ldb, nrhs, rhs0, splits, partial);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_tile_update(hipStream_t s, const TileView& L, int ti, int tj, bool transpose,
+                              const double* X, double* Y, int64_t ldb, int nrhs, double* partial) {
+    if (L.nb % kTU != 0) return hipErrorInvalidValue;
+    for (int rhs0 = 0; rhs0 < nrhs; rhs0 += kNR) {
+        hipLaunchKernelGGL(tile_update_kernel, dim3(L.nb / kTU, L.nb / kTU), dim3(256), 0, s, L, ti, tj,
+                           transpose ? 1 : 0, X, ldb, nrhs, rhs0, partial);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(tile_update_reduce_kernel, dim3((L.nb * kNR + 255) / 256), dim3(256), 0, s, Y,
+                           L.nb, ldb, nrhs, rhs0, partial);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

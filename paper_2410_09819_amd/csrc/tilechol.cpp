@@ -59,7 +59,8 @@ size_t big_bytes(int64_t n, int nb) {
             if (s > 1) mx = std::max(mx, (size_t)s * (size_t)(Nt - k) * nb * nb * sizeof(double));
         }
     }
-    mx = std::max(mx, (size_t)64 * nb * 16 * sizeof(double));  // backward-solve partials (<= 64 splits)
+    // backward-solve partials (<= 64 splits), one area per solve stream
+    mx = std::max(mx, (size_t)2 * tc::bwd_partial_doubles(nb) * sizeof(double));
     return mx;
 }
 
@@ -284,16 +285,45 @@ const double* diag_tile(const tc_factor* F, int k) {
 }
 
 // B <- (L L^T)^{-1} B, enqueued on the context stream (no synchronization).
-// B <- L^{-1} B (forward substitution by tile rows).
-tc_status fwd_enqueue(tc_ctx* ctx, const tc_factor* F, double* B, int64_t ldb, int nrhs) {
+// Both substitutions run a lookahead on a second stream: the long update of
+// the rows two or more tiles away from the diagonal solve in progress
+// overlaps the chain of diagonal-tile solves, which only waits for the
+// adjacent tile's update. ev[k] / ev[Nt + k]: diagonal solve k done (main)
+// / side update of column k done.
+tc_status solve_events(tc_ctx* ctx, int Nt) {
+    if (tc_status s = ctx_aux_streams(ctx)) return s;
+    while (ctx->solve_ev.size() < (size_t)2 * Nt) {
+        hipEvent_t e;
+        TC_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        ctx->solve_ev.push_back(e);
+    }
+    return TC_OK;
+}
+
+// B <- L^{-1} B (forward substitution by tile rows). big: partial sums of
+// the main stream's one-tile updates.
+tc_status fwd_enqueue(tc_ctx* ctx, const tc_factor* F, double* B, int64_t ldb, int nrhs,
+                      double* big) {
     const int Nt = F->Nt, nb = F->nb;
     const tc::TileView V = view_of(F);
+    if (tc_status s = solve_events(ctx, Nt)) return s;
+    hipStream_t sm = ctx->stream, ss = ctx->aux[0];
+    hipEvent_t* ev_t = ctx->solve_ev.data();
+    hipEvent_t* ev_s = ev_t + Nt;
     for (int k = 0; k < Nt; ++k) {
-        TC_HIP(tc::launch_trsv_diag(ctx->stream, diag_tile(F, k), nb, B + (int64_t)k * nb, ldb, nrhs,
-                                    false));
-        if (k + 1 < Nt)
-            TC_HIP(tc::launch_fwd_update(ctx->stream, V, k, B + (int64_t)k * nb,
-                                         B + (int64_t)(k + 1) * nb, ldb, nrhs));
+        if (k >= 1) {  // tile row k from column k-1, after the side's older updates of it
+            if (k >= 2) TC_HIP(hipStreamWaitEvent(sm, ev_s[k - 2], 0));
+            TC_HIP(tc::launch_tile_update(sm, V, k, k - 1, false, B + (int64_t)(k - 1) * nb,
+                                          B + (int64_t)k * nb, ldb, nrhs, big));
+        }
+        TC_HIP(tc::launch_trsv_diag(sm, diag_tile(F, k), nb, B + (int64_t)k * nb, ldb, nrhs, false));
+        if (k + 2 < Nt) {  // rows of tiles k+2.. from column k, on the side stream
+            TC_HIP(hipEventRecord(ev_t[k], sm));
+            TC_HIP(hipStreamWaitEvent(ss, ev_t[k], 0));
+            TC_HIP(tc::launch_fwd_update(ss, V, k, 1, Nt - k - 2, B + (int64_t)k * nb,
+                                         B + (int64_t)(k + 2) * nb, ldb, nrhs));
+            TC_HIP(hipEventRecord(ev_s[k], ss));
+        }
     }
     return TC_OK;
 }
@@ -303,21 +333,33 @@ tc_status bwd_enqueue(tc_ctx* ctx, const tc_factor* F, double* B, int64_t ldb, i
                       double* big) {
     const int Nt = F->Nt, nb = F->nb;
     const tc::TileView V = view_of(F);
+    if (tc_status s = solve_events(ctx, Nt)) return s;
+    hipStream_t sm = ctx->stream, ss = ctx->aux[0];
+    hipEvent_t* ev_t = ctx->solve_ev.data();
+    hipEvent_t* ev_s = ev_t + Nt;
+    double* part_side = big + tc::bwd_partial_doubles(nb);
     for (int k = Nt - 1; k >= 0; --k) {
-        if (k + 1 < Nt) {
-            const int64_t rows = (int64_t)(Nt - k - 1) * nb;
-            TC_HIP(tc::launch_bwd_update(ctx->stream, V, k, B + (int64_t)(k + 1) * nb,
-                                         B + (int64_t)k * nb, ldb, nrhs, big, tc::bwd_splits(rows)));
+        if (k + 1 < Nt) {  // tile k+1's contribution, after the side's (tiles k+2..)
+            if (k + 2 < Nt) TC_HIP(hipStreamWaitEvent(sm, ev_s[k], 0));
+            TC_HIP(tc::launch_tile_update(sm, V, k + 1, k, true, B + (int64_t)(k + 1) * nb,
+                                          B + (int64_t)k * nb, ldb, nrhs, big));
         }
-        TC_HIP(tc::launch_trsv_diag(ctx->stream, diag_tile(F, k), nb, B + (int64_t)k * nb, ldb, nrhs,
-                                    true));
+        TC_HIP(tc::launch_trsv_diag(sm, diag_tile(F, k), nb, B + (int64_t)k * nb, ldb, nrhs, true));
+        const int j = k - 2;  // column whose tiles k.. are now final
+        if (j >= 0) {
+            TC_HIP(hipEventRecord(ev_t[k], sm));
+            TC_HIP(hipStreamWaitEvent(ss, ev_t[k], 0));
+            TC_HIP(tc::launch_bwd_update(ss, V, j, 1, Nt - j - 2, B + (int64_t)k * nb,
+                                         B + (int64_t)j * nb, ldb, nrhs, part_side));
+            TC_HIP(hipEventRecord(ev_s[j], ss));
+        }
     }
     return TC_OK;
 }
 
 tc_status solve_enqueue(tc_ctx* ctx, const tc_factor* F, double* B, int64_t ldb, int nrhs,
                         double* big) {
-    if (tc_status s = fwd_enqueue(ctx, F, B, ldb, nrhs)) return s;
+    if (tc_status s = fwd_enqueue(ctx, F, B, ldb, nrhs, big)) return s;
     return bwd_enqueue(ctx, F, B, ldb, nrhs, big);
 }
 
@@ -407,6 +449,7 @@ tc_status tc_ctx_destroy(tc_ctx* ctx) {
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
     for (hipEvent_t e : ctx->gemm_ev) (void)hipEventDestroy(e);
     for (hipEvent_t e : ctx->la_ev) (void)hipEventDestroy(e);
+    for (hipEvent_t e : ctx->solve_ev) (void)hipEventDestroy(e);
     if (ctx->h2d) {
         (void)hipStreamSynchronize(ctx->h2d);
         (void)hipStreamDestroy(ctx->h2d);
@@ -898,7 +941,7 @@ tc_status tc_loglik_seed(tc_ctx* ctx, const tc_factor* F, const double* y, doubl
     double* z = reinterpret_cast<double*>(ctx->ws + Ly.ir);
     double* alpha = z + n;
     TC_HIP(tc::launch_copy_cols(ctx->stream, z, n, y, n, n, 1));
-    if (tc_status s = fwd_enqueue(ctx, F, z, n, 1)) return s;
+    if (tc_status s = fwd_enqueue(ctx, F, z, n, 1, big)) return s;
     TC_HIP(tc::launch_copy_cols(ctx->stream, alpha, n, z, n, n, 1));
     if (tc_status s = bwd_enqueue(ctx, F, alpha, n, 1, big)) return s;
     TC_HIP(tc::launch_loglik_seed(ctx->stream, view_of(F), alpha, z, Lbar, F->Nt, F->nb));

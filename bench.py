@@ -461,6 +461,58 @@ def kl_sweep(tc, si, dev, ns=(32768, 65536), nb=1024, betas=(0.02627, 0.078809, 
     return out
 
 
+def ooc_ablation(tc, si, dev, n=81920, nb=2048, cache_gib=40):
+    """The paper's comparison of out-of-core strategies (Section IV-B) on
+    one MI355X, FP64, the ooc workload's parameters at n=81920, nb=2048, a
+    40 GiB tile cache (holds the working set): the full schedule
+    (asynchronous copies, resident accumulator V1, operand reuse V2,
+    diagonal tile kept through the TRSMs V3), without operand reuse across
+    columns (V1 only), with every copy on the compute stream (no overlap),
+    and both reductions; against the in-core factorization."""
+    import torch
+    w = si.WORKLOADS["ooc"]
+    theta = (w["sigma2"], w["range"], w["nu"], w["nugget"])
+    pts = torch.from_numpy(si.points(n, seed=w["seed"])).to(dev)
+    ctx = tc.Context(n, nb)
+    A, _, _ = tc.matern_tiles(ctx, pts, theta, nb, norms=False)
+    storage = torch.empty_like(A)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    F = tc.factorize(ctx, A, n, nb, storage=storage)
+    torch.cuda.synchronize()
+    t_in = time.perf_counter() - t0
+    F.close()
+    del storage
+    flops = n ** 3 / 3.0
+    out = {"workload": "ooc FP64 tile Cholesky, n=%d nb=%d, Matern nu=%g range=%g nugget=%g, %d GiB cache"
+                       % (n, nb, theta[2], theta[1], theta[3], cache_gib),
+           "in_core_s": t_in, "in_core_tflops": flops / t_in / 1e12, "variants": []}
+    torch._C._host_emptyCache()
+    Abuf = tc.PinnedBuffer(A.numel() * 8)
+    Ah = Abuf.view(torch.float64)
+    cache = torch.empty(cache_gib << 30, dtype=torch.uint8, device=dev)
+    for name, sync, no_reuse in (("async, V1+V2+V3 (default)", False, False),
+                                 ("async, V1 (no operand reuse)", False, True),
+                                 ("sync, V1+V2+V3", True, False),
+                                 ("sync, V1 (no operand reuse)", True, True)):
+        Ah.copy_(A)
+        c2 = tc.Context(n, nb, ooc_sync=sync, ooc_no_reuse=no_reuse)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = tc.factorize_ooc(c2, Ah, n, nb, cache)
+        t = time.perf_counter() - t0
+        c2.close()
+        progress("ooc ablation: %s %.2f s" % (name, t))
+        out["variants"].append({"variant": name, "ooc_s": t, "tflops": flops / t / 1e12,
+                                "ooc_over_in_core": t / t_in, "bytes_h2d": st["bytes_h2d"],
+                                "bytes_d2h": st["bytes_d2h"], "tiles_reloaded": st["tiles_reloaded"],
+                                "h2d_gbps": st["bytes_h2d"] / t / 1e9})
+    del cache, A, Ah
+    torch.cuda.empty_cache()
+    Abuf.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -490,6 +542,8 @@ def main():
                     help="skip the out-of-core mixed-precision leg")
     ap.add_argument("--kl-sweep", action="store_true",
                     help="only the KL-divergence / rate sweep over beta and the target accuracy")
+    ap.add_argument("--ooc-ablation", action="store_true",
+                    help="only the comparison of out-of-core strategies (sync/async, V1/V2/V3)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the tile Cholesky here runs on a single MI355X "
@@ -506,9 +560,12 @@ def main():
         from paper_2410_09819_amd import build
         build.build()
     dev = torch.device("cuda", 0)
-    if args.mxp_only or args.grad_only or args.ooc_only or args.ooc_mixed_only or args.kl_sweep:
+    if (args.mxp_only or args.grad_only or args.ooc_only or args.ooc_mixed_only or args.kl_sweep
+            or args.ooc_ablation):
         if args.kl_sweep:
             res = kl_sweep(tc, si, dev)
+        elif args.ooc_ablation:
+            res = ooc_ablation(tc, si, dev)
         elif args.mxp_only:
             res = mxp_comparison(tc, si, dev, args.mxp_n or None, args.mxp_eps or None,
                                  extra_eps=())

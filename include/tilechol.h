@@ -133,8 +133,29 @@ size_t tc_workspace_bytes(int64_t n, int32_t nb, int32_t nrhs);
  * `workspace_bytes` bytes that the context uses for scratch (split-K
  * partial sums, failure flag, reduction partials); it must stay allocated
  * until tc_ctx_destroy. `compute_stream` is a hipStream_t (NULL: the null
- * stream). `flags` bit 0 times each panel GEMM launch with HIP events
- * (filled into tc_stats). */
+ * stream). `flags` bit 0 (TC_CTX_TIMED) times each panel GEMM launch with
+ * HIP events (filled into tc_stats). Bits 1 and 2 select reduced variants
+ * of tc_factorize_ooc for the paper's comparison of out-of-core strategies
+ * (Section IV-B): TC_CTX_OOC_SYNC issues every host transfer on the compute
+ * stream (no overlap of copies with compute); TC_CTX_OOC_NO_REUSE drops
+ * every cached operand tile after each column (the accumulator still stays
+ * resident, V1, but operands are not reused across columns, no V2).
+ *
+ * Besides the caller's stream the library uses three streams of its own per
+ * device (non-blocking, default priority), created by the first context on
+ * the device, shared by all contexts there and kept until the process ends.
+ * HIP places streams on a small pool of hardware queues (GPU_MAX_HW_QUEUES,
+ * 4 by default) and shares a queue between streams once the pool is used
+ * up; two streams on one queue run in submission order, which serializes
+ * the overlap of copies (and of the lookahead) with compute. A process that
+ * holds more streams than the pool has queues may therefore see slower
+ * out-of-core and lookahead schedules (results unchanged); raising
+ * GPU_MAX_HW_QUEUES avoids it. tc_ctx_destroy waits for the library's
+ * streams on the device. Errors: TC_EINVAL (device out of range),
+ * TC_EHIP (event or stream creation). */
+#define TC_CTX_TIMED 1u
+#define TC_CTX_OOC_SYNC 2u
+#define TC_CTX_OOC_NO_REUSE 4u
 tc_status tc_ctx_create(tc_ctx **ctx, int device, void *workspace, size_t workspace_bytes,
                         void *compute_stream, uint32_t flags);
 tc_status tc_ctx_destroy(tc_ctx *ctx);

@@ -19,14 +19,15 @@ struct tc_ctx {
     uint32_t flags = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     std::vector<hipEvent_t> gemm_ev;
-    // two more compute streams (default priority) for independent class
-    // groups of a mixed-precision column, and the events that order them
+    // the library's per-device streams (device_streams; borrowed, not owned):
+    // two more compute streams for the lookahead and class-group schedules,
+    // and the copy streams; d2h is the same stream as aux[0]
     hipStream_t aux[2] = {nullptr, nullptr};
     hipEvent_t aux_ev[3] = {nullptr, nullptr, nullptr};
     std::vector<hipEvent_t> la_ev;     // lookahead schedule events
     std::vector<hipEvent_t> solve_ev;  // triangular-solve lookahead events
-    // out-of-core resources, created on first use
     hipStream_t h2d = nullptr, d2h = nullptr;
+    // out-of-core staging, created on first use
     void* pinned = nullptr;
     size_t pinned_bytes = 0;
 };
@@ -64,10 +65,13 @@ Layout layout(int64_t n, int nb, int nrhs = 16);
 bool valid_shape(int64_t n, int nb);
 tc_status check_shape(int64_t n, int nb);
 tc_status check_ws(tc_ctx* ctx, int64_t n, int nb);
-// Create the out-of-core streams and a pinned staging buffer of at least
-// `bytes` bytes in the context (once).
+// The library's three streams on `device` (created on first call, shared by
+// all contexts on the device, kept until the process ends).
+tc_status device_streams(int device, hipStream_t out[3]);
+// A pinned staging buffer of at least `bytes` bytes in the context (grown
+// on demand).
 tc_status ctx_ooc_resources(tc_ctx* ctx, size_t bytes);
-// Create the auxiliary compute streams and their events in the context (once).
+// The events that order the auxiliary streams in the context (once).
 tc_status ctx_aux_streams(tc_ctx* ctx);
 // Storage plan of a mixed-precision factor (tiles per class in packed order,
 // then the operand copies, then the device tables); see make_plan.

@@ -104,7 +104,12 @@ extern "C" tc_status tc_factorize_ooc(tc_ctx* ctx, int64_t n, int32_t nb, const 
     if (tc_status s = ctx_ooc_resources(ctx, (size_t)kRing * tab_entries * sizeof(void*))) return s;
     const double** h_ring = reinterpret_cast<const double**>(ctx->pinned);
     char* cbase = static_cast<char*>(cache);
-    hipStream_t cs = ctx->stream, hs = ctx->h2d, ds = ctx->d2h;
+    // reduced variants for the comparison of strategies: all copies on the
+    // compute stream, and/or no reuse of operand tiles across columns
+    const bool sync = (ctx->flags & TC_CTX_OOC_SYNC) != 0;
+    const bool no_reuse = (ctx->flags & TC_CTX_OOC_NO_REUSE) != 0;
+    hipStream_t cs = ctx->stream;
+    hipStream_t hs = sync ? cs : ctx->h2d, ds = sync ? cs : ctx->d2h;
 
     Events E;
     std::vector<int> ring_ev(kRing, -1);
@@ -228,9 +233,13 @@ extern "C" tc_status tc_factorize_ooc(tc_ctx* ctx, int64_t n, int32_t nb, const 
         }
         if (tc_status s = potrf_rec(ctx, W, nb, 0, nb, (int64_t)k * nb, d_info, pot)) return s;
         if (rows > 1) TC_HIP(tc::launch_trsm(cs, W + nb2, W, nb, (int64_t)(rows - 1) * nb, nb));
+        if (no_reuse) {  // every operand tile is loaded again in the next column
+            std::vector<std::pair<int, int>> all(cached.begin(), cached.end());
+            for (const auto& nm : all) release(tc::tile_off(Nt, nm.second, nm.first), nm.first, nm.second);
+        }
         // new off-diagonal tiles into free slots (they are used last in the next column)
         int cached_new = 0;
-        for (int m = k + 1; m < Nt && !free_slots.empty(); ++m) {
+        for (int m = k + 1; m < Nt && !no_reuse && !free_slots.empty(); ++m) {
             const int64_t t = tc::tile_off(Nt, m, k);
             const int s = free_slots.back();
             free_slots.pop_back();

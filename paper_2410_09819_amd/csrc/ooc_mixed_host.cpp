@@ -205,8 +205,10 @@ extern "C" tc_status tc_factorize_ooc_mixed(tc_ctx* ctx, int64_t n, int32_t nb, 
     char* Lh = static_cast<char*>(L_host);
     if (tc_status s = ctx_aux_streams(ctx)) return s;
     // sa: prefetch of A's columns (host -> device), apart from the operand
-    // reloads on hs so that a column of A never queues ahead of them
-    hipStream_t cs = ctx->stream, hs = ctx->h2d, ds = ctx->d2h, sl = ctx->aux[1], sa = ctx->aux[0];
+    // reloads on hs so that a column of A never queues ahead of them; it is
+    // the write-back stream ds (column k + kWork's prefetch waits for the
+    // same event as column k's write-back and follows it)
+    hipStream_t cs = ctx->stream, hs = ctx->h2d, ds = ctx->d2h, sl = ctx->aux[1], sa = ctx->d2h;
 
     std::vector<int> lists, lcount;
     double cflops[5];

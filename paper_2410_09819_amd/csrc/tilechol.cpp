@@ -17,6 +17,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -100,9 +101,33 @@ Layout layout(int64_t n, int nb, int nrhs) {
     return L;
 }
 
+// The library's own streams: three per device, non-blocking, default
+// priority, created once per process and shared by every context on the
+// device. HIP runs streams on a small pool of hardware queues (4 unless
+// GPU_MAX_HW_QUEUES says otherwise) and lets streams share a queue once the
+// pool is used up; work of two streams on one queue runs in submission
+// order, so a copy stream that lands on the caller's queue serializes the
+// copies with the compute. Three streams plus the caller's fit in four
+// queues. Roles: aux[0] and the device-to-host copies share stream 0 (no
+// schedule uses both at once except the mixed out-of-core path, whose
+// prefetch of A follows the write-back of the column it replaces anyway),
+// aux[1] is stream 1, host-to-device copies stream 2.
+constexpr int kMaxDevices = 64;
+std::mutex g_streams_mu;
+hipStream_t g_streams[kMaxDevices][3];
+
+tc_status device_streams(int device, hipStream_t out[3]) {
+    if (device < 0 || device >= kMaxDevices)
+        return fail(TC_EINVAL, "device " + std::to_string(device) + " out of range");
+    std::lock_guard<std::mutex> lock(g_streams_mu);
+    for (int i = 0; i < 3; ++i)
+        if (!g_streams[device][i])
+            TC_HIP(hipStreamCreateWithFlags(&g_streams[device][i], hipStreamNonBlocking));
+    for (int i = 0; i < 3; ++i) out[i] = g_streams[device][i];
+    return TC_OK;
+}
+
 tc_status ctx_ooc_resources(tc_ctx* ctx, size_t bytes) {
-    if (!ctx->h2d) TC_HIP(hipStreamCreateWithFlags(&ctx->h2d, hipStreamNonBlocking));
-    if (!ctx->d2h) TC_HIP(hipStreamCreateWithFlags(&ctx->d2h, hipStreamNonBlocking));
     if (ctx->pinned_bytes < bytes) {
         if (ctx->pinned) {
             TC_HIP(hipDeviceSynchronize());
@@ -117,8 +142,6 @@ tc_status ctx_ooc_resources(tc_ctx* ctx, size_t bytes) {
 }
 
 tc_status ctx_aux_streams(tc_ctx* ctx) {
-    for (int i = 0; i < 2; ++i)
-        if (!ctx->aux[i]) TC_HIP(hipStreamCreateWithFlags(&ctx->aux[i], hipStreamNonBlocking));
     for (int i = 0; i < 3; ++i)
         if (!ctx->aux_ev[i]) TC_HIP(hipEventCreateWithFlags(&ctx->aux_ev[i], hipEventDisableTiming));
     return TC_OK;
@@ -434,9 +457,18 @@ tc_status tc_ctx_create(tc_ctx** out, int device, void* workspace, size_t worksp
     c->ws_bytes = workspace ? workspace_bytes : 0;
     c->flags = flags;
     if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
-        delete c;
+        tc_ctx_destroy(c);
         return fail(TC_EHIP, "hipEventCreate failed");
     }
+    hipStream_t ds[3];
+    if (tc_status s = device_streams(device, ds)) {
+        tc_ctx_destroy(c);
+        return s;
+    }
+    c->aux[0] = ds[0];
+    c->aux[1] = ds[1];
+    c->h2d = ds[2];
+    c->d2h = ds[0];
     *out = c;
     return TC_OK;
 }
@@ -450,20 +482,10 @@ tc_status tc_ctx_destroy(tc_ctx* ctx) {
     for (hipEvent_t e : ctx->gemm_ev) (void)hipEventDestroy(e);
     for (hipEvent_t e : ctx->la_ev) (void)hipEventDestroy(e);
     for (hipEvent_t e : ctx->solve_ev) (void)hipEventDestroy(e);
-    if (ctx->h2d) {
-        (void)hipStreamSynchronize(ctx->h2d);
-        (void)hipStreamDestroy(ctx->h2d);
-    }
-    if (ctx->d2h) {
-        (void)hipStreamSynchronize(ctx->d2h);
-        (void)hipStreamDestroy(ctx->d2h);
-    }
+    // the library's streams are shared, not destroyed: wait for them only
+    for (hipStream_t s : {ctx->aux[0], ctx->aux[1], ctx->h2d, ctx->d2h})
+        if (s) (void)hipStreamSynchronize(s);
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
-    for (int i = 0; i < 2; ++i)
-        if (ctx->aux[i]) {
-            (void)hipStreamSynchronize(ctx->aux[i]);
-            (void)hipStreamDestroy(ctx->aux[i]);
-        }
     for (int i = 0; i < 3; ++i)
         if (ctx->aux_ev[i]) (void)hipEventDestroy(ctx->aux_ev[i]);
     delete ctx;

@@ -101,3 +101,33 @@ def test_ooc_errors(tc, case):
     with pytest.raises(tc.NotPositiveDefinite) as e:
         tc.factorize_ooc(ctx, Bh, n, nb, cache)
     assert e.value.info == 701
+
+
+@pytest.mark.parametrize("sync,no_reuse", [(True, False), (False, True), (True, True)])
+def test_ooc_strategy_variants(tc, case, sync, no_reuse):
+    """The reduced strategies (copies on the compute stream; no operand
+    reuse across columns) run the same kernels in the same order, so the
+    factor is bitwise the default's; without reuse every column reloads its
+    operand tiles."""
+    import torch
+    n, nb, A = case["n"], case["nb"], case["A"]
+    Nt = n // nb
+    ntiles = Nt * (Nt + 1) // 2
+    tbytes = nb * nb * 8
+    cache = torch.empty(400 * tbytes, dtype=torch.uint8, device="cuda")
+    Ah = pinned(tc.pack_lower(A, nb))
+    st0 = tc.factorize_ooc(tc.Context(n, nb), Ah, n, nb, cache)
+    L0 = Ah.numpy().copy()
+    Ah = pinned(tc.pack_lower(A, nb))
+    ctx = tc.Context(n, nb, ooc_sync=sync, ooc_no_reuse=no_reuse)
+    st = tc.factorize_ooc(ctx, Ah, n, nb, cache)
+    assert st["info"] == 0
+    assert np.array_equal(Ah.numpy(), L0)
+    assert st["bytes_d2h"] == st0["bytes_d2h"] == ntiles * tbytes
+    if no_reuse:
+        # operands (m, n), m >= k > n, loaded in every column k
+        loads = sum((Nt - k) * k for k in range(1, Nt))
+        assert st["tiles_reloaded"] == loads
+        assert st["bytes_h2d"] == (ntiles + loads) * tbytes
+    else:
+        assert st["bytes_h2d"] == st0["bytes_h2d"] and st["tiles_reloaded"] == st0["tiles_reloaded"]

@@ -461,14 +461,16 @@ def kl_sweep(tc, si, dev, ns=(32768, 65536), nb=1024, betas=(0.02627, 0.078809, 
     return out
 
 
-def ooc_ablation(tc, si, dev, n=81920, nb=2048, cache_gib=40):
+def ooc_ablation(tc, si, dev, n=81920, nb=2048, cache_gib=40, small_gib=8):
     """The paper's comparison of out-of-core strategies (Section IV-B) on
     one MI355X, FP64, the ooc workload's parameters at n=81920, nb=2048, a
     40 GiB tile cache (holds the working set): the full schedule
     (asynchronous copies, resident accumulator V1, operand reuse V2,
     diagonal tile kept through the TRSMs V3), without operand reuse across
     columns (V1 only), with every copy on the compute stream (no overlap),
-    and both reductions; against the in-core factorization."""
+    and both reductions; against the in-core factorization. Then, with an
+    8 GiB cache (below the ~13 GiB peak working set), next-use eviction
+    against least-recently-used eviction."""
     import torch
     w = si.WORKLOADS["ooc"]
     theta = (w["sigma2"], w["range"], w["nu"], w["nugget"])
@@ -484,30 +486,35 @@ def ooc_ablation(tc, si, dev, n=81920, nb=2048, cache_gib=40):
     F.close()
     del storage
     flops = n ** 3 / 3.0
-    out = {"workload": "ooc FP64 tile Cholesky, n=%d nb=%d, Matern nu=%g range=%g nugget=%g, %d GiB cache"
-                       % (n, nb, theta[2], theta[1], theta[3], cache_gib),
+    out = {"workload": "ooc FP64 tile Cholesky, n=%d nb=%d, Matern nu=%g range=%g nugget=%g"
+                       % (n, nb, theta[2], theta[1], theta[3]),
            "in_core_s": t_in, "in_core_tflops": flops / t_in / 1e12, "variants": []}
     torch._C._host_emptyCache()
     Abuf = tc.PinnedBuffer(A.numel() * 8)
     Ah = Abuf.view(torch.float64)
     cache = torch.empty(cache_gib << 30, dtype=torch.uint8, device=dev)
-    for name, sync, no_reuse in (("async, V1+V2+V3 (default)", False, False),
-                                 ("async, V1 (no operand reuse)", False, True),
-                                 ("sync, V1+V2+V3", True, False),
-                                 ("sync, V1 (no operand reuse)", True, True)):
+    small = cache[:small_gib << 30]
+    for name, sync, no_reuse, lru, cbuf in (
+            ("async, V1+V2+V3 (default)", False, False, False, cache),
+            ("async, V1 (no operand reuse)", False, True, False, cache),
+            ("sync, V1+V2+V3", True, False, False, cache),
+            ("sync, V1 (no operand reuse)", True, True, False, cache),
+            ("%d GiB cache, next-use eviction (default)" % small_gib, False, False, False, small),
+            ("%d GiB cache, LRU eviction" % small_gib, False, False, True, small)):
         Ah.copy_(A)
-        c2 = tc.Context(n, nb, ooc_sync=sync, ooc_no_reuse=no_reuse)
+        c2 = tc.Context(n, nb, ooc_sync=sync, ooc_no_reuse=no_reuse, ooc_lru=lru)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        st = tc.factorize_ooc(c2, Ah, n, nb, cache)
+        st = tc.factorize_ooc(c2, Ah, n, nb, cbuf)
         t = time.perf_counter() - t0
         c2.close()
         progress("ooc ablation: %s %.2f s" % (name, t))
-        out["variants"].append({"variant": name, "ooc_s": t, "tflops": flops / t / 1e12,
+        out["variants"].append({"variant": name, "cache_gib": cbuf.numel() >> 30,
+                                "cache_slots": st["cache_slots"], "ooc_s": t, "tflops": flops / t / 1e12,
                                 "ooc_over_in_core": t / t_in, "bytes_h2d": st["bytes_h2d"],
                                 "bytes_d2h": st["bytes_d2h"], "tiles_reloaded": st["tiles_reloaded"],
-                                "h2d_gbps": st["bytes_h2d"] / t / 1e9})
-    del cache, A, Ah
+                                "evictions": st["evictions"], "h2d_gbps": st["bytes_h2d"] / t / 1e9})
+    del cache, small, A, Ah
     torch.cuda.empty_cache()
     Abuf.close()
     return out

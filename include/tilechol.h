@@ -140,6 +140,9 @@ size_t tc_workspace_bytes(int64_t n, int32_t nb, int32_t nrhs);
  * stream (no overlap of copies with compute); TC_CTX_OOC_NO_REUSE drops
  * every cached operand tile after each column (the accumulator still stays
  * resident, V1, but operands are not reused across columns, no V2).
+ * Bit 3 (TC_CTX_OOC_EVICT_LRU) replaces the next-use eviction of
+ * tc_factorize_ooc by least-recently-used eviction (the paper's "least
+ * utilized" tiles, Section IV-B), for the same comparison.
  *
  * Besides the caller's stream the library uses three streams of its own per
  * device (non-blocking, default priority), created by the first context on
@@ -156,6 +159,7 @@ size_t tc_workspace_bytes(int64_t n, int32_t nb, int32_t nrhs);
 #define TC_CTX_TIMED 1u
 #define TC_CTX_OOC_SYNC 2u
 #define TC_CTX_OOC_NO_REUSE 4u
+#define TC_CTX_OOC_EVICT_LRU 8u
 tc_status tc_ctx_create(tc_ctx **ctx, int device, void *workspace, size_t workspace_bytes,
                         void *compute_stream, uint32_t flags);
 tc_status tc_ctx_destroy(tc_ctx *ctx);

@@ -108,6 +108,7 @@ extern "C" tc_status tc_factorize_ooc(tc_ctx* ctx, int64_t n, int32_t nb, const 
     // compute stream, and/or no reuse of operand tiles across columns
     const bool sync = (ctx->flags & TC_CTX_OOC_SYNC) != 0;
     const bool no_reuse = (ctx->flags & TC_CTX_OOC_NO_REUSE) != 0;
+    const bool lru = (ctx->flags & TC_CTX_OOC_EVICT_LRU) != 0;
     hipStream_t cs = ctx->stream;
     hipStream_t hs = sync ? cs : ctx->h2d, ds = sync ? cs : ctx->d2h;
 
@@ -140,8 +141,25 @@ extern "C" tc_status tc_factorize_ooc(tc_ctx* ctx, int64_t n, int32_t nb, const 
             free_slots.pop_back();
             return TC_OK;
         }
-        auto it = cached.lower_bound({n0, -1});
         std::pair<int, int> victim;
+        if (lru) {
+            // least recently used: tiles not yet read in this column were last
+            // read in column k-1, at the chunk of their tile column n, so the
+            // smallest n >= n1 goes first; then the smallest n read in this
+            // column (never the chunk being loaded)
+            auto later = cached.lower_bound({n1, -1});
+            if (later != cached.end()) victim = *later;
+            else if (cached.begin()->first < n0) victim = *cached.begin();
+            else return fail(TC_ENOMEM, "tile cache cannot hold one chunk of column " + std::to_string(k));
+            const int64_t t = tc::tile_off(Nt, victim.second, victim.first);
+            out = (int)tile_slot[t];
+            tile_slot[t] = -1;
+            slot_tile[out] = -1;
+            cached.erase(victim);
+            st.evictions++;
+            return TC_OK;
+        }
+        auto it = cached.lower_bound({n0, -1});
         if (it != cached.begin()) {
             victim = *std::prev(it);  // used already in this column, largest n
         } else {

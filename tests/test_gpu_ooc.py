@@ -131,3 +131,30 @@ def test_ooc_strategy_variants(tc, case, sync, no_reuse):
         assert st["bytes_h2d"] == (ntiles + loads) * tbytes
     else:
         assert st["bytes_h2d"] == st0["bytes_h2d"] and st["tiles_reloaded"] == st0["tiles_reloaded"]
+
+
+@pytest.mark.parametrize("slots", [32, 40])
+def test_ooc_lru_eviction(tc, case, slots):
+    """Least-recently-used eviction in place of next-use eviction, with a
+    cache smaller than the working set: the same kernels on the same tile
+    values (bitwise the same factor); every operand load is counted once in
+    the transfer volume; on the left-looking schedule's cyclic reads LRU
+    reloads at least as many tiles as next-use eviction."""
+    import torch
+    n, nb, A = case["n"], case["nb"], case["A"]
+    Nt = n // nb
+    ntiles = Nt * (Nt + 1) // 2
+    tbytes = nb * nb * 8
+    cache = torch.empty(slots * tbytes, dtype=torch.uint8, device="cuda")
+    res = {}
+    for lru in (False, True):
+        Ah = pinned(tc.pack_lower(A, nb))
+        st = tc.factorize_ooc(tc.Context(n, nb, ooc_lru=lru), Ah, n, nb, cache)
+        assert st["info"] == 0 and st["evictions"] > 0
+        assert st["bytes_h2d"] == (ntiles + st["tiles_reloaded"]) * tbytes
+        assert st["bytes_d2h"] == ntiles * tbytes
+        res[lru] = (Ah.numpy().copy(), st)
+    print("slots %d: reloads next-use %d, LRU %d" % (slots, res[False][1]["tiles_reloaded"],
+                                                     res[True][1]["tiles_reloaded"]))
+    assert np.array_equal(res[True][0], res[False][0])
+    assert res[True][1]["tiles_reloaded"] >= res[False][1]["tiles_reloaded"]

@@ -302,12 +302,20 @@ def round_tile(t: np.ndarray, c: int) -> tuple[np.ndarray, int]:
 # accumulation is emulated with float32 matrix products per operand tile,
 # summed in float32. The GPU accumulates in a different order, so results
 # agree to within the error bounds, not bitwise.
+#
+# Variant (fp64_update = FP32): the updates into FP64-class tiles, the
+# diagonal tiles' SYRK included, are computed like those of FP32-class tiles
+# (operands rounded to binary32, FP32 accumulation), so binary64 arithmetic
+# remains only in POTRF, TRSM and the refinement residuals; FP64 tiles are
+# still stored in binary64.
 # ---------------------------------------------------------------------------
 
-def mxp_tile_cholesky(A: np.ndarray, nb: int, cmap: np.ndarray):
+def mxp_tile_cholesky(A: np.ndarray, nb: int, cmap: np.ndarray, fp64_update: int = FP64):
     """Mixed-precision left-looking tile Cholesky. Returns (Lh, info): Lh the
     stored factor as binary64 values (each tile exactly representable in
-    its class with its scale), info as in tile_cholesky."""
+    its class with its scale), info as in tile_cholesky. fp64_update: the
+    class whose arithmetic computes the updates into FP64-class tiles and
+    the diagonal SYRK (FP64, or FP32 for the variant above)."""
     from scipy.linalg import solve_triangular
     n = A.shape[0]
     Nt = n // nb
@@ -317,27 +325,28 @@ def mxp_tile_cholesky(A: np.ndarray, nb: int, cmap: np.ndarray):
     def T(M, i, j):
         return M[i * nb:(i + 1) * nb, j * nb:(j + 1) * nb]
 
-    for k in range(Nt):
-        C = T(As, k, k).copy()
+    def update(C, m, k, q):
+        """C - sum_{n<k} Lh_mn Lh_kn^T in class q's arithmetic."""
+        if q == FP64:
+            for n2 in range(k):
+                C -= T(Lh, m, n2) @ T(Lh, k, n2).T
+            return C
+        acc = np.zeros((nb, nb), dtype=np.float32)
         for n2 in range(k):
-            C -= T(Lh, k, n2) @ T(Lh, k, n2).T
+            a, _ = round_tile(T(Lh, m, n2), q)
+            b, _ = round_tile(T(Lh, k, n2), q)
+            acc += (a.astype(np.float32) @ b.astype(np.float32).T).astype(np.float32)
+        return C - acc.astype(np.float64)
+
+    for k in range(Nt):
+        C = update(T(As, k, k).copy(), k, k, fp64_update)
         Lkk, info = tile_cholesky(C, nb)
         if info:
             return Lh, k * nb + info
         T(Lh, k, k)[:] = Lkk
         for m in range(k + 1, Nt):
             p = int(cmap[tile_index(Nt, m, k)])
-            C = T(As, m, k).copy()
-            if p == FP64:
-                for n2 in range(k):
-                    C -= T(Lh, m, n2) @ T(Lh, k, n2).T
-            else:
-                acc = np.zeros((nb, nb), dtype=np.float32)
-                for n2 in range(k):
-                    a, _ = round_tile(T(Lh, m, n2), p)
-                    b, _ = round_tile(T(Lh, k, n2), p)
-                    acc += (a.astype(np.float32) @ b.astype(np.float32).T).astype(np.float32)
-                C -= acc.astype(np.float64)
+            C = update(T(As, m, k).copy(), m, k, fp64_update if p == FP64 else p)
             X = solve_triangular(Lkk, C.T, lower=True).T  # C L_kk^{-T}
             T(Lh, m, k)[:] = round_tile(X, p)[0]
     return Lh, 0

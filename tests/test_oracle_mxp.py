@@ -83,3 +83,48 @@ def test_refinement(mat):
     assert rel.max() <= 1e-9 and 1 <= it <= 10
     Xnp = np.linalg.solve(A, B)
     assert np.linalg.norm(X - Xnp) <= 1e-6 * np.linalg.norm(Xnp)
+
+
+def test_fp32_update_exact_on_integer_factor():
+    """A = L0 L0^T with small integers: every partial sum stays below 2^24,
+    so updates in binary32 arithmetic are exact and the FP32-update variant
+    must return L0 bit for bit (a dropped or transposed term, a wrong sign
+    or tile index would not), for FP64 and FP32 storage alike."""
+    n, nb = 48, 16
+    Nt = n // nb
+    rng = np.random.default_rng(7)
+    L0 = np.tril(rng.integers(-2, 3, size=(n, n)).astype(np.float64), -1)
+    L0 += np.diag(rng.integers(1, 4, size=n).astype(np.float64))
+    A = L0 @ L0.T
+    assert np.abs(A).max() < 2 ** 24
+    for cm in (np.zeros(Nt * (Nt + 1) // 2, dtype=np.uint8),
+               np.array([FP32 if i != j else FP64 for j in range(Nt) for i in range(j, Nt)],
+                        dtype=np.uint8)):
+        Lh, info = oracle.mxp_tile_cholesky(A, nb, cm, fp64_update=FP32)
+        assert info == 0
+        assert np.array_equal(Lh, L0)
+
+
+def test_fp32_update_rounds_like_fp32(mat):
+    """With an all-FP64 map the variant still computes every update in
+    binary32 arithmetic: its backward error is at the FP32 level, far above
+    the FP64 factorization's, and the FP64 variant stays exact-FP64."""
+    A, nb, Nt, _, _ = mat
+    cm = np.zeros(Nt * (Nt + 1) // 2, dtype=np.uint8)
+    L64, _ = oracle.mxp_tile_cholesky(A, nb, cm)
+    L32, info = oracle.mxp_tile_cholesky(A, nb, cm, fp64_update=FP32)
+    assert info == 0
+    be64, be32 = oracle.backward_error(A, L64), oracle.backward_error(A, L32)
+    assert be64 < 1e-14
+    assert 1e-10 < be32 < 64 * 2.0 ** -24, be32
+
+
+def test_fp32_update_refines_to_target(mat):
+    A, nb, Nt, norms, fro = mat
+    n = A.shape[0]
+    B = si.standard_normal((n, 4), seed=31)
+    cm = oracle.precision_map(norms, fro, Nt, 1e-9)
+    Lh, info = oracle.mxp_tile_cholesky(A, nb, cm, fp64_update=FP32)
+    assert info == 0
+    X, it, rel = oracle.refine(A, Lh, B, tol=1e-9)
+    assert rel.max() <= 1e-9 and 1 <= it <= 10

@@ -140,29 +140,39 @@ def mxp_comparison(tc, si, dev, n=None, eps=None, extra_eps=(1e-7, 1e-6)):
     F.close()
     del storage, F
     torch.cuda.empty_cache()
-    # the same refined-solve target (1e-9) reached from looser maps
-    out["looser_maps_same_residual_target"] = []
-    for e2 in extra_eps:
+    def timed(e2, fp64_update, label):
+        """map at e2 + factorization + refined solve to 1e-9, timed"""
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         cm = tc.precision_map(Nt, tf_h, fro, e2)
-        storage = torch.empty(tc.factor_bytes(n, nb, cm) // 8, dtype=torch.float64, device=dev)
-        F = tc.factorize(ctx, A, n, nb, cmap=cm, storage=storage)
+        storage = torch.empty(tc.factor_bytes(n, nb, cm, fp64_update) // 8, dtype=torch.float64,
+                              device=dev)
+        F = tc.factorize(ctx, A, n, nb, cmap=cm, storage=storage, fp64_update=fp64_update)
         B.copy_(B0)
         st = tc.solve_refine(ctx, F, A, B, max_iter=30, tol=1e-9)
         torch.cuda.synchronize()
         t2 = time.perf_counter() - t0
-        progress("mxp comparison: map at %g, refined to 1e-9: %.2f s" % (e2, t2))
+        progress("mxp comparison: %s, refined to 1e-9: %.2f s" % (label, t2))
         cf = list(F.stats.class_flops)
-        out["looser_maps_same_residual_target"].append({
-            "map_eps": e2, "mxp_time_to_solution_s": t2, "mxp_factor_ms": F.stats.ms_total,
-            "speedup_time_to_solution": t_fp64 / t2, "ir_iterations": st["iterations"],
-            "ir_rel_residual": st["rel_residual"], "converged": st["converged"],
-            "class_flop_share": dict(zip(["fp64", "fp32", "fp16", "bf16", "fp8"],
-                                         [c / max(sum(cf), 1.0) for c in cf]))})
+        r = {"map_eps": e2, "mxp_time_to_solution_s": t2, "mxp_factor_ms": F.stats.ms_total,
+             "mxp_tflops_fp64_equivalent": flops / (F.stats.ms_total * 1e-3) / 1e12,
+             "speedup_time_to_solution": t_fp64 / t2, "ir_iterations": st["iterations"],
+             "ir_rel_residual": st["rel_residual"], "converged": st["converged"],
+             "ir_ms": st["ms_total"],
+             "class_flop_share": dict(zip(["fp64", "fp32", "fp16", "bf16", "fp8"],
+                                           [c / max(sum(cf), 1.0) for c in cf]))}
         F.close()
         del storage, F
         torch.cuda.empty_cache()
+        return r
+
+    # the same map with the updates into its FP64 tiles (diagonal SYRK
+    # included) in the FP32 class's arithmetic: binary64 arithmetic only in
+    # POTRF, TRSM and the refinement residuals
+    out["fp32_updates_same_map"] = timed(w["eps"], tc.FP32, "same map, FP32 updates into FP64 tiles")
+    # the same refined-solve target (1e-9) reached from looser maps
+    out["looser_maps_same_residual_target"] = [timed(e2, tc.FP64, "map at %g" % e2)
+                                               for e2 in extra_eps]
     del A
     torch.cuda.empty_cache()
     return out

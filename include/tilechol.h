@@ -69,8 +69,18 @@ typedef struct {
 } tc_matern;
 
 typedef struct {
-    int32_t inplace;   /* 1: the factor overwrites the input tiles (storage == A) */
-    int32_t reserved[7];
+    int32_t inplace;     /* 1: the factor overwrites the input tiles (storage == A) */
+    /* Arithmetic of the GEMM/SYRK updates into FP64-class tiles, the
+     * diagonal tiles' SYRK included: TC_FP64 (0, default; the paper's
+     * four-precision scheme, Section IV-C) or TC_FP32 (the FP32 class's
+     * arithmetic: binary32-rounded operands split into two FP16 terms, FP32
+     * accumulation). With TC_FP32 binary64 arithmetic is left to POTRF,
+     * TRSM, the rounding of new tiles and the refinement residuals; FP64
+     * tiles stay stored in binary64. The factor is then a mixed factor
+     * even for an all-FP64 map, and its storage grows by the FP32 operand
+     * copies of the FP64 tiles (tc_factor_bytes with the same opts). */
+    int32_t fp64_update;
+    int32_t reserved[6];
 } tc_opts;
 
 typedef struct {
@@ -202,13 +212,15 @@ tc_status tc_precision_map(int32_t Nt, const double *tile_fro, double fro_A, dou
  *    FP16 terms (three products; at most 3 * 2^-22 relative error per
  *    product for entries within 2^18 of their tile's largest, before the
  *    FP32 accumulation).
- * storage: device buffer of tc_factor_bytes(n, nb, map) bytes that receives
- *    the factor (tiles, operand copies for the low-precision updates and the
- *    factor's own tables). It must outlive *L.
+ * opts: NULL for the defaults, or see tc_opts. TC_EINVAL for an
+ *    fp64_update other than TC_FP64 or TC_FP32.
+ * storage: device buffer of tc_factor_bytes(n, nb, map, opts) bytes that
+ *    receives the factor (tiles, operand copies for the low-precision
+ *    updates and the factor's own tables). It must outlive *L.
  * L: receives a new factor handle (free with tc_factor_destroy), also when
  *    the return value is positive (the factor is then partial).
  * stats: NULL or filled. */
-size_t tc_factor_bytes(int64_t n, int32_t nb, const uint8_t *map);
+size_t tc_factor_bytes(int64_t n, int32_t nb, const uint8_t *map, const tc_opts *opts);
 tc_status tc_factorize(tc_ctx *ctx, int64_t n, int32_t nb, const double *A, const uint8_t *map,
                        const tc_opts *opts, void *storage, size_t storage_bytes,
                        tc_factor **L, tc_stats *stats);

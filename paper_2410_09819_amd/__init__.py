@@ -42,7 +42,8 @@ class Matern(ctypes.Structure):
 
 
 class Opts(ctypes.Structure):
-    _fields_ = [("inplace", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+    _fields_ = [("inplace", ctypes.c_int32), ("fp64_update", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 6)]
 
 
 class Stats(ctypes.Structure):
@@ -104,7 +105,7 @@ def lib():
         "tc_ctx_destroy": (_i32, [_vp]),
         "tc_matern_tiles": (_i32, [_vp, _i64, _i32, _vp, ctypes.POINTER(Matern), _vp, _vp,
                                    ctypes.POINTER(ctypes.c_double)]),
-        "tc_factor_bytes": (_sz, [_i64, _i32, _vp]),
+        "tc_factor_bytes": (_sz, [_i64, _i32, _vp, ctypes.POINTER(Opts)]),
         "tc_factorize": (_i32, [_vp, _i64, _i32, _vp, _vp, ctypes.POINTER(Opts), _vp, _sz,
                                 ctypes.POINTER(_vp), ctypes.POINTER(Stats)]),
         "tc_solve": (_i32, [_vp, _vp, _vp, _i64, _i32]),
@@ -155,11 +156,14 @@ def workspace_bytes(n: int, nb: int, nrhs: int = 16) -> int:
     return lib().tc_workspace_bytes(n, nb, nrhs)
 
 
-def factor_bytes(n: int, nb: int, cmap=None) -> int:
+def factor_bytes(n: int, nb: int, cmap=None, fp64_update: int = 0) -> int:
+    """Bytes of storage tc_factorize needs for this map (None: all FP64) and
+    the arithmetic of the updates into FP64 tiles (FP64 or FP32)."""
+    opts = Opts(0, fp64_update)
     if cmap is None:
-        return lib().tc_factor_bytes(n, nb, None)
+        return lib().tc_factor_bytes(n, nb, None, ctypes.byref(opts))
     m = np.ascontiguousarray(cmap, dtype=np.uint8)
-    return lib().tc_factor_bytes(n, nb, m.ctypes.data)
+    return lib().tc_factor_bytes(n, nb, m.ctypes.data, ctypes.byref(opts))
 
 
 def precision_map(Nt: int, tile_fro, fro: float, eps: float,
@@ -282,16 +286,19 @@ class Factor:
 
 
 def factorize(ctx: Context, A, n: int, nb: int, cmap=None, inplace: bool = False,
-              storage=None) -> Factor:
+              storage=None, fp64_update: int = 0) -> Factor:
     """Tile Cholesky of the packed lower tiles A (device float64). With
-    inplace=True the factor overwrites A. Raises NotPositiveDefinite."""
+    inplace=True the factor overwrites A. fp64_update=FP32 computes the
+    updates into FP64-class tiles (diagonal SYRK included) in the FP32
+    class's arithmetic. Raises NotPositiveDefinite."""
     import torch
     if inplace:
         storage = A
     elif storage is None:
-        storage = torch.empty(factor_bytes(n, nb, cmap) // 8, dtype=torch.float64, device=A.device)
+        storage = torch.empty(factor_bytes(n, nb, cmap, fp64_update) // 8, dtype=torch.float64,
+                              device=A.device)
     m = None if cmap is None else np.ascontiguousarray(cmap, dtype=np.uint8)
-    opts = Opts(1 if inplace else 0)
+    opts = Opts(1 if inplace else 0, fp64_update)
     st = Stats()
     h = _vp()
     status = lib().tc_factorize(ctx.handle, n, nb, A.data_ptr(), None if m is None else m.ctypes.data,
@@ -300,7 +307,7 @@ def factorize(ctx: Context, A, n: int, nb: int, cmap=None, inplace: bool = False
                                 ctypes.byref(st))
     F = Factor(h, n, nb, storage, st) if h.value else None
     if F is not None:
-        F.mixed = m is not None and bool(np.any(m != FP64))
+        F.mixed = (m is not None and bool(np.any(m != FP64))) or fp64_update != FP64
     if status != 0:
         if F is not None:
             F.close()

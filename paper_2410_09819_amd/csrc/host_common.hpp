@@ -79,15 +79,23 @@ struct Plan {
     int Nt = 0, nb = 0;
     int64_t ntiles = 0;
     std::vector<uint8_t> cls;
+    // class whose arithmetic computes the updates into each tile: cls, or
+    // TC_FP32 for the FP64 tiles when their updates run in FP32
+    std::vector<uint8_t> ccls;
+    bool diag64 = true;  // the diagonal SYRK runs in binary64
     std::vector<int64_t> toff, shoff;  // shoff[t * 4 + c - 1], -1 if absent
     size_t tab_toff = 0, tab_shoff = 0, tab_tscl = 0, tab_tcls = 0, tab_cscl = 0, total = 0;
     bool mixed = false;
 };
 // Fills P for map (NULL: all FP64); false if the map is invalid.
-bool make_plan(int64_t n, int nb, const uint8_t* map, Plan& P);
-// Row lists of a mixed factorization: for column k and class c, the rows
-// r >= 1 (tile k + r) of that class at lists[(k * 5 + c) * Nt + i],
-// i < count[k * 5 + c]; flops per class (diagonal SYRK counted as FP64).
+// fp64_update: arithmetic of the updates into FP64-class tiles, diagonal
+// SYRK included (TC_FP64, or TC_FP32: the split-FP16 FP32 class; the plan
+// is then mixed even for an all-FP64 map).
+bool make_plan(int64_t n, int nb, const uint8_t* map, Plan& P, int fp64_update = 0);
+// Row lists of a mixed factorization: for column k and compute class c, the
+// rows r (tile k + r; r = 0, the diagonal, only in the FP32 list when the
+// diagonal SYRK runs in FP32) at lists[(k * 5 + c) * Nt + i], i < count[k *
+// 5 + c]; flops per compute class.
 void class_lists(const Plan& P, std::vector<int>& lists, std::vector<int>& count,
                  double* cflops, int* ctiles);
 // Read-only device view of a factor's tiles (any precision layout).

@@ -174,13 +174,14 @@ tc_status check_ws(tc_ctx* ctx, int64_t n, int nb) {
 // operand order) with a per-copy power-of-two scale: the class's own bits
 // for FP16, BF16 and FP8, and for FP32 the binary32 value split into two
 // FP16 planes (hi, lo). Then the device tables.
-bool make_plan(int64_t n, int nb, const uint8_t* map, Plan& P) {
+bool make_plan(int64_t n, int nb, const uint8_t* map, Plan& P, int fp64_update) {
+    if (fp64_update != TC_FP64 && fp64_update != TC_FP32) return false;
     P.Nt = (int)(n / nb);
     P.nb = nb;
     const int Nt = P.Nt;
     P.ntiles = (int64_t)Nt * (Nt + 1) / 2;
     P.cls.assign(P.ntiles, TC_FP64);
-    P.mixed = false;
+    P.mixed = fp64_update != TC_FP64;
     if (map) {
         for (int64_t t = 0; t < P.ntiles; ++t) {
             if (map[t] > TC_FP8E4M3) return false;
@@ -190,6 +191,10 @@ bool make_plan(int64_t n, int nb, const uint8_t* map, Plan& P) {
         for (int k = 0; k < Nt; ++k)
             if (P.cls[tc::tile_off(Nt, k, k)] != TC_FP64) return false;
     }
+    P.diag64 = fp64_update == TC_FP64;
+    P.ccls = P.cls;
+    for (auto& c : P.ccls)
+        if (c == TC_FP64) c = (uint8_t)fp64_update;
     const size_t tb = (size_t)nb * nb;
     P.toff.assign(P.ntiles, 0);
     size_t off = 0;
@@ -201,13 +206,13 @@ bool make_plan(int64_t n, int nb, const uint8_t* map, Plan& P) {
         P.total = off;
         return true;
     }
-    auto C = [&](int i, int j) { return (int)P.cls[tc::tile_off(Nt, i, j)]; };
-    // classes present in each row m left of the diagonal and in each column m
-    // below it (as bit masks)
+    auto C = [&](int i, int j) { return (int)P.ccls[tc::tile_off(Nt, i, j)]; };
+    // compute classes present in each row m left of the diagonal and in each
+    // column m on and below it (as bit masks; the diagonal's is the SYRK's)
     P.shoff.assign((size_t)P.ntiles * 4, -1);
     for (int m = 1; m < Nt; ++m) {
         uint32_t colmask = 0;
-        for (int mp = m + 1; mp < Nt; ++mp) colmask |= 1u << C(mp, m);
+        for (int mp = m; mp < Nt; ++mp) colmask |= 1u << C(mp, m);
         // suffix masks of row m: classes of (m, k) for k in (n, m)
         std::vector<uint32_t> suf(m + 1, 0);
         for (int k = m - 1; k >= 0; --k) suf[k] = suf[k + 1] | (1u << C(m, k));
@@ -249,9 +254,15 @@ void class_lists(const Plan& P, std::vector<int>& lists, std::vector<int>& count
     for (int64_t t = 0; t < P.ntiles; ++t) ctiles[P.cls[t]]++;
     for (int k = 0; k < Nt; ++k) {
         const double K = (double)k * P.nb;
-        cflops[TC_FP64] += nb2 * K;  // diagonal SYRK (lower half)
+        // diagonal SYRK (lower half of the flops)
+        if (P.diag64) {
+            cflops[TC_FP64] += nb2 * K;
+        } else {
+            lists[((size_t)k * 5 + TC_FP32) * Nt + count[(size_t)k * 5 + TC_FP32]++] = 0;
+            cflops[TC_FP32] += nb2 * K;
+        }
         for (int r = 1; r < Nt - k; ++r) {
-            const int c = P.cls[tc::tile_off(Nt, k + r, k)];
+            const int c = P.ccls[tc::tile_off(Nt, k + r, k)];
             lists[((size_t)k * 5 + c) * Nt + count[(size_t)k * 5 + c]++] = r;
             cflops[c] += 2.0 * nb2 * K;
         }
@@ -563,10 +574,10 @@ tc_status tc_precision_map(int32_t Nt, const double* tile_fro, double fro_A, dou
     return TC_OK;
 }
 
-size_t tc_factor_bytes(int64_t n, int32_t nb, const uint8_t* map) {
+size_t tc_factor_bytes(int64_t n, int32_t nb, const uint8_t* map, const tc_opts* opts) {
     if (!valid_shape(n, nb)) return 0;
     Plan P;
-    if (!make_plan(n, nb, map, P)) return 0;
+    if (!make_plan(n, nb, map, P, opts ? opts->fp64_update : TC_FP64)) return 0;
     if (!P.mixed) return (size_t)P.ntiles * nb * nb * sizeof(double);
     return P.total;
 }
@@ -775,9 +786,10 @@ tc_status factorize_mixed(tc_ctx* ctx, int64_t n, int nb, const double* A, const
             TC_HIP(hipStreamWaitEvent(sm, ev_blo[k], 0));
         }
         if (k >= 1) {  // tile column k-1 (no split-K: the partials belong to aux[0])
-            TC_HIP(tc::launch_mxp_gemm_f64(sm, Wk, Nt, nb, k, k - 1, k, list(k, TC_FP64),
-                                           count(k, TC_FP64), true, storage, d_toff, d_tcls, d_tscl,
-                                           nullptr, 0));
+            if (P.diag64 || count(k, TC_FP64))
+                TC_HIP(tc::launch_mxp_gemm_f64(sm, Wk, Nt, nb, k, k - 1, k, list(k, TC_FP64),
+                                               count(k, TC_FP64), P.diag64, storage, d_toff, d_tcls,
+                                               d_tscl, nullptr, 0));
             if (tc_status s = low_groups(sm, k, k - 1, k)) return s;
         }
         if (tc_status s = potrf_rec(ctx, Wk, nb, 0, nb, (int64_t)k * nb, d_info, pot)) return s;
@@ -793,9 +805,11 @@ tc_status factorize_mixed(tc_ctx* ctx, int64_t n, int nb, const double* A, const
             TC_HIP(hipMemcpyAsync(Wb[c % 2], A + tc::tile_off(Nt, c, c) * nb2, col_bytes(c),
                                   hipMemcpyDeviceToDevice, s64));
             TC_HIP(hipEventRecord(ev_c[c], s64));
-            TC_HIP(tc::launch_mxp_gemm_f64(s64, Wb[c % 2], Nt, nb, c, 0, c - 1, list(c, TC_FP64),
-                                           count(c, TC_FP64), true, storage, d_toff, d_tcls, d_tscl,
-                                           big, big_cap / sizeof(double)));
+            if (P.diag64 || count(c, TC_FP64))
+                TC_HIP(tc::launch_mxp_gemm_f64(s64, Wb[c % 2], Nt, nb, c, 0, c - 1,
+                                               list(c, TC_FP64), count(c, TC_FP64), P.diag64,
+                                               storage, d_toff, d_tcls, d_tscl, big,
+                                               big_cap / sizeof(double)));
             TC_HIP(hipEventRecord(ev_b64[c], s64));
             TC_HIP(hipStreamWaitEvent(slo, ev_c[c], 0));
             if (tc_status s = low_groups(slo, c, 0, c - 1)) return s;
@@ -842,12 +856,14 @@ tc_status factorize_mixed(tc_ctx* ctx, int64_t n, int nb, const double* A, const
 tc_status tc_factorize(tc_ctx* ctx, int64_t n, int32_t nb, const double* A, const uint8_t* map,
                        const tc_opts* opts, void* storage, size_t storage_bytes, tc_factor** Lout,
                        tc_stats* stats) {
-    (void)opts;
     if (!ctx || !A || !storage || !Lout) return fail(TC_EINVAL, "NULL argument");
     *Lout = nullptr;
     if (tc_status s = check_shape(n, nb)) return s;
+    const int fp64_update = opts ? opts->fp64_update : TC_FP64;
+    if (fp64_update != TC_FP64 && fp64_update != TC_FP32)
+        return fail(TC_EINVAL, "opts->fp64_update must be TC_FP64 or TC_FP32");
     Plan P;
-    if (!make_plan(n, nb, map, P))
+    if (!make_plan(n, nb, map, P, fp64_update))
         return fail(TC_EINVAL, "bad precision map (codes 0..4, diagonal tiles TC_FP64)");
     const size_t need = P.mixed ? P.total : (size_t)P.ntiles * nb * nb * sizeof(double);
     if (storage_bytes < need)

@@ -111,3 +111,20 @@ def test_mixed_factor_bytes_cover_tiles():
     bad = cm.copy()
     bad[0] = tc.FP32  # diagonal tile must stay FP64
     assert tc.factor_bytes(Nt * nb, nb, bad) == 0
+
+
+def test_fp32_update_factor_bytes():
+    """With the updates into FP64 tiles in FP32 arithmetic, every
+    off-diagonal tile (an operand of a later column or of its row's
+    diagonal SYRK) also gets an FP32 operand copy (two FP16 planes), even
+    for an all-FP64 map; other arithmetic codes are rejected."""
+    tc = _lib()
+    Nt, nb = 6, 128
+    ntiles = Nt * (Nt + 1) // 2
+    cm = np.zeros(ntiles, dtype=np.uint8)
+    plain = tc.factor_bytes(Nt * nb, nb, cm)
+    assert plain == ntiles * nb * nb * 8
+    low = tc.factor_bytes(Nt * nb, nb, cm, fp64_update=tc.FP32)
+    assert low >= (ntiles * 8 + (ntiles - Nt) * 4) * nb * nb
+    assert tc.factor_bytes(Nt * nb, nb, None, fp64_update=tc.FP32) == low
+    assert tc.factor_bytes(Nt * nb, nb, cm, fp64_update=tc.FP16) == 0

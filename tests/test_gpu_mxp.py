@@ -128,3 +128,47 @@ def test_fp64_refinement_converges_immediately(tc, case):
     Bd = to_dev(np.ascontiguousarray(si.standard_normal((n, 4), seed=6).T))
     st = tc.solve_refine(ctx, F, Ad, Bd, tol=1e-12)
     assert st["iterations"] <= 1 and st["rel_residual"] <= 1e-12
+
+
+@pytest.mark.parametrize("eps", [1e-6, 1e-9, None])
+def test_fp32_update_matches_oracle(tc, case, eps):
+    """Updates into FP64-class tiles (diagonal SYRK included) in the FP32
+    class's arithmetic: no FP64 GEMM/SYRK flops remain; stored tiles are
+    representable in their classes; the backward error is within 10x of the
+    oracle's emulation of the same variant (the split's per-product error,
+    at most 3 * 2^-22, is within 6x of binary32 product rounding plus one
+    FP32 addition) and well above binary64's, so the option took effect;
+    the factors agree within the perturbation bound; refinement reaches
+    1e-9. eps=None: an all-FP64 map."""
+    n, nb, Nt, A = case["n"], case["nb"], case["Nt"], case["A"]
+    if eps is None:
+        cm = np.zeros(Nt * (Nt + 1) // 2, dtype=np.uint8)
+    else:
+        cm = tc.precision_map(Nt, case["norms"], case["fro"], eps)
+    ctx = tc.Context(n, nb, nrhs=3)
+    Ad = to_dev(tc.pack_lower(A, nb))
+    F = tc.factorize(ctx, Ad, n, nb, cmap=cm, fp64_update=tc.FP32)
+    assert F.stats.info == 0 and F.mixed
+    assert F.stats.class_flops[tc.FP64] == 0
+    # every panel-update flop (SYRK nb^2 K, GEMM 2 nb^2 K per tile) is counted once
+    upd = sum(nb ** 3 * k * (1 + 2 * (Nt - k - 1)) for k in range(Nt))
+    assert sum(F.stats.class_flops) == upd
+    assert list(F.stats.class_tiles) == np.bincount(cm, minlength=5).tolist()
+    Lg = tc.unpack_lower(tc.export(ctx, F).cpu().numpy(), n, nb)
+    for j in range(Nt):
+        for i in range(j + 1, Nt):
+            t = Lg[i * nb:(i + 1) * nb, j * nb:(j + 1) * nb]
+            c = int(cm[oracle.tile_index(Nt, i, j)])
+            assert np.array_equal(oracle.round_tile(t, c)[0], t), (i, j, c)
+    Lo, info = oracle.mxp_tile_cholesky(A, nb, cm, fp64_update=oracle.FP32)
+    assert info == 0
+    be_g, be_o = oracle.backward_error(A, Lg), oracle.backward_error(A, Lo)
+    assert be_g <= 10 * be_o and be_g > 1e-12, (be_g, be_o)
+    diff = np.linalg.norm(Lg - Lo) / np.linalg.norm(Lo)
+    assert diff <= 4 * case["kappa"] * (be_g + be_o) + 1e-13, diff
+    B = si.standard_normal((n, 3), seed=si.rhs_seed(3))
+    Bd = to_dev(np.ascontiguousarray(B.T))
+    st = tc.solve_refine(ctx, F, Ad, Bd, max_iter=30, tol=1e-9)
+    X = Bd.cpu().numpy().T
+    rel = np.linalg.norm(B - A @ X, axis=0) / np.linalg.norm(B, axis=0)
+    assert st["converged"] and rel.max() <= 1e-9, (st, rel.max())

@@ -694,6 +694,10 @@ tc_status factorize_fp64(tc_ctx* ctx, int64_t n, int nb, const double* A, double
 // binary64 working column W, subtract the updates class group by class
 // group, POTRF the diagonal tile and TRSM the rest in FP64, then store the
 // diagonal tile in FP64 and round the others into their classes.
+// Tile columns per bulk group launch of the mixed schedule (16: measured
+// against 8, 32 and whole columns at n = 131072, nb = 1024).
+constexpr int kBulkChunk = 16;
+
 tc_status factorize_mixed(tc_ctx* ctx, int64_t n, int nb, const double* A, const Plan& P,
                           char* storage, tc_factor** Lout, tc_stats* stats) {
     const int Nt = P.Nt;
@@ -805,14 +809,22 @@ tc_status factorize_mixed(tc_ctx* ctx, int64_t n, int nb, const double* A, const
             TC_HIP(hipMemcpyAsync(Wb[c % 2], A + tc::tile_off(Nt, c, c) * nb2, col_bytes(c),
                                   hipMemcpyDeviceToDevice, s64));
             TC_HIP(hipEventRecord(ev_c[c], s64));
-            if (P.diag64 || count(c, TC_FP64))
-                TC_HIP(tc::launch_mxp_gemm_f64(s64, Wb[c % 2], Nt, nb, c, 0, c - 1,
-                                               list(c, TC_FP64), count(c, TC_FP64), P.diag64,
-                                               storage, d_toff, d_tcls, d_tscl, big,
-                                               big_cap / sizeof(double)));
+            // the bulk in launches of at most kBulkChunk tile columns: each
+            // workgroup retires after that many, so the critical path's
+            // kernels on the main stream are not held out of the CUs for a
+            // whole column's K range
+            for (int n0 = 0; n0 < c - 1; n0 += kBulkChunk) {
+                const int n1 = std::min(c - 1, n0 + kBulkChunk);
+                if (P.diag64 || count(c, TC_FP64))
+                    TC_HIP(tc::launch_mxp_gemm_f64(s64, Wb[c % 2], Nt, nb, c, n0, n1,
+                                                   list(c, TC_FP64), count(c, TC_FP64), P.diag64,
+                                                   storage, d_toff, d_tcls, d_tscl, big,
+                                                   big_cap / sizeof(double)));
+            }
             TC_HIP(hipEventRecord(ev_b64[c], s64));
             TC_HIP(hipStreamWaitEvent(slo, ev_c[c], 0));
-            if (tc_status s = low_groups(slo, c, 0, c - 1)) return s;
+            for (int n0 = 0; n0 < c - 1; n0 += kBulkChunk)
+                if (tc_status s = low_groups(slo, c, n0, std::min(c - 1, n0 + kBulkChunk))) return s;
             TC_HIP(hipEventRecord(ev_blo[c], slo));
         }
     }

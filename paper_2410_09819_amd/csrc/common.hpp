@@ -72,6 +72,14 @@ int syrk_sub_splits(int m, int kdim);
 // tiles of a tile column, or a sub-block of one tile when M <= nb).
 // L: w x w lower, column-major with leading dimension nb.
 hipError_t launch_trsm(hipStream_t s, double* C, const double* L, int nb, int64_t M, int w);
+// The same solve for a whole nb x nb factor tile (w = nb) in two launches:
+// inverses of L's 64 x 64 diagonal blocks into dinv (nb * 64 doubles), then
+// one pass in which each workgroup walks its 64 rows' column blocks with
+// MFMA products (the substitution inside a block becomes a product with the
+// block's inverse). M a multiple of 64. Used where binary64 substitution
+// order is not required (the mixed-precision factorizations).
+hipError_t launch_trsm_blockinv(hipStream_t s, double* C, const double* L, int nb, int64_t M,
+                                double* dinv);
 
 // Leaf POTRF of an s x s block (s <= 128) at T (leading dimension ld), in
 // place; on failure sets *info = col0 + j + 1 if *info was 0 (potrf.hip).

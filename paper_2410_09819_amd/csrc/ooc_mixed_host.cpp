@@ -408,7 +408,8 @@ extern "C" tc_status tc_factorize_ooc_mixed(tc_ctx* ctx, int64_t n, int32_t nb, 
             }
         }
         if (tc_status s = potrf_rec(ctx, W, nb, 0, nb, (int64_t)k * nb, d_info, pot)) return s;
-        if (rows > 1) TC_HIP(tc::launch_trsm(cs, W + nb2, W, nb, (int64_t)(rows - 1) * nb, nb));
+        if (rows > 1)
+            TC_HIP(tc::launch_trsm_blockinv(cs, W + nb2, W, nb, (int64_t)(rows - 1) * nb, pot));
         // new tiles: free slots (used again in the next column) or staging
         // half k & 1, free once the column that last used it is written back
         const int h = k & 1;

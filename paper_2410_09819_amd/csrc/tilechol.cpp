@@ -66,7 +66,8 @@ size_t big_bytes(int64_t n, int nb) {
 }
 
 size_t potrf_bytes(int nb) {
-    size_t mx = 256;
+    // also the inverses of a tile's 64 x 64 diagonal blocks (mixed TRSM)
+    size_t mx = std::max<size_t>(256, (size_t)nb * 64 * sizeof(double));
     // in-tile recursion (sizes are multiples of 128 below nb)
     for (int m = 128; m < nb; m += 128) {
         for (int kd = 128; kd < nb; kd += 128) {
@@ -797,7 +798,8 @@ tc_status factorize_mixed(tc_ctx* ctx, int64_t n, int nb, const double* A, const
             if (tc_status s = low_groups(sm, k, k - 1, k)) return s;
         }
         if (tc_status s = potrf_rec(ctx, Wk, nb, 0, nb, (int64_t)k * nb, d_info, pot)) return s;
-        if (k + 1 < Nt) TC_HIP(tc::launch_trsm(sm, Wk + nb2, Wk, nb, (int64_t)(Nt - k - 1) * nb, nb));
+        if (k + 1 < Nt)
+            TC_HIP(tc::launch_trsm_blockinv(sm, Wk + nb2, Wk, nb, (int64_t)(Nt - k - 1) * nb, pot));
         TC_HIP(hipMemcpyAsync(storage + P.toff[tc::tile_off(Nt, k, k)], Wk, nb2 * sizeof(double),
                               hipMemcpyDeviceToDevice, sm));
         TC_HIP(tc::launch_mxp_finalize(sm, Wk, Nt, nb, k, part, storage, d_toff, d_tcls, d_tscl,

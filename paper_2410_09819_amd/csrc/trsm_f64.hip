@@ -162,6 +162,85 @@ __global__ __launch_bounds__(kGemmThreads, 2) void strided_gemm_kernel(
             }
 }
 
+// Inverses of the 64 x 64 diagonal blocks of a lower-triangular tile L
+// (leading dimension nb), for trsm_blockinv_kernel: element (i, j) of
+// block b's inverse goes to Dinv + j * nb + 64 b + i (so block b is a
+// 64 x 64 column-major matrix with leading dimension nb). Thread j of
+// workgroup b solves D x = e_j by forward substitution with IEEE division
+// (x_i = 0 for i < j, so those terms drop out).
+__global__ __launch_bounds__(kCol) void diag_inv_kernel(const double* __restrict__ L, int nb,
+                                                        double* __restrict__ Dinv) {
+    __shared__ double D[kCol * kP];  // D[i * kP + l] = L[64b + i][64b + l]
+    const int b = blockIdx.x, j = threadIdx.x;
+    const double* Lb = L + (int64_t)b * kCol * nb + b * kCol;
+    for (int l = 0; l < kCol; ++l) D[j * kP + l] = Lb[(int64_t)l * nb + j];  // coalesced in j
+    __syncthreads();
+    double x[kCol];
+#pragma unroll
+    for (int i = 0; i < kCol; ++i) {
+        double t = i == j ? 1.0 : 0.0;
+#pragma unroll
+        for (int l = 0; l < i; ++l) t -= D[i * kP + l] * x[l];
+        x[i] = i < j ? 0.0 : t / D[i * kP + i];
+    }
+    double* out = Dinv + (int64_t)j * nb + b * kCol;
+#pragma unroll
+    for (int i = 0; i < kCol; ++i) out[i] = x[i];
+}
+
+// X L^T = C over the whole width w (a multiple of 64) in one launch, with
+// the diagonal blocks' inverses from diag_inv_kernel. Each workgroup owns
+// 64 rows and walks the 64-wide column blocks jb:
+//   R = C_jb - X_[0,jb) L[jb, 0:jb]^T  (MFMA, written over C_jb),
+//   X_jb = R D_jb^{-T}                 (MFMA, written over C_jb).
+// The product with the inverse of each 64 x 64 diagonal block replaces the
+// serial substitution (its error grows with the condition number of that
+// block only).
+__global__ __launch_bounds__(kGemmThreads) void trsm_blockinv_kernel(double* __restrict__ C,
+                                                                     const double* __restrict__ L,
+                                                                     const double* __restrict__ Dinv,
+                                                                     int nb, int w) {
+    using Tl = MfmaTile<kRows, kCol>;
+    __shared__ double lds[Tl::LDS_DOUBLES];
+    const int64_t r0 = (int64_t)blockIdx.x * kRows;
+    const int64_t nb2 = (int64_t)nb * nb;
+    double* Cb = C + (r0 / nb) * nb2 + (r0 % nb);  // row 0 of this block; column c at + c*nb
+    for (int jb = 0; jb < w; jb += kCol) {
+        d4 acc[Tl::MI][Tl::NI];
+#pragma unroll
+        for (int mi = 0; mi < Tl::MI; ++mi)
+#pragma unroll
+            for (int ni = 0; ni < Tl::NI; ++ni) acc[mi][ni] = d4{0.0, 0.0, 0.0, 0.0};
+        mfma_mainloop<kRows, kCol>(acc, ColOp{Cb, nb}, ColOp{L + jb, nb}, nb, 0, jb, lds);
+#pragma unroll
+        for (int mi = 0; mi < Tl::MI; ++mi)
+#pragma unroll
+            for (int ni = 0; ni < Tl::NI; ++ni)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    double* p = Cb + (int64_t)(jb + acc_col<kRows, kCol>(ni, v)) * nb +
+                                acc_row<kRows, kCol>(mi);
+                    *p -= acc[mi][ni][v];
+                    acc[mi][ni][v] = 0.0;
+                }
+        __threadfence_block();
+        __syncthreads();
+        mfma_mainloop<kRows, kCol>(acc, ColOp{Cb + (int64_t)jb * nb, nb}, ColOp{Dinv + jb, nb}, nb, 0,
+                                   kCol, lds);
+        // the main loop ends with a barrier: every read of R is done
+#pragma unroll
+        for (int mi = 0; mi < Tl::MI; ++mi)
+#pragma unroll
+            for (int ni = 0; ni < Tl::NI; ++ni)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    Cb[(int64_t)(jb + acc_col<kRows, kCol>(ni, v)) * nb + acc_row<kRows, kCol>(mi)] =
+                        acc[mi][ni][v];
+        __threadfence_block();
+        __syncthreads();
+    }
+}
+
 hipError_t trsm_rec(hipStream_t s, double* C, const double* L, int nb, int64_t M, int w) {
     if (w <= 128) {
         hipLaunchKernelGGL(trsm_leaf_kernel, dim3((unsigned)(M / kRows)), dim3(kGemmThreads), 0, s,
@@ -185,6 +264,17 @@ hipError_t trsm_rec(hipStream_t s, double* C, const double* L, int nb, int64_t M
 hipError_t launch_trsm(hipStream_t s, double* C, const double* L, int nb, int64_t M, int w) {
     if (M % kGB != 0 || w % kGB != 0) return hipErrorInvalidValue;
     return trsm_rec(s, C, L, nb, M, w);
+}
+
+hipError_t launch_trsm_blockinv(hipStream_t s, double* C, const double* L, int nb, int64_t M,
+                                double* dinv) {
+    if (M % kRows != 0 || nb % kCol != 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(diag_inv_kernel, dim3((unsigned)(nb / kCol)), dim3(kCol), 0, s, L, nb, dinv);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || M == 0) return e;
+    hipLaunchKernelGGL(trsm_blockinv_kernel, dim3((unsigned)(M / kRows)), dim3(kGemmThreads), 0, s,
+                       C, L, dinv, nb, nb);
+    return hipGetLastError();
 }
 
 }  // namespace tc

@@ -370,6 +370,16 @@ def ooc_mixed_leg(tc, si, dev, n=90112, nb=2048, eps=1e-9, caches_gib=(40, 20)):
            for ij in samples}
     F.close()
     del F, storage, L64
+    # the same map with the updates into FP64 tiles in FP32-class arithmetic
+    storage = torch.empty(tc.factor_bytes(n, nb, cm, tc.FP32) // 8, dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    F = tc.factorize(ctx, A, n, nb, cmap=cm, storage=storage, fp64_update=tc.FP32)
+    torch.cuda.synchronize()
+    t_in32 = time.perf_counter() - t0
+    progress("ooc mixed: in-core, FP32-class updates %.2f s" % t_in32)
+    F.close()
+    del F, storage
     torch.cuda.empty_cache()
     flops = n ** 3 / 3.0
     cls_bytes = {c: int(np.sum(cm == c)) * nb2 * IMAGE_BYTES[c] for c in IMAGE_BYTES}
@@ -410,6 +420,21 @@ def ooc_mixed_leg(tc, si, dev, n=90112, nb=2048, eps=1e-9, caches_gib=(40, 20)):
             "h2d_gbps": st["bytes_h2d"] / t_ooc / 1e9, "d2h_gbps": st["bytes_d2h"] / t_ooc / 1e9,
             "tiles_reloaded": st["tiles_reloaded"], "evictions": st["evictions"],
             "chunks": st["chunks"], "max_rel_diff_sampled_tiles_vs_in_core": worst})
+    # FP32-class updates into FP64 tiles, largest cache
+    gib = max(caches_gib)
+    cache = torch.empty(gib << 30, dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, _ = tc.factorize_ooc_mixed(ctx, Ah, n, nb, cm, cache, L_host=img, fp64_update=tc.FP32)
+    t_ooc = time.perf_counter() - t0
+    del cache
+    torch.cuda.empty_cache()
+    progress("ooc mixed: FP32-class updates, %d GiB cache %.2f s" % (gib, t_ooc))
+    out["fp32_updates"] = {
+        "in_core_s": t_in32, "cache_gib": gib, "cache_slots": st["cache_slots"], "ooc_s": t_ooc,
+        "ooc_tflops_fp64_equivalent": flops / t_ooc / 1e12, "ooc_over_in_core": t_ooc / t_in32,
+        "bytes_h2d": st["bytes_h2d"], "bytes_d2h": st["bytes_d2h"],
+        "h2d_gbps": st["bytes_h2d"] / t_ooc / 1e9, "tiles_reloaded": st["tiles_reloaded"]}
     del Ah, img
     Abuf.close()
     Ibuf.close()

@@ -275,9 +275,12 @@ tc_status tc_factorize_ooc(tc_ctx *ctx, int64_t n, int32_t nb, const double *A_h
 size_t tc_ooc_mixed_host_bytes(int64_t n, int32_t nb, const uint8_t *map);
 
 /* Device cache bytes tc_factorize_ooc_mixed needs to hold `slots` tile
- * slots (plus its tables and the staging of new tiles); at least
- * 2 * Nt slots are required. 0 if the shape or the map is invalid. */
-size_t tc_ooc_mixed_cache_bytes(int64_t n, int32_t nb, const uint8_t *map, int64_t slots);
+ * slots (plus its tables and the staging of new tiles) with the same opts
+ * (NULL: defaults; fp64_update = TC_FP32 adds FP32 operand copies of the
+ * FP64 tiles to each slot); at least 2 * Nt slots are required. 0 if the
+ * shape, the map or the opts are invalid. */
+size_t tc_ooc_mixed_cache_bytes(int64_t n, int32_t nb, const uint8_t *map, int64_t slots,
+                                const tc_opts *opts);
 
 /* Out-of-core mixed-precision tile Cholesky (Sections III-C, IV-B, IV-C):
  * the schedule of tc_factorize_ooc with the precision map of tc_factorize,
@@ -293,14 +296,17 @@ size_t tc_ooc_mixed_cache_bytes(int64_t n, int32_t nb, const uint8_t *map, int64
  *    multiplied in, rebuilt on the device when the tile is loaded); at
  *    least 2 * Nt slots, else TC_ENOMEM with the required size in
  *    tc_last_error().
+ * opts: NULL for the defaults; fp64_update as in tc_factorize (the cache
+ *    must then be sized with the same opts). TC_EINVAL for other codes.
  * Updates into a tile of class p are computed as in tc_factorize (same
  * kernels; the summation is split at the chunk boundaries, so results
  * agree with the in-core factor up to rounding). Runs on the compute stream
- * and the two library copy streams, default priority; returns after
- * everything has completed (no tc_factor handle). */
+ * and the library's streams, default priority; returns after everything
+ * has completed (no tc_factor handle). */
 tc_status tc_factorize_ooc_mixed(tc_ctx *ctx, int64_t n, int32_t nb, const double *A_host,
                                  const uint8_t *map, void *L_host, size_t L_host_bytes,
-                                 void *cache, size_t cache_bytes, tc_ooc_stats *stats);
+                                 void *cache, size_t cache_bytes, const tc_opts *opts,
+                                 tc_ooc_stats *stats);
 
 /* Copy the factor into L64 (device, packed lower tiles, binary64; each tile
  * upcast from its class) with the strict upper triangle of every diagonal

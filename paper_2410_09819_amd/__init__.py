@@ -118,9 +118,9 @@ def lib():
         "tc_ooc_mixed_host_bytes": (_sz, [_i64, _i32, _vp]),
         "tc_host_alloc": (_i32, [_sz, ctypes.POINTER(_vp)]),
         "tc_host_free": (_i32, [_vp]),
-        "tc_ooc_mixed_cache_bytes": (_sz, [_i64, _i32, _vp, _i64]),
+        "tc_ooc_mixed_cache_bytes": (_sz, [_i64, _i32, _vp, _i64, ctypes.POINTER(Opts)]),
         "tc_factorize_ooc_mixed": (_i32, [_vp, _i64, _i32, _vp, _vp, _vp, _sz, _vp, _sz,
-                                          ctypes.POINTER(OocStats)]),
+                                          ctypes.POINTER(Opts), ctypes.POINTER(OocStats)]),
         "tc_factor_export": (_i32, [_vp, _vp, _vp]),
         "tc_factor_destroy": (_i32, [_vp]),
         "tc_loglik_seed": (_i32, [_vp, _vp, _vp, _vp, ctypes.POINTER(ctypes.c_double)]),
@@ -394,21 +394,24 @@ def ooc_mixed_host_bytes(n: int, nb: int, cmap) -> int:
     return b
 
 
-def ooc_mixed_cache_bytes(n: int, nb: int, cmap, slots: int) -> int:
+def ooc_mixed_cache_bytes(n: int, nb: int, cmap, slots: int, fp64_update: int = 0) -> int:
     """Device cache bytes of factorize_ooc_mixed with `slots` tile slots."""
     m = np.ascontiguousarray(cmap, dtype=np.uint8)
-    b = lib().tc_ooc_mixed_cache_bytes(n, nb, m.ctypes.data, slots)
+    opts = Opts(0, fp64_update)
+    b = lib().tc_ooc_mixed_cache_bytes(n, nb, m.ctypes.data, slots, ctypes.byref(opts))
     if b == 0:
         raise TileCholError(TC_EINVAL, "invalid shape or precision map")
     return b
 
 
-def factorize_ooc_mixed(ctx: Context, A_host, n: int, nb: int, cmap, cache, L_host=None):
+def factorize_ooc_mixed(ctx: Context, A_host, n: int, nb: int, cmap, cache, L_host=None,
+                        fp64_update: int = 0):
     """Out-of-core mixed-precision factorization: A_host (pinned CPU float64
     tensor, packed lower tiles) streams through the device cache `cache`;
     the factor image (tiles in their classes, then the tile scale exponents)
-    goes to L_host (pinned CPU uint8 tensor, allocated if None). Returns
-    (transfer statistics, L_host). Raises NotPositiveDefinite."""
+    goes to L_host (pinned CPU uint8 tensor, allocated if None). fp64_update
+    as in factorize (size the cache with the same value). Returns (transfer
+    statistics, L_host). Raises NotPositiveDefinite."""
     import torch
     assert A_host.device.type == "cpu" and A_host.is_pinned()
     m = np.ascontiguousarray(cmap, dtype=np.uint8)
@@ -420,7 +423,7 @@ def factorize_ooc_mixed(ctx: Context, A_host, n: int, nb: int, cmap, cache, L_ho
     _check(lib().tc_factorize_ooc_mixed(ctx.handle, n, nb, A_host.data_ptr(), m.ctypes.data,
                                         L_host.data_ptr(), L_host.numel() * L_host.element_size(),
                                         cache.data_ptr(), cache.numel() * cache.element_size(),
-                                        ctypes.byref(st)))
+                                        ctypes.byref(Opts(0, fp64_update)), ctypes.byref(st)))
     return st.as_dict(), L_host
 
 

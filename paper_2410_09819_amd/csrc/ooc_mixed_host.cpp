@@ -134,10 +134,11 @@ extern "C" size_t tc_ooc_mixed_host_bytes(int64_t n, int32_t nb, const uint8_t* 
     return align_up(tiles_end(P)) + align_up((size_t)P.ntiles * sizeof(int32_t));
 }
 
-extern "C" size_t tc_ooc_mixed_cache_bytes(int64_t n, int32_t nb, const uint8_t* map, int64_t slots) {
+extern "C" size_t tc_ooc_mixed_cache_bytes(int64_t n, int32_t nb, const uint8_t* map, int64_t slots,
+                                           const tc_opts* opts) {
     if (!valid_shape(n, nb) || !map || slots < 0) return 0;
     Plan P;
-    if (!make_plan(n, nb, map, P)) return 0;
+    if (!make_plan(n, nb, map, P, opts ? opts->fp64_update : TC_FP64)) return 0;
     const int Nt = P.Nt;
     const Bundle B = bundle_of(P);
     const Tables T = tables_of(P, (size_t)Nt * Nt + 2 * (size_t)Nt);
@@ -149,12 +150,16 @@ extern "C" size_t tc_ooc_mixed_cache_bytes(int64_t n, int32_t nb, const uint8_t*
 
 extern "C" tc_status tc_factorize_ooc_mixed(tc_ctx* ctx, int64_t n, int32_t nb, const double* A_host,
                                             const uint8_t* map, void* L_host, size_t L_host_bytes,
-                                            void* cache, size_t cache_bytes, tc_ooc_stats* stats) {
+                                            void* cache, size_t cache_bytes, const tc_opts* opts,
+                                            tc_ooc_stats* stats) {
     if (!ctx || !A_host || !map || !L_host || !cache) return fail(TC_EINVAL, "NULL argument");
     if (tc_status s = check_shape(n, nb)) return s;
     if (tc_status s = check_ws(ctx, n, nb)) return s;
+    const int fp64_update = opts ? opts->fp64_update : TC_FP64;
+    if (fp64_update != TC_FP64 && fp64_update != TC_FP32)
+        return fail(TC_EINVAL, "opts->fp64_update must be TC_FP64 or TC_FP32");
     Plan P;
-    if (!make_plan(n, nb, map, P)) return fail(TC_EINVAL, "invalid precision map");
+    if (!make_plan(n, nb, map, P, fp64_update)) return fail(TC_EINVAL, "invalid precision map");
     const int Nt = P.Nt;
     const int64_t nb2 = (int64_t)nb * nb;
     const size_t host_tiles = align_up(tiles_end(P));
@@ -387,9 +392,10 @@ extern "C" tc_status tc_factorize_ooc_mixed(tc_ctx* ctx, int64_t n, int32_t nb, 
                                                               cls, cbase, d_shoff, d_cscl));
                     }
                 }
-                TC_HIP(tc::launch_mxp_gemm_f64(cs, W, Nt, nb, k, n0, n1, list(k, TC_FP64),
-                                               count(k, TC_FP64), true, cbase, d_toff, d_tcls, d_tscl,
-                                               big, big_cap / sizeof(double)));
+                if (P.diag64 || count(k, TC_FP64))
+                    TC_HIP(tc::launch_mxp_gemm_f64(cs, W, Nt, nb, k, n0, n1, list(k, TC_FP64),
+                                                   count(k, TC_FP64), P.diag64, cbase, d_toff, d_tcls,
+                                                   d_tscl, big, big_cap / sizeof(double)));
                 if (low) {
                     int ej;
                     if (tc_status r = E.get(ej)) return r;

@@ -80,6 +80,16 @@ hipError_t launch_trsm(hipStream_t s, double* C, const double* L, int nb, int64_
 // order is not required (the mixed-precision factorizations).
 hipError_t launch_trsm_blockinv(hipStream_t s, double* C, const double* L, int nb, int64_t M,
                                 double* dinv);
+// xinv + k nb^2 <- L_kk^{-T} (upper triangular, column-major) for every
+// diagonal tile k of the factor view, in two launches (dinv: Nt * nb * 64
+// doubles of scratch for the inverted 64 x 64 diagonal blocks).
+hipError_t launch_diag_tiles_inv(hipStream_t s, const TileView& V, double* dinv, double* xinv);
+// out = M in for one diagonal tile's inverse Xinv = L_kk^{-T}: M = Xinv^T
+// (= L_kk^{-1}, transpose false) or Xinv (= L_kk^{-T}, transpose true).
+// in and out: nb rows x nrhs, column-major with leading dimension ldb, not
+// overlapping.
+hipError_t launch_tile_inv_apply(hipStream_t s, const double* xinv, int nb, const double* in,
+                                 double* out, int64_t ldb, int nrhs, bool transpose);
 
 // Leaf POTRF of an s x s block (s <= 128) at T (leading dimension ld), in
 // place; on failure sets *info = col0 + j + 1 if *info was 0 (potrf.hip).

@@ -46,6 +46,9 @@ struct tc_factor {
     const uint8_t* d_tcls = nullptr;
     const int* d_tscl = nullptr;
     std::vector<int64_t> toff;
+    // mixed factor: L_kk^{-T} of every diagonal tile (binary64, column-major
+    // nb x nb, in tile order) for the solves
+    const double* d_xinv = nullptr;
 };
 
 namespace tc {
@@ -84,7 +87,8 @@ struct Plan {
     std::vector<uint8_t> ccls;
     bool diag64 = true;  // the diagonal SYRK runs in binary64
     std::vector<int64_t> toff, shoff;  // shoff[t * 4 + c - 1], -1 if absent
-    size_t tab_toff = 0, tab_shoff = 0, tab_tscl = 0, tab_tcls = 0, tab_cscl = 0, total = 0;
+    size_t tab_toff = 0, tab_shoff = 0, tab_tscl = 0, tab_tcls = 0, tab_cscl = 0, tab_xinv = 0,
+           total = 0;
     bool mixed = false;
 };
 // Fills P for map (NULL: all FP64); false if the map is invalid.

@@ -166,6 +166,54 @@ __device__ __forceinline__ void fwd_row(double (&acc)[kNR], const char* tile, in
 // rows of one tile (one per lane); its 4 waves split the nb columns j and
 // combine their partial sums in LDS in a fixed order. Y entries are uniform
 // across a wave.
+// out = M in with the inverse of a diagonal tile (Xinv = L_kk^{-T},
+// column-major): M = Xinv^T (lower; forward solve) or Xinv (upper; backward
+// solve). Workgroup: 64 output rows x 16 right-hand sides; thread (r, q)
+// holds row r0 + r and right-hand sides c0 + 4q .. c0 + 4q + 3. K runs over
+// the 64-wide blocks where M is nonzero (j <= i forward, j >= i backward),
+// each staged in LDS: the M block read along contiguous memory, the input
+// block along its rows.
+constexpr int kIA = 64;
+constexpr int kIR = 16;
+__global__ __launch_bounds__(256) void tile_inv_apply_kernel(const double* __restrict__ Xinv, int nb,
+                                                             const double* __restrict__ in,
+                                                             double* __restrict__ out, int64_t ldb,
+                                                             int nrhs, int transpose) {
+    __shared__ double Ms[kIA * (kIA + 1)];  // Ms[r * 65 + jj] = M[r0 + r][j0 + jj]
+    __shared__ double Is[kIA * kIR];        // Is[jj * 16 + c] = in[j0 + jj][c0 + c]
+    const int tid = threadIdx.x, r = tid & 63, q = tid >> 6;
+    const int r0 = blockIdx.x * kIA, c0 = blockIdx.y * kIR;
+    const int nc = nrhs - c0 < kIR ? nrhs - c0 : kIR;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    const int jbeg = transpose ? r0 : 0, jend = transpose ? nb : r0 + kIA;
+    for (int j0 = jbeg; j0 < jend; j0 += kIA) {
+        for (int e = tid; e < kIA * kIA; e += 256) {
+            if (!transpose) {  // M[i][j] = Xinv[j][i]: row i of M contiguous in j
+                const int rr = e / kIA, jj = e % kIA;
+                Ms[rr * (kIA + 1) + jj] = Xinv[(int64_t)(r0 + rr) * nb + j0 + jj];
+            } else {           // M[i][j] = Xinv[i][j]: column j contiguous in i
+                const int jj = e / kIA, rr = e % kIA;
+                Ms[rr * (kIA + 1) + jj] = Xinv[(int64_t)(j0 + jj) * nb + r0 + rr];
+            }
+        }
+        for (int e = tid; e < kIA * kIR; e += 256) {
+            const int c = e / kIA, jj = e % kIA;
+            Is[jj * kIR + c] = c < nc ? in[(int64_t)(c0 + c) * ldb + j0 + jj] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll 8
+        for (int jj = 0; jj < kIA; ++jj) {
+            const double m = Ms[r * (kIA + 1) + jj];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acc[u] += m * Is[jj * kIR + 4 * q + u];
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+        if (4 * q + u < nc) out[(int64_t)(c0 + 4 * q + u) * ldb + r0 + r] = acc[u];
+}
+
 constexpr int kFwdRows = 64;
 __global__ __launch_bounds__(256) void fwd_update_kernel(TileView L, int k, int t0,
                                                          const double* __restrict__ Y,
@@ -359,6 +407,15 @@ __global__ __launch_bounds__(256) void export_kernel(TileView L, double* __restr
 }
 
 }  // namespace
+
+hipError_t launch_tile_inv_apply(hipStream_t s, const double* xinv, int nb, const double* in,
+                                 double* out, int64_t ldb, int nrhs, bool transpose) {
+    if (nb % kIA != 0 || nrhs <= 0) return hipErrorInvalidValue;
+    dim3 grid((unsigned)(nb / kIA), (unsigned)((nrhs + kIR - 1) / kIR));
+    hipLaunchKernelGGL(tile_inv_apply_kernel, grid, dim3(256), 0, s, xinv, nb, in, out, ldb, nrhs,
+                       transpose ? 1 : 0);
+    return hipGetLastError();
+}
 
 hipError_t launch_trsv_diag(hipStream_t s, const double* Lkk, int nb, double* B, int64_t ldb,
                             int nrhs, bool transpose) {

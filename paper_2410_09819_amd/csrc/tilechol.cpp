@@ -62,6 +62,8 @@ size_t big_bytes(int64_t n, int nb) {
     }
     // backward-solve partials (<= 64 splits), one area per solve stream
     mx = std::max(mx, (size_t)2 * tc::bwd_partial_doubles(nb) * sizeof(double));
+    // inverted 64 x 64 diagonal blocks of every diagonal tile (mixed factor)
+    mx = std::max(mx, (size_t)Nt * nb * 64 * sizeof(double));
     return mx;
 }
 
@@ -97,7 +99,9 @@ Layout layout(int64_t n, int nb, int nrhs) {
     const size_t lists = std::max<size_t>((size_t)5 * Nt * Nt * sizeof(int),
                                           (size_t)64 * ((size_t)Nt * Nt / 4 + Nt) * sizeof(void*));
     L.ir = L.lists + align_up(lists);
-    const size_t ir = (size_t)2 * n * nrhs + tc::residual_partial_doubles((int)Nt, nb, nrhs);
+    // refinement: b, the residual / correction, the solves' intermediate
+    // vector, residual partial sums
+    const size_t ir = (size_t)3 * n * nrhs + tc::residual_partial_doubles((int)Nt, nb, nrhs);
     L.total = L.ir + align_up(ir * sizeof(double));
     return L;
 }
@@ -238,6 +242,8 @@ bool make_plan(int64_t n, int nb, const uint8_t* map, Plan& P, int fp64_update) 
     off += align_up(P.ntiles);
     P.tab_cscl = off;  // scale exponents of the operand copies, [t * 4 + c - 1]
     off += align_up(P.ntiles * 4 * sizeof(int));
+    P.tab_xinv = off;  // inverses of the diagonal tiles (for the solves)
+    off += align_up((size_t)Nt * nb * nb * sizeof(double));
     P.total = off;
     return true;
 }
@@ -336,26 +342,37 @@ tc_status solve_events(tc_ctx* ctx, int Nt) {
 }
 
 // B <- L^{-1} B (forward substitution by tile rows). big: partial sums of
-// the main stream's one-tile updates.
+// the main stream's one-tile updates. With Y (a mixed factor's stored
+// diagonal-tile inverses; Y: n x nrhs with the same leading dimension) the
+// result goes to Y instead: each diagonal step is then Y_k = L_kk^{-1} B_k,
+// a product with the stored inverse, and B keeps the updated right-hand
+// sides.
 tc_status fwd_enqueue(tc_ctx* ctx, const tc_factor* F, double* B, int64_t ldb, int nrhs,
-                      double* big) {
+                      double* big, double* Y) {
     const int Nt = F->Nt, nb = F->nb;
     const tc::TileView V = view_of(F);
     if (tc_status s = solve_events(ctx, Nt)) return s;
     hipStream_t sm = ctx->stream, ss = ctx->aux[0];
     hipEvent_t* ev_t = ctx->solve_ev.data();
     hipEvent_t* ev_s = ev_t + Nt;
+    double* X = Y ? Y : B;  // where the solved tile rows go
+    const int64_t nb2 = (int64_t)nb * nb;
     for (int k = 0; k < Nt; ++k) {
         if (k >= 1) {  // tile row k from column k-1, after the side's older updates of it
             if (k >= 2) TC_HIP(hipStreamWaitEvent(sm, ev_s[k - 2], 0));
-            TC_HIP(tc::launch_tile_update(sm, V, k, k - 1, false, B + (int64_t)(k - 1) * nb,
+            TC_HIP(tc::launch_tile_update(sm, V, k, k - 1, false, X + (int64_t)(k - 1) * nb,
                                           B + (int64_t)k * nb, ldb, nrhs, big));
         }
-        TC_HIP(tc::launch_trsv_diag(sm, diag_tile(F, k), nb, B + (int64_t)k * nb, ldb, nrhs, false));
+        if (Y)
+            TC_HIP(tc::launch_tile_inv_apply(sm, F->d_xinv + k * nb2, nb, B + (int64_t)k * nb,
+                                             Y + (int64_t)k * nb, ldb, nrhs, false));
+        else
+            TC_HIP(tc::launch_trsv_diag(sm, diag_tile(F, k), nb, B + (int64_t)k * nb, ldb, nrhs,
+                                        false));
         if (k + 2 < Nt) {  // rows of tiles k+2.. from column k, on the side stream
             TC_HIP(hipEventRecord(ev_t[k], sm));
             TC_HIP(hipStreamWaitEvent(ss, ev_t[k], 0));
-            TC_HIP(tc::launch_fwd_update(ss, V, k, 1, Nt - k - 2, B + (int64_t)k * nb,
+            TC_HIP(tc::launch_fwd_update(ss, V, k, 1, Nt - k - 2, X + (int64_t)k * nb,
                                          B + (int64_t)(k + 2) * nb, ldb, nrhs));
             TC_HIP(hipEventRecord(ev_s[k], ss));
         }
@@ -363,9 +380,11 @@ tc_status fwd_enqueue(tc_ctx* ctx, const tc_factor* F, double* B, int64_t ldb, i
     return TC_OK;
 }
 
-// B <- L^{-T} B (back substitution by tile rows).
+// B <- L^{-T} B (back substitution by tile rows). With Y: the input is Y
+// (the forward result, updated in place) and each diagonal step writes
+// B_k = L_kk^{-T} Y_k with the stored inverse.
 tc_status bwd_enqueue(tc_ctx* ctx, const tc_factor* F, double* B, int64_t ldb, int nrhs,
-                      double* big) {
+                      double* big, double* Y) {
     const int Nt = F->Nt, nb = F->nb;
     const tc::TileView V = view_of(F);
     if (tc_status s = solve_events(ctx, Nt)) return s;
@@ -373,29 +392,40 @@ tc_status bwd_enqueue(tc_ctx* ctx, const tc_factor* F, double* B, int64_t ldb, i
     hipEvent_t* ev_t = ctx->solve_ev.data();
     hipEvent_t* ev_s = ev_t + Nt;
     double* part_side = big + tc::bwd_partial_doubles(nb);
+    double* R = Y ? Y : B;  // the right-hand sides being reduced
+    const int64_t nb2 = (int64_t)nb * nb;
     for (int k = Nt - 1; k >= 0; --k) {
         if (k + 1 < Nt) {  // tile k+1's contribution, after the side's (tiles k+2..)
             if (k + 2 < Nt) TC_HIP(hipStreamWaitEvent(sm, ev_s[k], 0));
             TC_HIP(tc::launch_tile_update(sm, V, k + 1, k, true, B + (int64_t)(k + 1) * nb,
-                                          B + (int64_t)k * nb, ldb, nrhs, big));
+                                          R + (int64_t)k * nb, ldb, nrhs, big));
         }
-        TC_HIP(tc::launch_trsv_diag(sm, diag_tile(F, k), nb, B + (int64_t)k * nb, ldb, nrhs, true));
+        if (Y)
+            TC_HIP(tc::launch_tile_inv_apply(sm, F->d_xinv + k * nb2, nb, Y + (int64_t)k * nb,
+                                             B + (int64_t)k * nb, ldb, nrhs, true));
+        else
+            TC_HIP(tc::launch_trsv_diag(sm, diag_tile(F, k), nb, B + (int64_t)k * nb, ldb, nrhs,
+                                        true));
         const int j = k - 2;  // column whose tiles k.. are now final
         if (j >= 0) {
             TC_HIP(hipEventRecord(ev_t[k], sm));
             TC_HIP(hipStreamWaitEvent(ss, ev_t[k], 0));
             TC_HIP(tc::launch_bwd_update(ss, V, j, 1, Nt - j - 2, B + (int64_t)k * nb,
-                                         B + (int64_t)j * nb, ldb, nrhs, part_side));
+                                         R + (int64_t)j * nb, ldb, nrhs, part_side));
             TC_HIP(hipEventRecord(ev_s[j], ss));
         }
     }
     return TC_OK;
 }
 
+// Y: n x nrhs scratch with leading dimension ldb for the inverse-based
+// diagonal steps, used when the factor stores its diagonal-tile inverses
+// (else NULL: substitution with the diagonal tiles in place).
 tc_status solve_enqueue(tc_ctx* ctx, const tc_factor* F, double* B, int64_t ldb, int nrhs,
-                        double* big) {
-    if (tc_status s = fwd_enqueue(ctx, F, B, ldb, nrhs, big)) return s;
-    return bwd_enqueue(ctx, F, B, ldb, nrhs, big);
+                        double* big, double* Y) {
+    if (!F->d_xinv) Y = nullptr;
+    if (tc_status s = fwd_enqueue(ctx, F, B, ldb, nrhs, big, Y)) return s;
+    return bwd_enqueue(ctx, F, B, ldb, nrhs, big, Y);
 }
 
 // Column norms of X (n x nrhs): ||x_j||_2 into out[j] (synchronizes).
@@ -830,6 +860,12 @@ tc_status factorize_mixed(tc_ctx* ctx, int64_t n, int nb, const double* A, const
             TC_HIP(hipEventRecord(ev_blo[c], slo));
         }
     }
+    // L_kk^{-T} of every diagonal tile for the solves (the bulk streams have
+    // been joined by the last column, so `big` is free for the inverted
+    // 64 x 64 blocks)
+    double* xinv = reinterpret_cast<double*>(storage + P.tab_xinv);
+    const tc::TileView V{storage, d_toff, d_tcls, d_tscl, Nt, nb};
+    TC_HIP(tc::launch_diag_tiles_inv(sm, V, big, xinv));
     TC_HIP(hipEventRecord(ctx->ev1, ctx->stream));
     int info = 0;
     TC_HIP(hipMemcpyAsync(&info, d_info, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
@@ -842,6 +878,7 @@ tc_status factorize_mixed(tc_ctx* ctx, int64_t n, int nb, const double* A, const
     f->Nt = Nt;
     f->info = info;
     f->mixed = true;
+    f->d_xinv = xinv;
     f->storage = storage;
     f->d_toff = d_toff;
     f->d_tcls = d_tcls;
@@ -902,7 +939,9 @@ tc_status tc_solve(tc_ctx* ctx, const tc_factor* F, double* B, int64_t ldb, int3
     DeviceGuard g(ctx->device);
     const Layout Ly = layout(F->n, F->nb);
     double* big = reinterpret_cast<double*>(ctx->ws + Ly.big);
-    if (tc_status s = solve_enqueue(ctx, F, B, ldb, nrhs, big)) return s;
+    // the refinement area holds an n x 16 intermediate vector
+    double* Y = (ldb == F->n && nrhs <= 16) ? reinterpret_cast<double*>(ctx->ws + Ly.ir) : nullptr;
+    if (tc_status s = solve_enqueue(ctx, F, B, ldb, nrhs, big, Y)) return s;
     TC_HIP(hipStreamSynchronize(ctx->stream));
     return TC_OK;
 }
@@ -923,12 +962,13 @@ tc_status tc_solve_refine(tc_ctx* ctx, const tc_factor* F, const double* A, doub
     double* part = reinterpret_cast<double*>(ctx->ws + Ly.small);
     double* Bc = reinterpret_cast<double*>(ctx->ws + Ly.ir);  // b
     double* R = Bc + (size_t)n * nrhs;                          // residual / correction
-    double* rp = R + (size_t)n * nrhs;                          // residual partial sums
+    double* Y = R + (size_t)n * nrhs;                           // the solves' intermediate
+    double* rp = Y + (size_t)n * nrhs;                          // residual partial sums
     TC_HIP(hipEventRecord(ctx->ev0, ctx->stream));
     TC_HIP(tc::launch_copy_cols(ctx->stream, Bc, n, B, ldb, n, nrhs));
     std::vector<double> bn, rn;
     if (tc_status s = colnorms(ctx, Bc, n, n, nrhs, part, bn)) return s;
-    if (tc_status s = solve_enqueue(ctx, F, B, ldb, nrhs, big)) return s;
+    if (tc_status s = solve_enqueue(ctx, F, B, ldb, nrhs, big, ldb == n ? Y : nullptr)) return s;
     tc_ir_stats st;
     std::memset(&st, 0, sizeof(st));
     double rel = 0.0;
@@ -943,7 +983,7 @@ tc_status tc_solve_refine(tc_ctx* ctx, const tc_factor* F, const double* A, doub
         }
         if (it < 32) st.history[it] = rel;
         if (rel <= tol || it >= max_iter) break;
-        if (tc_status s = solve_enqueue(ctx, F, R, n, nrhs, big)) return s;
+        if (tc_status s = solve_enqueue(ctx, F, R, n, nrhs, big, Y)) return s;
         TC_HIP(tc::launch_axpy(ctx->stream, B, ldb, R, n, n, nrhs));
         ++it;
     }
@@ -993,9 +1033,9 @@ tc_status tc_loglik_seed(tc_ctx* ctx, const tc_factor* F, const double* y, doubl
     double* z = reinterpret_cast<double*>(ctx->ws + Ly.ir);
     double* alpha = z + n;
     TC_HIP(tc::launch_copy_cols(ctx->stream, z, n, y, n, n, 1));
-    if (tc_status s = fwd_enqueue(ctx, F, z, n, 1, big)) return s;
+    if (tc_status s = fwd_enqueue(ctx, F, z, n, 1, big, nullptr)) return s;
     TC_HIP(tc::launch_copy_cols(ctx->stream, alpha, n, z, n, n, 1));
-    if (tc_status s = bwd_enqueue(ctx, F, alpha, n, 1, big)) return s;
+    if (tc_status s = bwd_enqueue(ctx, F, alpha, n, 1, big, nullptr)) return s;
     TC_HIP(tc::launch_loglik_seed(ctx->stream, view_of(F), alpha, z, Lbar, F->Nt, F->nb));
     std::vector<double> zn;
     if (tc_status s = colnorms(ctx, z, n, n, 1, part, zn)) return s;

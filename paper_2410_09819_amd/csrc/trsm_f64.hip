@@ -196,15 +196,17 @@ __global__ __launch_bounds__(kCol) void diag_inv_kernel(const double* __restrict
 // The product with the inverse of each 64 x 64 diagonal block replaces the
 // serial substitution (its error grows with the condition number of that
 // block only).
-__global__ __launch_bounds__(kGemmThreads) void trsm_blockinv_kernel(double* __restrict__ C,
-                                                                     const double* __restrict__ L,
-                                                                     const double* __restrict__ Dinv,
-                                                                     int nb, int w) {
+// X L^T = C for the 64 rows of C at Cb (tile-strided rows, column c at
+// + c * nb), walking the 64-wide column blocks jb of the width w:
+//   R = C_jb - X_[0,jb) L[jb, 0:jb]^T  (MFMA, written over C_jb),
+//   X_jb = R D_jb^{-T}                 (MFMA, written over C_jb),
+// with D_jb^{-1} from diag_inv_kernel at Dinv + jb (leading dimension nb).
+// The product with the inverse of each 64 x 64 diagonal block replaces the
+// serial substitution (its error grows with the condition number of that
+// block only).
+__device__ __forceinline__ void blockinv_rows(double* Cb, const double* L, const double* Dinv,
+                                              int nb, int w, double* lds) {
     using Tl = MfmaTile<kRows, kCol>;
-    __shared__ double lds[Tl::LDS_DOUBLES];
-    const int64_t r0 = (int64_t)blockIdx.x * kRows;
-    const int64_t nb2 = (int64_t)nb * nb;
-    double* Cb = C + (r0 / nb) * nb2 + (r0 % nb);  // row 0 of this block; column c at + c*nb
     for (int jb = 0; jb < w; jb += kCol) {
         d4 acc[Tl::MI][Tl::NI];
 #pragma unroll
@@ -241,6 +243,65 @@ __global__ __launch_bounds__(kGemmThreads) void trsm_blockinv_kernel(double* __r
     }
 }
 
+// X L^T = C over the whole width w (a multiple of 64) in one launch; each
+// workgroup owns 64 rows of C.
+__global__ __launch_bounds__(kGemmThreads) void trsm_blockinv_kernel(double* __restrict__ C,
+                                                                     const double* __restrict__ L,
+                                                                     const double* __restrict__ Dinv,
+                                                                     int nb, int w) {
+    __shared__ double lds[MfmaTile<kRows, kCol>::LDS_DOUBLES];
+    const int64_t r0 = (int64_t)blockIdx.x * kRows;
+    double* Cb = C + (r0 / nb) * ((int64_t)nb * nb) + (r0 % nb);
+    blockinv_rows(Cb, L, Dinv, nb, w, lds);
+}
+
+// The diagonal tiles of a factor (binary64 in every precision layout).
+__device__ __forceinline__ const double* diag_of(const TileView& V, int k) {
+    const int64_t t = tile_off(V.Nt, k, k);
+    const int64_t nb2 = (int64_t)V.nb * V.nb;
+    return reinterpret_cast<const double*>(V.base + (V.toff ? V.toff[t] : t * nb2 * 8));
+}
+
+// diag_inv_kernel for every diagonal tile k = blockIdx.y of a factor, into
+// Dinv + k * nb * 64.
+__global__ __launch_bounds__(kCol) void diag_tiles_inv_kernel(TileView V, double* __restrict__ Dinv) {
+    __shared__ double D[kCol * kP];
+    const int b = blockIdx.x, j = threadIdx.x, k = blockIdx.y, nb = V.nb;
+    const double* Lb = diag_of(V, k) + (int64_t)b * kCol * nb + b * kCol;
+    for (int l = 0; l < kCol; ++l) D[j * kP + l] = Lb[(int64_t)l * nb + j];
+    __syncthreads();
+    double x[kCol];
+#pragma unroll
+    for (int i = 0; i < kCol; ++i) {
+        double t = i == j ? 1.0 : 0.0;
+#pragma unroll
+        for (int l = 0; l < i; ++l) t -= D[i * kP + l] * x[l];
+        x[i] = i < j ? 0.0 : t / D[i * kP + i];
+    }
+    double* out = Dinv + (int64_t)k * nb * kCol + (int64_t)j * nb + b * kCol;
+#pragma unroll
+    for (int i = 0; i < kCol; ++i) out[i] = x[i];
+}
+
+// Xinv_k = L_kk^{-T} (solution of X L_kk^T = I; upper triangular,
+// column-major nb x nb at Xinv + k * nb^2) for every diagonal tile k =
+// blockIdx.y; workgroup blockIdx.x owns 64 rows.
+__global__ __launch_bounds__(kGemmThreads) void tiles_inv_kernel(TileView V,
+                                                                 const double* __restrict__ Dinv,
+                                                                 double* __restrict__ Xinv) {
+    __shared__ double lds[MfmaTile<kRows, kCol>::LDS_DOUBLES];
+    const int k = blockIdx.y, nb = V.nb;
+    const int64_t r0 = (int64_t)blockIdx.x * kRows;
+    double* Cb = Xinv + (int64_t)k * nb * nb + r0;
+    for (int e = threadIdx.x; e < kRows * nb; e += kGemmThreads) {  // identity rows r0 ..
+        const int c = e / kRows, r = e % kRows;
+        Cb[(int64_t)c * nb + r] = (r0 + r == c) ? 1.0 : 0.0;
+    }
+    __threadfence_block();
+    __syncthreads();
+    blockinv_rows(Cb, diag_of(V, k), Dinv + (int64_t)k * nb * kCol, nb, nb, lds);
+}
+
 hipError_t trsm_rec(hipStream_t s, double* C, const double* L, int nb, int64_t M, int w) {
     if (w <= 128) {
         hipLaunchKernelGGL(trsm_leaf_kernel, dim3((unsigned)(M / kRows)), dim3(kGemmThreads), 0, s,
@@ -264,6 +325,17 @@ hipError_t trsm_rec(hipStream_t s, double* C, const double* L, int nb, int64_t M
 hipError_t launch_trsm(hipStream_t s, double* C, const double* L, int nb, int64_t M, int w) {
     if (M % kGB != 0 || w % kGB != 0) return hipErrorInvalidValue;
     return trsm_rec(s, C, L, nb, M, w);
+}
+
+hipError_t launch_diag_tiles_inv(hipStream_t s, const TileView& V, double* dinv, double* xinv) {
+    if (V.nb % kCol != 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(diag_tiles_inv_kernel, dim3((unsigned)(V.nb / kCol), (unsigned)V.Nt), dim3(kCol), 0,
+                       s, V, dinv);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(tiles_inv_kernel, dim3((unsigned)(V.nb / kRows), (unsigned)V.Nt),
+                       dim3(kGemmThreads), 0, s, V, dinv, xinv);
+    return hipGetLastError();
 }
 
 hipError_t launch_trsm_blockinv(hipStream_t s, double* C, const double* L, int nb, int64_t M,

@@ -216,7 +216,8 @@ tc_status tc_precision_map(int32_t Nt, const double *tile_fro, double fro_A, dou
  *    fp64_update other than TC_FP64 or TC_FP32.
  * storage: device buffer of tc_factor_bytes(n, nb, map, opts) bytes that
  *    receives the factor (tiles, operand copies for the low-precision
- *    updates and the factor's own tables). It must outlive *L.
+ *    updates, the factor's own tables and, for a mixed factor, L_kk^{-T} of
+ *    every diagonal tile for the solves). It must outlive *L.
  * L: receives a new factor handle (free with tc_factor_destroy), also when
  *    the return value is positive (the factor is then partial).
  * stats: NULL or filled. */

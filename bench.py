@@ -448,9 +448,10 @@ def kl_sweep(tc, si, dev, ns=(32768, 65536), nb=1024, betas=(0.02627, 0.078809, 
     accuracies of its figures, the KL divergence of Eq. 3 at y = 0,
     D = l_0 - l_a = (log|Sigma_a| - log|Sigma_0|) / 2, with Sigma_0 factored
     in FP64 and Sigma_a in mixed precision, and the factorization rates
-    (FP64-equivalent TFLOP/s, n^3/3 over the factorization time). A nugget
-    of 1e-4 is added on the diagonal (the map is computed from the tile
-    norms of the same matrix)."""
+    (FP64-equivalent TFLOP/s, n^3/3 over the factorization time), for the
+    updates into FP64 tiles in binary64 and in FP32-class arithmetic. A
+    nugget of 1e-4 is added on the diagonal (the map is computed from the
+    tile norms of the same matrix)."""
     import numpy as np
     import torch
     out = {"workload": "Matern nu=1/2 sigma2=1 nugget=%g, nb=%d, Z-ordered seeded points (seed %d)" % (nugget, nb, seed),
@@ -489,8 +490,25 @@ def kl_sweep(tc, si, dev, ns=(32768, 65536), nb=1024, betas=(0.02627, 0.078809, 
                     row.update({"kl": None, "breakdown_column": e.info})
                 del storage
                 torch.cuda.empty_cache()
+                # the same map with FP32-class updates into its FP64 tiles
+                storage = torch.empty(tc.factor_bytes(n, nb, cm, tc.FP32) // 8, dtype=torch.float64,
+                                      device=dev)
+                try:
+                    F = tc.factorize(ctx, A, n, nb, cmap=cm, storage=storage, fp64_update=tc.FP32)
+                    ld = tc.logdet(ctx, F)
+                    ms = F.stats.ms_total
+                    row.update({"kl_fp32_updates": 0.5 * (ld - ld0), "fp32_updates_factor_ms": ms,
+                                "fp32_updates_tflops_fp64_equivalent": n ** 3 / 3.0 / ms / 1e9,
+                                "fp32_updates_speedup_factor": ms0 / ms})
+                    F.close()
+                    del F
+                except tc.NotPositiveDefinite as e:
+                    row.update({"kl_fp32_updates": None, "fp32_updates_breakdown_column": e.info})
+                del storage
+                torch.cuda.empty_cache()
                 out["rows"].append(row)
-                progress("kl sweep: n=%d beta=%g eps=%g kl=%s" % (n, beta, eps, row.get("kl")))
+                progress("kl sweep: n=%d beta=%g eps=%g kl=%s kl(FP32 updates)=%s" % (
+                    n, beta, eps, row.get("kl"), row.get("kl_fp32_updates")))
             del A, tf
             torch.cuda.empty_cache()
     return out

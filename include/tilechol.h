@@ -78,7 +78,9 @@ typedef struct {
      * TRSM, the rounding of new tiles and the refinement residuals; FP64
      * tiles stay stored in binary64. The factor is then a mixed factor
      * even for an all-FP64 map, and its storage grows by the FP32 operand
-     * copies of the FP64 tiles (tc_factor_bytes with the same opts). */
+     * copies of the FP64 tiles (tc_factor_bytes with the same opts).
+     * Refined solves reach binary64 accuracy with such a factor; its
+     * log-determinant carries the FP32-class error of the updates. */
     int32_t fp64_update;
     int32_t reserved[6];
 } tc_opts;

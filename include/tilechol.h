@@ -229,7 +229,10 @@ tc_status tc_factorize(tc_ctx *ctx, int64_t n, int32_t nb, const double *A, cons
                        tc_factor **L, tc_stats *stats);
 
 /* Solve Sigma X = B with the factor: B <- L^{-T} L^{-1} B (tiles used as
- * stored, upcast to binary64).
+ * stored, upcast to binary64). For a mixed factor with ldb == n and
+ * nrhs <= 16 the diagonal steps multiply by the stored L_kk^{-1} and
+ * L_kk^{-T} (through an intermediate vector in the workspace); otherwise
+ * they substitute with the diagonal tiles.
  * B: device, n x nrhs binary64, column-major with leading dimension ldb >= n
  *    (may be NULL when nrhs == 0, which does nothing). */
 tc_status tc_solve(tc_ctx *ctx, const tc_factor *L, double *B, int64_t ldb, int32_t nrhs);

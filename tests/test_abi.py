@@ -107,7 +107,8 @@ def test_mixed_factor_bytes_cover_tiles():
     Nt, nb = 6, 128
     cm = np.zeros(Nt * (Nt + 1) // 2, dtype=np.uint8)
     cm[[1, 2, 3]] = [tc.FP32, tc.FP16, tc.FP8E4M3]
-    assert tc.factor_bytes(Nt * nb, nb, cm) > (18 * 8 + 4 + 2 + 1) * nb * nb
+    # tiles in their classes, and L_kk^{-T} of the Nt diagonal tiles for the solves
+    assert tc.factor_bytes(Nt * nb, nb, cm) > (18 * 8 + 4 + 2 + 1 + Nt * 8) * nb * nb
     bad = cm.copy()
     bad[0] = tc.FP32  # diagonal tile must stay FP64
     assert tc.factor_bytes(Nt * nb, nb, bad) == 0

@@ -141,6 +141,8 @@ extern "C" tc_status tc_factorize_ooc(tc_ctx* ctx, int64_t n, int32_t nb, const 
             free_slots.pop_back();
             return TC_OK;
         }
+        if (cached.empty())
+            return fail(TC_ENOMEM, "tile cache cannot hold one chunk of column " + std::to_string(k));
         std::pair<int, int> victim;
         if (lru) {
             // least recently used: tiles not yet read in this column were last

@@ -162,10 +162,6 @@ __device__ __forceinline__ void fwd_row(double (&acc)[kNR], const char* tile, in
     }
 }
 
-// B_below[r][c] -= sum_j L[k+1+r/nb, k][r%nb][j] Y[j][c]. A workgroup owns 64
-// rows of one tile (one per lane); its 4 waves split the nb columns j and
-// combine their partial sums in LDS in a fixed order. Y entries are uniform
-// across a wave.
 // out = M in with the inverse of a diagonal tile (Xinv = L_kk^{-T},
 // column-major): M = Xinv^T (lower; forward solve) or Xinv (upper; backward
 // solve). Workgroup: 64 output rows x 16 right-hand sides; thread (r, q)
@@ -214,6 +210,10 @@ __global__ __launch_bounds__(256) void tile_inv_apply_kernel(const double* __res
         if (4 * q + u < nc) out[(int64_t)(c0 + 4 * q + u) * ldb + r0 + r] = acc[u];
 }
 
+// B_below[r][c] -= sum_j L[k+1+r/nb, k][r%nb][j] Y[j][c]. A workgroup owns 64
+// rows of one tile (one per lane); its 4 waves split the nb columns j and
+// combine their partial sums in LDS in a fixed order. Y entries are uniform
+// across a wave.
 constexpr int kFwdRows = 64;
 __global__ __launch_bounds__(256) void fwd_update_kernel(TileView L, int k, int t0,
                                                          const double* __restrict__ Y,

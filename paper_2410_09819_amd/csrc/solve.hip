@@ -138,30 +138,6 @@ __device__ __forceinline__ double ld_cls(const char* base, int64_t i) {
     return dec_fp8(reinterpret_cast<const uint8_t*>(base)[i]);
 }
 
-// acc[c] += sum_{j in [jbeg, jend)} L[row][j] Y[j][c] for one row of a tile
-// stored in class C (unscaled values; the caller applies the tile's scale).
-template <int C>
-__device__ __forceinline__ void fwd_row(double (&acc)[kNR], const char* tile, int nb, int row,
-                                        int jbeg, int jend, const double* Yc, int64_t ldb, int nr) {
-    for (int j = jbeg; j < jend; j += 8) {
-        double lv[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) lv[u] = ld_cls<C>(tile, (int64_t)(j + u) * nb + row);
-        if (nr == kNR) {
-#pragma unroll
-            for (int u = 0; u < 8; ++u)
-#pragma unroll
-                for (int c = 0; c < kNR; ++c) acc[c] += lv[u] * Yc[(int64_t)c * ldb + j + u];
-        } else {
-#pragma unroll
-            for (int u = 0; u < 8; ++u)
-#pragma unroll
-                for (int c = 0; c < kNR; ++c)
-                    if (c < nr) acc[c] += lv[u] * Yc[(int64_t)c * ldb + j + u];
-        }
-    }
-}
-
 // out = M in with the inverse of a diagonal tile (Xinv = L_kk^{-T},
 // column-major): M = Xinv^T (lower; forward solve) or Xinv (upper; backward
 // solve). Workgroup: 64 output rows x 16 right-hand sides; thread (r, q)
@@ -210,54 +186,88 @@ __global__ __launch_bounds__(256) void tile_inv_apply_kernel(const double* __res
         if (4 * q + u < nc) out[(int64_t)(c0 + 4 * q + u) * ldb + r0 + r] = acc[u];
 }
 
+// One 64 x 64 block of a tile stored in class C (unscaled values) and the
+// matching 64 x 16 block of right-hand sides into registers: thread t takes
+// L elements (row t % 64 + 64-row offset, column j0 + t / 64 + 4u), read
+// along contiguous rows, and right-hand-side elements (row t % 64, column
+// t / 64 + 4u). The caller stores them to LDS a block later.
+template <int C>
+__device__ __forceinline__ void fetch_block(const char* tile, int nb, int64_t col0, int row0,
+                                            const double* X, int64_t ldb, int64_t xrow0, int c0,
+                                            int nr, double (&lr)[16], double (&xr)[4]) {
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        const int e = tid + 256 * u;
+        lr[u] = ld_cls<C>(tile, (col0 + e / 64) * nb + row0 + e % 64);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int e = tid + 256 * u, c = e / 64;
+        xr[u] = c < nr ? X[(int64_t)(c0 + c) * ldb + xrow0 + e % 64] : 0.0;
+    }
+}
+__device__ __forceinline__ void fetch_block_cls(int cls, const char* tile, int nb, int64_t col0,
+                                                int row0, const double* X, int64_t ldb,
+                                                int64_t xrow0, int c0, int nr, double (&lr)[16],
+                                                double (&xr)[4]) {
+    switch (cls) {
+        case kFP64: fetch_block<kFP64>(tile, nb, col0, row0, X, ldb, xrow0, c0, nr, lr, xr); break;
+        case kFP32: fetch_block<kFP32>(tile, nb, col0, row0, X, ldb, xrow0, c0, nr, lr, xr); break;
+        case kFP16: fetch_block<kFP16>(tile, nb, col0, row0, X, ldb, xrow0, c0, nr, lr, xr); break;
+        case kBF16: fetch_block<kBF16>(tile, nb, col0, row0, X, ldb, xrow0, c0, nr, lr, xr); break;
+        default: fetch_block<kFP8>(tile, nb, col0, row0, X, ldb, xrow0, c0, nr, lr, xr); break;
+    }
+}
+
 // B_below[r][c] -= sum_j L[k+1+r/nb, k][r%nb][j] Y[j][c]. A workgroup owns 64
-// rows of one tile (one per lane); its 4 waves split the nb columns j and
-// combine their partial sums in LDS in a fixed order. Y entries are uniform
-// across a wave.
+// rows of one tile and 16 right-hand sides; thread (r, q) holds row r0 + r
+// and right-hand sides c0 + 4q .. c0 + 4q + 3. The tile's 64 x 64 blocks
+// along j and the matching Y rows pass through LDS (the sum over j runs in
+// a fixed order); the next block is loaded into registers while the
+// current one is multiplied.
 constexpr int kFwdRows = 64;
 __global__ __launch_bounds__(256) void fwd_update_kernel(TileView L, int k, int t0,
                                                          const double* __restrict__ Y,
                                                          double* __restrict__ Bb, int64_t ldb,
                                                          int nrhs) {
-    __shared__ double red[4 * kFwdRows * kNR];
+    __shared__ double Ls[64 * 65];  // Ls[j * 65 + r] = L[r0 + r][j0 + j] (unscaled)
+    __shared__ double Ys[64 * kNR];  // Ys[j * 16 + c] = Y[j0 + j][c0 + c]
     const int nb = L.nb;
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int tid = threadIdx.x, r = tid & 63, q = tid >> 6;
     const int c0 = blockIdx.y * kNR;
     const int nr = nrhs - c0 < kNR ? nrhs - c0 : kNR;
     const int64_t r0 = (int64_t)blockIdx.x * kFwdRows;
     int cls, scale;
     const char* tile = view_tile(L, k + 1 + t0 + (int)(r0 / nb), k, cls, scale);
-    const int row = (int)(r0 % nb) + lane;
-    const double* Yc = Y + (int64_t)c0 * ldb;
-    double acc[kNR];
+    const int rr0 = (int)(r0 % nb);
+    double lr[16], yr[4], acc[4] = {0.0, 0.0, 0.0, 0.0};
+    fetch_block_cls(cls, tile, nb, 0, rr0, Y, ldb, 0, c0, nr, lr, yr);
+    for (int j0 = 0; j0 < nb; j0 += 64) {
+        __syncthreads();
 #pragma unroll
-    for (int c = 0; c < kNR; ++c) acc[c] = 0.0;
-    const int jq = nb / 4;
-    const int jbeg = wave * jq, jend = jbeg + jq;
-    switch (cls) {
-        case kFP64: fwd_row<kFP64>(acc, tile, nb, row, jbeg, jend, Yc, ldb, nr); break;
-        case kFP32: fwd_row<kFP32>(acc, tile, nb, row, jbeg, jend, Yc, ldb, nr); break;
-        case kFP16: fwd_row<kFP16>(acc, tile, nb, row, jbeg, jend, Yc, ldb, nr); break;
-        case kBF16: fwd_row<kBF16>(acc, tile, nb, row, jbeg, jend, Yc, ldb, nr); break;
-        default: fwd_row<kFP8>(acc, tile, nb, row, jbeg, jend, Yc, ldb, nr); break;
-    }
-    if (scale) {
+        for (int u = 0; u < 16; ++u) {
+            const int e = tid + 256 * u;
+            Ls[(e / 64) * 65 + e % 64] = lr[u];
+        }
 #pragma unroll
-        for (int c = 0; c < kNR; ++c) acc[c] = ldexp(acc[c], scale);
-    }
+        for (int u = 0; u < 4; ++u) {
+            const int e = tid + 256 * u;
+            Ys[(e % 64) * kNR + e / 64] = yr[u];
+        }
+        __syncthreads();
+        if (j0 + 64 < nb) fetch_block_cls(cls, tile, nb, j0 + 64, rr0, Y, ldb, j0 + 64, c0, nr, lr, yr);
+#pragma unroll 8
+        for (int jj = 0; jj < 64; ++jj) {
+            const double l = Ls[jj * 65 + r];
 #pragma unroll
-    for (int c = 0; c < kNR; ++c) red[(wave * kFwdRows + lane) * kNR + c] = acc[c];
-    __syncthreads();
-    for (int e = tid; e < kFwdRows * kNR; e += 256) {
-        const int rr = e % kFwdRows, c = e / kFwdRows;
-        if (c < nr) {
-            const double s = (red[(0 * kFwdRows + rr) * kNR + c] + red[(1 * kFwdRows + rr) * kNR + c]) +
-                             (red[(2 * kFwdRows + rr) * kNR + c] + red[(3 * kFwdRows + rr) * kNR + c]);
-            Bb[(int64_t)(c0 + c) * ldb + r0 + rr] -= s;
+            for (int u = 0; u < 4; ++u) acc[u] += l * Ys[jj * kNR + 4 * q + u];
         }
     }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+        if (4 * q + u < nr)
+            Bb[(int64_t)(c0 + 4 * q + u) * ldb + r0 + r] -= scale ? ldexp(acc[u], scale) : acc[u];
 }
 
 // partial[split][j][c] = sum over the split's rows r of L[k+1+r/nb, k][r%nb][j]
@@ -278,20 +288,41 @@ __global__ __launch_bounds__(256) void bwd_partial_kernel(TileView L, int k, int
     const int jj = tid & 63, cg = tid >> 6;  // column of the strip, group of 4 RHS
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     const int64_t rbeg = (int64_t)split * rows_per_split;
-    for (int64_t rb = rbeg; rb < rbeg + rows_per_split; rb += kBwdSub) {
-        __syncthreads();
-        int cls, scale;
+    const int64_t rend = rbeg + rows_per_split;
+    // the L block (64 rows of the panel x the 64 strip columns) and the 64
+    // X rows of each sub-block pass through LDS; the next sub-block is loaded
+    // into registers while the current one is multiplied. The tile's class
+    // is looked up once per sub-block and its power-of-two scale applied to
+    // the loaded values (the sub-blocks of a split may span several tiles).
+    double lr[16], xr[4];
+    int scale = 0;
+    auto fetch = [&](int64_t rb) {
+        int cls;
         const char* tile = view_tile(L, k + 1 + t0 + (int)(rb / nb), k, cls, scale);
-        const int rr = (int)(rb % nb);
-        for (int e = tid; e < kBwdStrip * kBwdSub; e += 256) {
-            const int j = e / kBwdSub, r = e % kBwdSub;
-            Ls[j * (kBwdSub + 1) + r] = load_elem(tile, (int64_t)(j0 + j) * nb + rr + r, cls, scale);
+        // block element (row rr + r, column j0 + j) at column-major offset
+        // (j0 + j) * nb + rr + r: fetch_block's (col0 + e / 64, row0 + e % 64)
+        fetch_block_cls(cls, tile, nb, j0, (int)(rb % nb), X, ldb, rb, rhs0, nr, lr, xr);
+        if (scale) {
+#pragma unroll
+            for (int u = 0; u < 16; ++u) lr[u] = ldexp(lr[u], scale);
         }
-        for (int e = tid; e < kBwdSub * kNR; e += 256) {
-            const int c = e / kBwdSub, r = e % kBwdSub;
-            Xs[r * kNR + c] = (c < nr) ? X[(int64_t)(rhs0 + c) * ldb + rb + r] : 0.0;
+    };
+    if (rbeg < rend) fetch(rbeg);
+    for (int64_t rb = rbeg; rb < rend; rb += kBwdSub) {
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int e = tid + 256 * u;
+            Ls[(e / kBwdSub) * (kBwdSub + 1) + e % kBwdSub] = lr[u];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = tid + 256 * u;
+            Xs[(e % kBwdSub) * kNR + e / kBwdSub] = xr[u];
         }
         __syncthreads();
+        if (rb + kBwdSub < rend) fetch(rb + kBwdSub);
+#pragma unroll 8
         for (int r = 0; r < kBwdSub; ++r) {
             const double lv = Ls[jj * (kBwdSub + 1) + r];
 #pragma unroll

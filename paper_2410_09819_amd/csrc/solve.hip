@@ -158,28 +158,44 @@ __global__ __launch_bounds__(256) void tile_inv_apply_kernel(const double* __res
     const int nc = nrhs - c0 < kIR ? nrhs - c0 : kIR;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     const int jbeg = transpose ? r0 : 0, jend = transpose ? nb : r0 + kIA;
-    for (int j0 = jbeg; j0 < jend; j0 += kIA) {
-        for (int e = tid; e < kIA * kIA; e += 256) {
-            if (!transpose) {  // M[i][j] = Xinv[j][i]: row i of M contiguous in j
-                const int rr = e / kIA, jj = e % kIA;
-                Ms[rr * (kIA + 1) + jj] = Xinv[(int64_t)(r0 + rr) * nb + j0 + jj];
-            } else {           // M[i][j] = Xinv[i][j]: column j contiguous in i
-                const int jj = e / kIA, rr = e % kIA;
-                Ms[rr * (kIA + 1) + jj] = Xinv[(int64_t)(j0 + jj) * nb + r0 + rr];
-            }
+    // the next block is loaded into registers while the current one is
+    // multiplied out of LDS
+    double mr[16], ir[4];
+    auto fetch = [&](int j0) {
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int e = tid + 256 * u;
+            mr[u] = transpose ? Xinv[(int64_t)(j0 + e / kIA) * nb + r0 + e % kIA]   // M[i][j] = Xinv[i][j]
+                              : Xinv[(int64_t)(r0 + e / kIA) * nb + j0 + e % kIA];  // M[i][j] = Xinv[j][i]
         }
-        for (int e = tid; e < kIA * kIR; e += 256) {
-            const int c = e / kIA, jj = e % kIA;
-            Is[jj * kIR + c] = c < nc ? in[(int64_t)(c0 + c) * ldb + j0 + jj] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = tid + 256 * u, c = e / kIA;
+            ir[u] = c < nc ? in[(int64_t)(c0 + c) * ldb + j0 + e % kIA] : 0.0;
+        }
+    };
+    fetch(jbeg);
+    for (int j0 = jbeg; j0 < jend; j0 += kIA) {
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int e = tid + 256 * u, a = e / kIA, b = e % kIA;
+            if (transpose) Ms[b * (kIA + 1) + a] = mr[u];  // row r0 + b, column j0 + a
+            else Ms[a * (kIA + 1) + b] = mr[u];            // row r0 + a, column j0 + b
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = tid + 256 * u;
+            Is[(e % kIA) * kIR + e / kIA] = ir[u];
         }
         __syncthreads();
+        if (j0 + kIA < jend) fetch(j0 + kIA);
 #pragma unroll 8
         for (int jj = 0; jj < kIA; ++jj) {
             const double m = Ms[r * (kIA + 1) + jj];
 #pragma unroll
             for (int u = 0; u < 4; ++u) acc[u] += m * Is[jj * kIR + 4 * q + u];
         }
-        __syncthreads();
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u)

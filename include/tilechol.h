@@ -50,7 +50,7 @@ typedef int32_t tc_status;
 #define TC_ENOMEM (-2)        /* workspace or budget too small */
 #define TC_EHIP (-3)          /* a HIP runtime call failed */
 #define TC_ENOTCONV (-4)      /* refinement did not reach the tolerance */
-#define TC_EUNSUPPORTED (-5)  /* valid request this build does not implement */
+#define TC_EUNSUPPORTED (-5)  /* valid request the library does not implement */
 
 /* Storage classes of a tile (Section IV-C: one precision per tile). */
 typedef enum { TC_FP64 = 0, TC_FP32 = 1, TC_FP16 = 2, TC_BF16 = 3, TC_FP8E4M3 = 4 } tc_prec;

@@ -87,9 +87,11 @@ hipError_t launch_diag_tiles_inv(hipStream_t s, const TileView& V, double* dinv,
 // out = M in for one diagonal tile's inverse Xinv = L_kk^{-T}: M = Xinv^T
 // (= L_kk^{-1}, transpose false) or Xinv (= L_kk^{-T}, transpose true).
 // in and out: nb rows x nrhs, column-major with leading dimension ldb, not
-// overlapping.
+// overlapping. Split over the nonzero 64 x 64 blocks of M like
+// launch_tile_update (partial: the same workspace).
 hipError_t launch_tile_inv_apply(hipStream_t s, const double* xinv, int nb, const double* in,
-                                 double* out, int64_t ldb, int nrhs, bool transpose);
+                                 double* out, int64_t ldb, int nrhs, bool transpose,
+                                 double* partial);
 
 // Leaf POTRF of an s x s block (s <= 128) at T (leading dimension ld), in
 // place; on failure sets *info = col0 + j + 1 if *info was 0 (potrf.hip).

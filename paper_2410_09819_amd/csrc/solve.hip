@@ -138,70 +138,6 @@ __device__ __forceinline__ double ld_cls(const char* base, int64_t i) {
     return dec_fp8(reinterpret_cast<const uint8_t*>(base)[i]);
 }
 
-// out = M in with the inverse of a diagonal tile (Xinv = L_kk^{-T},
-// column-major): M = Xinv^T (lower; forward solve) or Xinv (upper; backward
-// solve). Workgroup: 64 output rows x 16 right-hand sides; thread (r, q)
-// holds row r0 + r and right-hand sides c0 + 4q .. c0 + 4q + 3. K runs over
-// the 64-wide blocks where M is nonzero (j <= i forward, j >= i backward),
-// each staged in LDS: the M block read along contiguous memory, the input
-// block along its rows.
-constexpr int kIA = 64;
-constexpr int kIR = 16;
-__global__ __launch_bounds__(256) void tile_inv_apply_kernel(const double* __restrict__ Xinv, int nb,
-                                                             const double* __restrict__ in,
-                                                             double* __restrict__ out, int64_t ldb,
-                                                             int nrhs, int transpose) {
-    __shared__ double Ms[kIA * (kIA + 1)];  // Ms[r * 65 + jj] = M[r0 + r][j0 + jj]
-    __shared__ double Is[kIA * kIR];        // Is[jj * 16 + c] = in[j0 + jj][c0 + c]
-    const int tid = threadIdx.x, r = tid & 63, q = tid >> 6;
-    const int r0 = blockIdx.x * kIA, c0 = blockIdx.y * kIR;
-    const int nc = nrhs - c0 < kIR ? nrhs - c0 : kIR;
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    const int jbeg = transpose ? r0 : 0, jend = transpose ? nb : r0 + kIA;
-    // the next block is loaded into registers while the current one is
-    // multiplied out of LDS
-    double mr[16], ir[4];
-    auto fetch = [&](int j0) {
-#pragma unroll
-        for (int u = 0; u < 16; ++u) {
-            const int e = tid + 256 * u;
-            mr[u] = transpose ? Xinv[(int64_t)(j0 + e / kIA) * nb + r0 + e % kIA]   // M[i][j] = Xinv[i][j]
-                              : Xinv[(int64_t)(r0 + e / kIA) * nb + j0 + e % kIA];  // M[i][j] = Xinv[j][i]
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int e = tid + 256 * u, c = e / kIA;
-            ir[u] = c < nc ? in[(int64_t)(c0 + c) * ldb + j0 + e % kIA] : 0.0;
-        }
-    };
-    fetch(jbeg);
-    for (int j0 = jbeg; j0 < jend; j0 += kIA) {
-        __syncthreads();
-#pragma unroll
-        for (int u = 0; u < 16; ++u) {
-            const int e = tid + 256 * u, a = e / kIA, b = e % kIA;
-            if (transpose) Ms[b * (kIA + 1) + a] = mr[u];  // row r0 + b, column j0 + a
-            else Ms[a * (kIA + 1) + b] = mr[u];            // row r0 + a, column j0 + b
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int e = tid + 256 * u;
-            Is[(e % kIA) * kIR + e / kIA] = ir[u];
-        }
-        __syncthreads();
-        if (j0 + kIA < jend) fetch(j0 + kIA);
-#pragma unroll 8
-        for (int jj = 0; jj < kIA; ++jj) {
-            const double m = Ms[r * (kIA + 1) + jj];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) acc[u] += m * Is[jj * kIR + 4 * q + u];
-        }
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-        if (4 * q + u < nc) out[(int64_t)(c0 + 4 * q + u) * ldb + r0 + r] = acc[u];
-}
-
 // One 64 x 64 block of a tile stored in class C (unscaled values) and the
 // matching 64 x 16 block of right-hand sides into registers: thread t takes
 // L elements (row t % 64 + 64-row offset, column j0 + t / 64 + 4u), read
@@ -366,11 +302,17 @@ __global__ void bwd_reduce_kernel(double* __restrict__ Y, int nb, int64_t ldb, i
 // ... any tile of a factor view) or T^T (backward), X = nb rows of B.
 // Workgroup (i, s) takes output rows 64 i .. 64 i + 63 and the 64 inner
 // indices 64 s .. 64 s + 63: the 64 x 64 block of op(T) (decoded from its
-// class) and the X rows go through LDS, each thread forms 4 (row, rhs)
-// sums, and writes its partial to part[s][row][rhs]; tile_update_reduce
-// subtracts the nb / 64 partials in a fixed order.
+// class, all 16 loads of a thread issued together) and the X rows go
+// through LDS, each thread forms 4 (row, rhs) sums, and writes its partial
+// to part[s][row][rhs]; tile_update_reduce adds up the nb / 64 partials in
+// a fixed order. With dense != NULL, T is that binary64 nb x nb matrix
+// (column-major) instead of a factor tile, and tri names the blocks of
+// op(T) known to be zero (1: op(T) lower triangular, 2: upper); their
+// workgroups write zero partials without reading T.
 constexpr int kTU = 64;
-__global__ __launch_bounds__(256) void tile_update_kernel(TileView L, int ti, int tj, int transpose,
+__global__ __launch_bounds__(256) void tile_update_kernel(TileView L, int ti, int tj,
+                                                          const double* __restrict__ dense, int tri,
+                                                          int transpose,
                                                           const double* __restrict__ X, int64_t ldb,
                                                           int nrhs, int rhs0,
                                                           double* __restrict__ part) {
@@ -380,36 +322,53 @@ __global__ __launch_bounds__(256) void tile_update_kernel(TileView L, int ti, in
     const int tid = threadIdx.x;
     const int r0 = blockIdx.x * kTU, q0 = blockIdx.y * kTU;
     const int nr = nrhs - rhs0 < kNR ? nrhs - rhs0 : kNR;
-    int cls, scale;
-    const char* tile = view_tile(L, ti, tj, cls, scale);
-    for (int e = tid; e < kTU * kTU; e += 256) {
-        // consecutive threads read consecutive elements of a stored column
-        const int a = e % kTU, b = e / kTU;
-        if (!transpose) {  // T[r0 + a][q0 + b]: column q0 + b, row r0 + a
-            Ts[b * (kTU + 1) + a] = load_elem(tile, (int64_t)(q0 + b) * nb + r0 + a, cls, scale);
-        } else {  // T^T[r0 + b][q0 + a] = T[q0 + a][r0 + b]: column r0 + b, row q0 + a
-            Ts[a * (kTU + 1) + b] = load_elem(tile, (int64_t)(r0 + b) * nb + q0 + a, cls, scale);
-        }
+    const int r = tid & 63, cg = tid >> 6;  // row, group of 4 right-hand sides
+    double* p = part + ((int64_t)blockIdx.y * nb + r0 + r) * kNR + cg * 4;
+    if ((tri == 1 && q0 > r0) || (tri == 2 && q0 < r0)) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) p[u] = 0.0;
+        return;
     }
-    for (int e = tid; e < kTU * kNR; e += 256) {
-        const int q = e % kTU, c = e / kTU;
-        Xs[q * kNR + c] = c < nr ? X[(int64_t)(rhs0 + c) * ldb + q0 + q] : 0.0;
+    int cls = kFP64, scale = 0;
+    const char* tile = dense ? reinterpret_cast<const char*>(dense) : view_tile(L, ti, tj, cls, scale);
+    double lr[16], xr[4];
+    // the stored block: rows r0.., columns q0.. (op(T) = T) or rows q0..,
+    // columns r0.. (op(T) = T^T); lr[u] = element (row e % 64, column e / 64)
+    // of it, e = tid + 256 u
+    if (!transpose)
+        fetch_block_cls(cls, tile, nb, q0, r0, X, ldb, q0, rhs0, nr, lr, xr);
+    else
+        fetch_block_cls(cls, tile, nb, r0, q0, X, ldb, q0, rhs0, nr, lr, xr);
+    if (scale != 0 && cls != kFP64) {
+#pragma unroll
+        for (int u = 0; u < 16; ++u) lr[u] = ldexp(lr[u], scale);
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        const int e = tid + 256 * u, a = e % kTU, b = e / kTU;
+        if (!transpose) Ts[b * (kTU + 1) + a] = lr[u];  // op(T)[r0 + a][q0 + b]
+        else Ts[a * (kTU + 1) + b] = lr[u];             // op(T)[r0 + b][q0 + a]
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int e = tid + 256 * u;
+        Xs[(e % kTU) * kNR + e / kTU] = xr[u];
     }
     __syncthreads();
-    const int r = tid & 63, cg = tid >> 6;  // row, group of 4 right-hand sides
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 8
     for (int q = 0; q < kTU; ++q) {
         const double t = Ts[q * (kTU + 1) + r];
 #pragma unroll
         for (int u = 0; u < 4; ++u) acc[u] += t * Xs[q * kNR + cg * 4 + u];
     }
-    double* p = part + ((int64_t)blockIdx.y * nb + r0 + r) * kNR + cg * 4;
 #pragma unroll
     for (int u = 0; u < 4; ++u) p[u] = acc[u];
 }
 
+// Y -= (assign: Y =) the sum of the nb / 64 partials, in split order.
 __global__ void tile_update_reduce_kernel(double* __restrict__ Y, int nb, int64_t ldb, int nrhs,
-                                          int rhs0, const double* __restrict__ part) {
+                                          int rhs0, const double* __restrict__ part, int assign) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= nb * kNR) return;
     const int row = e / kNR, c = e % kNR;
@@ -417,7 +376,9 @@ __global__ void tile_update_reduce_kernel(double* __restrict__ Y, int nb, int64_
     const int splits = nb / kTU;
     double s = 0.0;
     for (int sp = 0; sp < splits; ++sp) s += part[(int64_t)sp * nb * kNR + e];
-    Y[(int64_t)(rhs0 + c) * ldb + row] -= s;
+    double* y = Y + (int64_t)(rhs0 + c) * ldb + row;
+    if (assign) *y = s;
+    else *y -= s;
 }
 
 __global__ __launch_bounds__(256) void logdet_kernel(TileView L, double* __restrict__ partial) {
@@ -454,15 +415,6 @@ __global__ __launch_bounds__(256) void export_kernel(TileView L, double* __restr
 }
 
 }  // namespace
-
-hipError_t launch_tile_inv_apply(hipStream_t s, const double* xinv, int nb, const double* in,
-                                 double* out, int64_t ldb, int nrhs, bool transpose) {
-    if (nb % kIA != 0 || nrhs <= 0) return hipErrorInvalidValue;
-    dim3 grid((unsigned)(nb / kIA), (unsigned)((nrhs + kIR - 1) / kIR));
-    hipLaunchKernelGGL(tile_inv_apply_kernel, grid, dim3(256), 0, s, xinv, nb, in, out, ldb, nrhs,
-                       transpose ? 1 : 0);
-    return hipGetLastError();
-}
 
 hipError_t launch_trsv_diag(hipStream_t s, const double* Lkk, int nb, double* B, int64_t ldb,
                             int nrhs, bool transpose) {
@@ -512,20 +464,37 @@ hipError_t launch_bwd_update(hipStream_t s, const TileView& L, int k, int t0, in
     return hipSuccess;
 }
 
-hipError_t launch_tile_update(hipStream_t s, const TileView& L, int ti, int tj, bool transpose,
-                              const double* X, double* Y, int64_t ldb, int nrhs, double* partial) {
-    if (L.nb % kTU != 0) return hipErrorInvalidValue;
+namespace {
+hipError_t tile_product(hipStream_t s, const TileView& L, int ti, int tj, const double* dense,
+                        int tri, bool transpose, const double* X, double* Y, int64_t ldb,
+                        int nrhs, double* partial, int assign) {
+    if (L.nb % kTU != 0 || nrhs <= 0) return hipErrorInvalidValue;
     for (int rhs0 = 0; rhs0 < nrhs; rhs0 += kNR) {
         hipLaunchKernelGGL(tile_update_kernel, dim3(L.nb / kTU, L.nb / kTU), dim3(256), 0, s, L, ti, tj,
-                           transpose ? 1 : 0, X, ldb, nrhs, rhs0, partial);
+                           dense, tri, transpose ? 1 : 0, X, ldb, nrhs, rhs0, partial);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(tile_update_reduce_kernel, dim3((L.nb * kNR + 255) / 256), dim3(256), 0, s, Y,
-                           L.nb, ldb, nrhs, rhs0, partial);
+                           L.nb, ldb, nrhs, rhs0, partial, assign);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+}  // namespace
+
+hipError_t launch_tile_update(hipStream_t s, const TileView& L, int ti, int tj, bool transpose,
+                              const double* X, double* Y, int64_t ldb, int nrhs, double* partial) {
+    return tile_product(s, L, ti, tj, nullptr, 0, transpose, X, Y, ldb, nrhs, partial, 0);
+}
+
+hipError_t launch_tile_inv_apply(hipStream_t s, const double* xinv, int nb, const double* in,
+                                 double* out, int64_t ldb, int nrhs, bool transpose,
+                                 double* partial) {
+    // M = Xinv^T (lower) is op(T) = T^T with T = Xinv; M = Xinv (upper) is op(T) = T
+    TileView D{nullptr, nullptr, nullptr, nullptr, 1, nb};
+    return tile_product(s, D, 0, 0, xinv, transpose ? 2 : 1, !transpose, in, out, ldb, nrhs,
+                        partial, 1);
 }
 
 hipError_t launch_logdet_partials(hipStream_t s, const TileView& L, double* partial) {

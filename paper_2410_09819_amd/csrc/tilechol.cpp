@@ -365,7 +365,7 @@ tc_status fwd_enqueue(tc_ctx* ctx, const tc_factor* F, double* B, int64_t ldb, i
         }
         if (Y)
             TC_HIP(tc::launch_tile_inv_apply(sm, F->d_xinv + k * nb2, nb, B + (int64_t)k * nb,
-                                             Y + (int64_t)k * nb, ldb, nrhs, false));
+                                             Y + (int64_t)k * nb, ldb, nrhs, false, big));
         else
             TC_HIP(tc::launch_trsv_diag(sm, diag_tile(F, k), nb, B + (int64_t)k * nb, ldb, nrhs,
                                         false));
@@ -402,7 +402,7 @@ tc_status bwd_enqueue(tc_ctx* ctx, const tc_factor* F, double* B, int64_t ldb, i
         }
         if (Y)
             TC_HIP(tc::launch_tile_inv_apply(sm, F->d_xinv + k * nb2, nb, Y + (int64_t)k * nb,
-                                             B + (int64_t)k * nb, ldb, nrhs, true));
+                                             B + (int64_t)k * nb, ldb, nrhs, true, big));
         else
             TC_HIP(tc::launch_trsv_diag(sm, diag_tile(F, k), nb, B + (int64_t)k * nb, ldb, nrhs,
                                         true));

@@ -104,9 +104,11 @@ hipError_t launch_zero_upper(hipStream_t s, double* L, int Nt, int nb);
 hipError_t launch_trsv_diag(hipStream_t s, const double* Lkk, int nb, double* B, int64_t ldb,
                             int nrhs, bool transpose);
 // B rows of tiles m = k+1+t0 .. k+t0+tcount -= L[m, k] Y_k (Y_k = B rows of
-// tile k; Bbelow = B rows of tile k+1+t0).
+// tile k; Bbelow = B rows of tile k+1+t0). partial: bwd_partial_doubles(nb)
+// doubles of workspace (launches with few tiles are split over K).
 hipError_t launch_fwd_update(hipStream_t s, const TileView& L, int k, int t0, int tcount,
-                             const double* Yk, double* Bbelow, int64_t ldb, int nrhs);
+                             const double* Yk, double* Bbelow, int64_t ldb, int nrhs,
+                             double* partial);
 // Y_k -= sum L_mk^T X_m over m = k+1+t0 .. k+t0+tcount (Xbelow = B rows of
 // tile k+1+t0); partial: bwd_partial_doubles(nb) doubles of workspace.
 hipError_t launch_bwd_update(hipStream_t s, const TileView& L, int k, int t0, int tcount,

@@ -172,54 +172,129 @@ __device__ __forceinline__ void fetch_block_cls(int cls, const char* tile, int n
     }
 }
 
-// B_below[r][c] -= sum_j L[k+1+r/nb, k][r%nb][j] Y[j][c]. A workgroup owns 64
-// rows of one tile and 16 right-hand sides; thread (r, q) holds row r0 + r
-// and right-hand sides c0 + 4q .. c0 + 4q + 3. The tile's 64 x 64 blocks
-// along j and the matching Y rows pass through LDS (the sum over j runs in
-// a fixed order); the next block is loaded into registers while the
-// current one is multiplied.
-constexpr int kFwdRows = 64;
-__global__ __launch_bounds__(256) void fwd_update_kernel(TileView L, int k, int t0,
-                                                         const double* __restrict__ Y,
-                                                         double* __restrict__ Bb, int64_t ldb,
-                                                         int nrhs) {
-    __shared__ double Ls[64 * 65];  // Ls[j * 65 + r] = L[r0 + r][j0 + j] (unscaled)
-    __shared__ double Ys[64 * kNR];  // Ys[j * 16 + c] = Y[j0 + j][c0 + c]
-    const int nb = L.nb;
-    const int tid = threadIdx.x, r = tid & 63, q = tid >> 6;
-    const int c0 = blockIdx.y * kNR;
-    const int nr = nrhs - c0 < kNR ? nrhs - c0 : kNR;
-    const int64_t r0 = (int64_t)blockIdx.x * kFwdRows;
-    int cls, scale;
-    const char* tile = view_tile(L, k + 1 + t0 + (int)(r0 / nb), k, cls, scale);
-    const int rr0 = (int)(r0 % nb);
-    double lr[16], yr[4], acc[4] = {0.0, 0.0, 0.0, 0.0};
-    fetch_block_cls(cls, tile, nb, 0, rr0, Y, ldb, 0, c0, nr, lr, yr);
-    for (int j0 = 0; j0 < nb; j0 += 64) {
-        __syncthreads();
+// B_below[r][c] -= sum_j L[k+1+r/nb, k][r%nb][j] Y[j][c], on the FP64 matrix
+// cores, straight from HBM into the MFMA operands (no LDS, no barriers). A wave owns 64 rows of one tile
+// and 16 right-hand sides and runs v_mfma_f64_16x16x4f64 with A = Y^T
+// (16 RHS x 4 k) and B = L^T (4 k x 16 rows). The order of rows and of k
+// inside the MFMA blocks is free, and is chosen so that every load is a
+// short vector: row block mi of lane i is tile row 4 i + mi (the lane's
+// four rows are adjacent in a column), and in k-step t of a 16-column
+// group j0, lane group g takes column j0 + 4 g + t (its four Y rows are
+// adjacent). A wave covers the columns of its K split; with more than one
+// split, each writes its (scaled) partial sums and fwd_reduce subtracts
+// them in split order.
+template <int C>
+__device__ __forceinline__ void ld4_cls(const char* base, int64_t i, double (&v)[4]) {
+    if (C == kFP64) {
+        const d2 a = *reinterpret_cast<const d2*>(reinterpret_cast<const double*>(base) + i);
+        const d2 b = *reinterpret_cast<const d2*>(reinterpret_cast<const double*>(base) + i + 2);
+        v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+    } else if (C == kFP32) {
+        const float4 a = *reinterpret_cast<const float4*>(reinterpret_cast<const float*>(base) + i);
+        v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+    } else if (C == kFP16 || C == kBF16) {
+        const uint2 a = *reinterpret_cast<const uint2*>(reinterpret_cast<const uint16_t*>(base) + i);
+        const uint16_t h[4] = {(uint16_t)(a.x & 0xFFFFu), (uint16_t)(a.x >> 16),
+                               (uint16_t)(a.y & 0xFFFFu), (uint16_t)(a.y >> 16)};
 #pragma unroll
-        for (int u = 0; u < 16; ++u) {
-            const int e = tid + 256 * u;
-            Ls[(e / 64) * 65 + e % 64] = lr[u];
-        }
+        for (int u = 0; u < 4; ++u) v[u] = C == kFP16 ? dec_fp16(h[u]) : dec_bf16(h[u]);
+    } else {
+        const uint32_t a = *reinterpret_cast<const uint32_t*>(reinterpret_cast<const uint8_t*>(base) + i);
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int e = tid + 256 * u;
-            Ys[(e % 64) * kNR + e / 64] = yr[u];
-        }
-        __syncthreads();
-        if (j0 + 64 < nb) fetch_block_cls(cls, tile, nb, j0 + 64, rr0, Y, ldb, j0 + 64, c0, nr, lr, yr);
-#pragma unroll 8
-        for (int jj = 0; jj < 64; ++jj) {
-            const double l = Ls[jj * 65 + r];
+        for (int u = 0; u < 4; ++u) v[u] = dec_fp8((uint8_t)(a >> (8 * u)));
+    }
+}
+
+template <int C>
+__device__ __forceinline__ void fwd_mfma_wave(const char* tile, int nb, int rr0, int jbeg, int jend,
+                                              const double* __restrict__ Y, int64_t ldb, int c0,
+                                              int nr, d4 (&acc)[4]) {
+    const int lane = threadIdx.x & 63, i = lane & 15, g = lane >> 4;
+    const int64_t lofs = (int64_t)rr0 + 4 * i;
+    const bool yok = i < nr;
+    const double* yp = Y + (int64_t)(c0 + (yok ? i : 0)) * ldb + 4 * g;
+    double lv[4][4], yv[4], ln[4][4], yn[4];
+    auto fetch = [&](int j0, double (&l)[4][4], double (&y)[4]) {
 #pragma unroll
-            for (int u = 0; u < 4; ++u) acc[u] += l * Ys[jj * kNR + 4 * q + u];
+        for (int t = 0; t < 4; ++t) ld4_cls<C>(tile, (int64_t)(j0 + 4 * g + t) * nb + lofs, l[t]);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) y[t] = yok ? yp[j0 + t] : 0.0;
+    };
+    fetch(jbeg, lv, yv);
+    for (int j0 = jbeg; j0 < jend; j0 += 16) {
+        if (j0 + 16 < jend) fetch(j0 + 16, ln, yn);
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int mi = 0; mi < 4; ++mi)
+                acc[mi] = __builtin_amdgcn_mfma_f64_16x16x4f64(yv[t], lv[t][mi], acc[mi], 0, 0, 0);
+        if (j0 + 16 < jend) {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                yv[t] = yn[t];
+#pragma unroll
+                for (int mi = 0; mi < 4; ++mi) lv[t][mi] = ln[t][mi];
+            }
         }
     }
+}
+
+constexpr int kFwdWaveRows = 64;
+__global__ __launch_bounds__(256) void fwd_update_mfma_kernel(TileView L, int k, int t0, int64_t rows,
+                                                              int splits,
+                                                              const double* __restrict__ Y,
+                                                              double* __restrict__ Bb, int64_t ldb,
+                                                              int nrhs, int cbase,
+                                                              double* __restrict__ part) {
+    const int nb = L.nb;
+    const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);  // wave: rows 64 w ..
+    const int64_t row0 = w * kFwdWaveRows;
+    if (row0 >= rows) return;
+    const int split = blockIdx.y, c0 = cbase + blockIdx.z * kNR;
+    const int nr = nrhs - c0 < kNR ? nrhs - c0 : kNR;
+    const int kc = nb / splits;
+    const int jbeg = split * kc, jend = jbeg + kc;
+    int cls, scale;
+    const char* tile = view_tile(L, k + 1 + t0 + (int)(row0 / nb), k, cls, scale);
+    const int rr0 = (int)(row0 % nb);
+    d4 acc[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
-        if (4 * q + u < nr)
-            Bb[(int64_t)(c0 + 4 * q + u) * ldb + r0 + r] -= scale ? ldexp(acc[u], scale) : acc[u];
+    for (int mi = 0; mi < 4; ++mi) acc[mi] = d4{0.0, 0.0, 0.0, 0.0};
+    switch (cls) {
+        case kFP64: fwd_mfma_wave<kFP64>(tile, nb, rr0, jbeg, jend, Y, ldb, c0, nr, acc); break;
+        case kFP32: fwd_mfma_wave<kFP32>(tile, nb, rr0, jbeg, jend, Y, ldb, c0, nr, acc); break;
+        case kFP16: fwd_mfma_wave<kFP16>(tile, nb, rr0, jbeg, jend, Y, ldb, c0, nr, acc); break;
+        case kBF16: fwd_mfma_wave<kBF16>(tile, nb, rr0, jbeg, jend, Y, ldb, c0, nr, acc); break;
+        default: fwd_mfma_wave<kFP8>(tile, nb, rr0, jbeg, jend, Y, ldb, c0, nr, acc); break;
+    }
+    // lane l, value v of block mi: row 4 (l % 16) + mi, right-hand side l / 16 + 4 v
+    const int lane = threadIdx.x & 63, i = lane & 15, g = lane >> 4;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int c = g + 4 * v;
+        if (c >= nr) continue;
+#pragma unroll
+        for (int mi = 0; mi < 4; ++mi) {
+            const int64_t r = row0 + 4 * i + mi;
+            const double a = scale ? ldexp(acc[mi][v], scale) : acc[mi][v];
+            if (splits == 1)
+                Bb[(int64_t)(c0 + c) * ldb + r] -= a;
+            else
+                part[((int64_t)split * rows + r) * kNR + c] = a;
+        }
+    }
+}
+
+__global__ void fwd_reduce_kernel(double* __restrict__ Bb, int64_t rows, int64_t ldb, int nrhs,
+                                  int c0, int splits, const double* __restrict__ part) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= rows * kNR) return;
+    const int64_t r = e / kNR;
+    const int c = (int)(e % kNR);
+    if (c0 + c >= nrhs) return;
+    double s = 0.0;
+    for (int sp = 0; sp < splits; ++sp) s += part[(int64_t)sp * rows * kNR + e];
+    Bb[(int64_t)(c0 + c) * ldb + r] -= s;
 }
 
 // partial[split][j][c] = sum over the split's rows r of L[k+1+r/nb, k][r%nb][j]
@@ -424,16 +499,38 @@ hipError_t launch_trsv_diag(hipStream_t s, const double* Lkk, int nb, double* B,
 }
 
 hipError_t launch_fwd_update(hipStream_t s, const TileView& L, int k, int t0, int tcount,
-                             const double* Yk, double* Bbelow, int64_t ldb, int nrhs) {
+                             const double* Yk, double* Bbelow, int64_t ldb, int nrhs,
+                             double* partial) {
     if (tcount <= 0) return hipSuccess;
     if (t0 < 0 || k + 1 + t0 + tcount > L.Nt) return hipErrorInvalidValue;
     const int64_t rows = (int64_t)tcount * L.nb;
-    if (rows % kFwdRows != 0 || L.nb % 32 != 0) return hipErrorInvalidValue;
-    dim3 grid((unsigned)(rows / kFwdRows), (nrhs + kNR - 1) / kNR);
-    hipLaunchKernelGGL(fwd_update_kernel, grid, dim3(256), 0, s, L, k, t0, Yk, Bbelow, ldb, nrhs);
-    return hipGetLastError();
+    if (L.nb % kFwdWaveRows != 0 || L.nb % 32 != 0 || nrhs <= 0) return hipErrorInvalidValue;
+    // K splits while the launch has few tiles: tcount * splits <= 64 keeps
+    // the partials within bwd_partial_doubles(nb), and each split keeps a
+    // whole number of 16-column groups
+    int splits = 1;
+    while (splits < 8 && tcount * splits * 2 <= 64 && L.nb % (16 * splits * 2) == 0) splits *= 2;
+    const int64_t waves = rows / kFwdWaveRows;
+    const unsigned wgs = (unsigned)((waves + 3) / 4);
+    const int groups = (nrhs + kNR - 1) / kNR;
+    if (splits == 1) {
+        hipLaunchKernelGGL(fwd_update_mfma_kernel, dim3(wgs, 1, (unsigned)groups), dim3(256), 0, s, L,
+                           k, t0, rows, 1, Yk, Bbelow, ldb, nrhs, 0, partial);
+        return hipGetLastError();
+    }
+    // split: the partials hold one group of 16 right-hand sides at a time
+    for (int c0 = 0; c0 < nrhs; c0 += kNR) {
+        hipLaunchKernelGGL(fwd_update_mfma_kernel, dim3(wgs, (unsigned)splits, 1), dim3(256), 0, s, L,
+                           k, t0, rows, splits, Yk, Bbelow, ldb, nrhs, c0, partial);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(fwd_reduce_kernel, dim3((unsigned)((rows * kNR + 255) / 256)), dim3(256), 0,
+                           s, Bbelow, rows, ldb, nrhs, c0, splits, partial);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
-
 int bwd_splits(int64_t rows) {
     // rows is a multiple of nb >= 128; aim for >= 512 workgroups with at least
     // 256 rows each

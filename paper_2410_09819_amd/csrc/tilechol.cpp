@@ -355,6 +355,7 @@ tc_status fwd_enqueue(tc_ctx* ctx, const tc_factor* F, double* B, int64_t ldb, i
     hipStream_t sm = ctx->stream, ss = ctx->aux[0];
     hipEvent_t* ev_t = ctx->solve_ev.data();
     hipEvent_t* ev_s = ev_t + Nt;
+    double* part_side = big + tc::bwd_partial_doubles(nb);
     double* X = Y ? Y : B;  // where the solved tile rows go
     const int64_t nb2 = (int64_t)nb * nb;
     for (int k = 0; k < Nt; ++k) {
@@ -373,7 +374,7 @@ tc_status fwd_enqueue(tc_ctx* ctx, const tc_factor* F, double* B, int64_t ldb, i
             TC_HIP(hipEventRecord(ev_t[k], sm));
             TC_HIP(hipStreamWaitEvent(ss, ev_t[k], 0));
             TC_HIP(tc::launch_fwd_update(ss, V, k, 1, Nt - k - 2, X + (int64_t)k * nb,
-                                         B + (int64_t)(k + 2) * nb, ldb, nrhs));
+                                         B + (int64_t)(k + 2) * nb, ldb, nrhs, part_side));
             TC_HIP(hipEventRecord(ev_s[k], ss));
         }
     }

@@ -142,7 +142,7 @@ __device__ __forceinline__ double ld_cls(const char* base, int64_t i) {
 // matching 64 x 16 block of right-hand sides into registers: thread t takes
 // L elements (row t % 64 + 64-row offset, column j0 + t / 64 + 4u), read
 // along contiguous rows, and right-hand-side elements (row t % 64, column
-// t / 64 + 4u). The caller stores them to LDS a block later.
+// t / 64 + 4u). The caller stores them to LDS.
 template <int C>
 __device__ __forceinline__ void fetch_block(const char* tile, int nb, int64_t col0, int row0,
                                             const double* X, int64_t ldb, int64_t xrow0, int c0,
@@ -298,67 +298,87 @@ __global__ void fwd_reduce_kernel(double* __restrict__ Bb, int64_t rows, int64_t
 }
 
 // partial[split][j][c] = sum over the split's rows r of L[k+1+r/nb, k][r%nb][j]
-// X[r][c] for the 64 columns j of this workgroup's strip.
-constexpr int kBwdStrip = 64;
-constexpr int kBwdSub = 64;
-__global__ __launch_bounds__(256) void bwd_partial_kernel(TileView L, int k, int t0, int64_t rows_per_split,
-                                                          const double* __restrict__ X,
-                                                          int64_t ldb, int nrhs, int rhs0,
-                                                          double* __restrict__ partial) {
-    __shared__ double Ls[kBwdStrip * (kBwdSub + 1)];  // Ls[j * 65 + r]
-    __shared__ double Xs[kBwdSub * kNR];
-    const int nb = L.nb;
-    const int tid = threadIdx.x;
-    const int j0 = blockIdx.x * kBwdStrip;
-    const int split = blockIdx.y;
-    const int nr = nrhs - rhs0 < kNR ? nrhs - rhs0 : kNR;
-    const int jj = tid & 63, cg = tid >> 6;  // column of the strip, group of 4 RHS
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    const int64_t rbeg = (int64_t)split * rows_per_split;
-    const int64_t rend = rbeg + rows_per_split;
-    // the L block (64 rows of the panel x the 64 strip columns) and the 64
-    // X rows of each sub-block pass through LDS; the next sub-block is loaded
-    // into registers while the current one is multiplied. The tile's class
-    // is looked up once per sub-block and its power-of-two scale applied to
-    // the loaded values (the sub-blocks of a split may span several tiles).
-    double lr[16], xr[4];
-    int scale = 0;
-    auto fetch = [&](int64_t rb) {
-        int cls;
-        const char* tile = view_tile(L, k + 1 + t0 + (int)(rb / nb), k, cls, scale);
-        // block element (row rr + r, column j0 + j) at column-major offset
-        // (j0 + j) * nb + rr + r: fetch_block's (col0 + e / 64, row0 + e % 64)
-        fetch_block_cls(cls, tile, nb, j0, (int)(rb % nb), X, ldb, rb, rhs0, nr, lr, xr);
-        if (scale) {
+// X[r][c] for the columns j of the tile column k, on the FP64 matrix cores,
+// straight from HBM into the
+// MFMA operands. A wave owns 16 columns j of the tile column and the rows
+// of its split, and runs v_mfma_f64_16x16x4f64 with A = X^T (16 RHS x 4 k)
+// and B = L (4 k x 16 columns). Rows go in 32-row groups (never across a
+// tile, as nb and the split length are multiples of 64); in k-step t of a
+// group at row rb, lane group g takes row rb + 8 g + t, so each lane reads
+// 8 adjacent rows of its column of L and of its right-hand side of X. The
+// next group is loaded while the current one is multiplied; each tile's
+// power-of-two scale is applied to its loaded values (exact).
+template <int C>
+__device__ __forceinline__ void bwd_mfma_range(const char* tile, int nb, int scale, int col,
+                                               int64_t rr, int64_t xr0, int ngroups,
+                                               const double* __restrict__ xp, bool xok, d4& acc) {
+    const int g = (threadIdx.x & 63) >> 4;
+    double lv[8], xv[8], ln[8], xn[8];
+    auto fetch = [&](int q, double (&l)[8], double (&x)[8]) {
+        const int64_t o = (int64_t)32 * q + 8 * g;
 #pragma unroll
-            for (int u = 0; u < 16; ++u) lr[u] = ldexp(lr[u], scale);
+        for (int u = 0; u < 2; ++u) {
+            double v4[4];
+            ld4_cls<C>(tile, (int64_t)col * nb + rr + o + 4 * u, v4);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) l[4 * u + t] = v4[t];
         }
+        if (C != kFP64 && scale != 0) {
+#pragma unroll
+            for (int t = 0; t < 8; ++t) l[t] = ldexp(l[t], scale);
+        }
+#pragma unroll
+        for (int t = 0; t < 8; ++t) x[t] = xok ? xp[xr0 + o + t] : 0.0;
     };
-    if (rbeg < rend) fetch(rbeg);
-    for (int64_t rb = rbeg; rb < rend; rb += kBwdSub) {
-        __syncthreads();
+    fetch(0, lv, xv);
+    for (int q = 0; q < ngroups; ++q) {
+        if (q + 1 < ngroups) fetch(q + 1, ln, xn);
 #pragma unroll
-        for (int u = 0; u < 16; ++u) {
-            const int e = tid + 256 * u;
-            Ls[(e / kBwdSub) * (kBwdSub + 1) + e % kBwdSub] = lr[u];
-        }
+        for (int t = 0; t < 8; ++t) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xv[t], lv[t], acc, 0, 0, 0);
+        if (q + 1 < ngroups) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int e = tid + 256 * u;
-            Xs[(e % kBwdSub) * kNR + e / kBwdSub] = xr[u];
-        }
-        __syncthreads();
-        if (rb + kBwdSub < rend) fetch(rb + kBwdSub);
-#pragma unroll 8
-        for (int r = 0; r < kBwdSub; ++r) {
-            const double lv = Ls[jj * (kBwdSub + 1) + r];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) acc[q] += lv * Xs[r * kNR + cg * 4 + q];
+            for (int t = 0; t < 8; ++t) {
+                lv[t] = ln[t];
+                xv[t] = xn[t];
+            }
         }
     }
-    double* p = partial + (int64_t)split * nb * kNR;
+}
+
+__global__ __launch_bounds__(256) void bwd_partial_mfma_kernel(TileView L, int k, int t0,
+                                                               int64_t rows_per_split,
+                                                               const double* __restrict__ X,
+                                                               int64_t ldb, int nrhs, int rhs0,
+                                                               double* __restrict__ partial) {
+    const int nb = L.nb;
+    const int lane = threadIdx.x & 63, i = lane & 15, g = lane >> 4;
+    const int col = blockIdx.x * 64 + (threadIdx.x >> 6) * 16 + i;  // this lane's column of L
+    const int split = blockIdx.y;
+    const int nr = nrhs - rhs0 < kNR ? nrhs - rhs0 : kNR;
+    const bool xok = i < nr;
+    const double* xp = X + (int64_t)(rhs0 + (xok ? i : 0)) * ldb;
+    const int64_t rbeg = (int64_t)split * rows_per_split, rend = rbeg + rows_per_split;
+    d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+    for (int64_t ra = rbeg; ra < rend;) {
+        const int m = (int)(ra / nb);
+        const int64_t tend = (int64_t)(m + 1) * nb < rend ? (int64_t)(m + 1) * nb : rend;
+        int cls, scale;
+        const char* tile = view_tile(L, k + 1 + t0 + m, k, cls, scale);
+        const int64_t rr = ra - (int64_t)m * nb;
+        const int ng = (int)((tend - ra) / 32);
+        switch (cls) {
+            case kFP64: bwd_mfma_range<kFP64>(tile, nb, scale, col, rr, ra, ng, xp, xok, acc); break;
+            case kFP32: bwd_mfma_range<kFP32>(tile, nb, scale, col, rr, ra, ng, xp, xok, acc); break;
+            case kFP16: bwd_mfma_range<kFP16>(tile, nb, scale, col, rr, ra, ng, xp, xok, acc); break;
+            case kBF16: bwd_mfma_range<kBF16>(tile, nb, scale, col, rr, ra, ng, xp, xok, acc); break;
+            default: bwd_mfma_range<kFP8>(tile, nb, scale, col, rr, ra, ng, xp, xok, acc); break;
+        }
+        ra = tend;
+    }
+    // lane l, value v: right-hand side l / 16 + 4 v, column col
+    double* p = partial + ((int64_t)split * nb + col) * kNR;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) p[(int64_t)(j0 + jj) * kNR + cg * 4 + q] = acc[q];
+    for (int v = 0; v < 4; ++v) p[g + 4 * v] = acc[v];
 }
 
 __global__ void bwd_reduce_kernel(double* __restrict__ Y, int nb, int64_t ldb, int nrhs, int rhs0,
@@ -532,11 +552,11 @@ hipError_t launch_fwd_update(hipStream_t s, const TileView& L, int k, int t0, in
     return hipSuccess;
 }
 int bwd_splits(int64_t rows) {
-    // rows is a multiple of nb >= 128; aim for >= 512 workgroups with at least
-    // 256 rows each
-    int64_t s = rows / 256;
+    // rows is a multiple of nb (itself a multiple of 64): up to 64 splits of
+    // at least 128 rows, each a multiple of 64 rows
+    int64_t s = rows / 128;
     if (s > 64) s = 64;
-    while (s > 1 && rows % (s * kBwdSub) != 0) --s;
+    while (s > 1 && rows % (s * 64) != 0) --s;
     return s < 1 ? 1 : (int)s;
 }
 
@@ -546,11 +566,12 @@ hipError_t launch_bwd_update(hipStream_t s, const TileView& L, int k, int t0, in
     if (tcount <= 0) return hipSuccess;
     if (t0 < 0 || k + 1 + t0 + tcount > L.Nt) return hipErrorInvalidValue;
     const int64_t rows = (int64_t)tcount * L.nb;
+    if (L.nb % 64 != 0 || nrhs <= 0) return hipErrorInvalidValue;
     const int splits = bwd_splits(rows);
     for (int rhs0 = 0; rhs0 < nrhs; rhs0 += kNR) {
-        dim3 grid(L.nb / kBwdStrip, splits);
-        hipLaunchKernelGGL(bwd_partial_kernel, grid, dim3(256), 0, s, L, k, t0, rows / splits, Xbelow,
-                           ldb, nrhs, rhs0, partial);
+        dim3 grid(L.nb / 64, splits);
+        hipLaunchKernelGGL(bwd_partial_mfma_kernel, grid, dim3(256), 0, s, L, k, t0, rows / splits,
+                           Xbelow, ldb, nrhs, rhs0, partial);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(bwd_reduce_kernel, dim3((L.nb * kNR + 255) / 256), dim3(256), 0, s, Yk,

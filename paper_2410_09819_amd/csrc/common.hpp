@@ -114,7 +114,7 @@ hipError_t launch_fwd_update(hipStream_t s, const TileView& L, int k, int t0, in
 hipError_t launch_bwd_update(hipStream_t s, const TileView& L, int k, int t0, int tcount,
                              const double* Xbelow, double* Yk, int64_t ldb, int nrhs,
                              double* partial);
-int bwd_splits(int64_t rows);
+int64_t bwd_split_rows(int64_t rows);
 inline int64_t bwd_partial_doubles(int nb) { return (int64_t)64 * nb * 16; }
 // Y -= op(T) X for the single tile T = (ti, tj) of a factor view (op = T or
 // T^T), split over nb / 64 inner blocks (partial: nb / 64 * nb * 16 doubles,

@@ -300,9 +300,10 @@ __global__ void fwd_reduce_kernel(double* __restrict__ Bb, int64_t rows, int64_t
 // partial[split][j][c] = sum over the split's rows r of L[k+1+r/nb, k][r%nb][j]
 // X[r][c] for the columns j of the tile column k, on the FP64 matrix cores,
 // straight from HBM into the
-// MFMA operands. A wave owns 16 columns j of the tile column and the rows
-// of its split, and runs v_mfma_f64_16x16x4f64 with A = X^T (16 RHS x 4 k)
-// and B = L (4 k x 16 columns). Rows go in 32-row groups (never across a
+// MFMA operands. A wave owns 32 columns j of the tile column (two MFMA
+// blocks sharing the X operand) and the rows of its split, and runs
+// v_mfma_f64_16x16x4f64 with A = X^T (16 RHS x 4 k) and B = L (4 k x 16
+// columns). Rows go in 32-row groups (never across a
 // tile, as nb and the split length are multiples of 64); in k-step t of a
 // group at row rb, lane group g takes row rb + 8 g + t, so each lane reads
 // 8 adjacent rows of its column of L and of its right-hand side of X. The
@@ -311,21 +312,26 @@ __global__ void fwd_reduce_kernel(double* __restrict__ Bb, int64_t rows, int64_t
 template <int C>
 __device__ __forceinline__ void bwd_mfma_range(const char* tile, int nb, int scale, int col,
                                                int64_t rr, int64_t xr0, int ngroups,
-                                               const double* __restrict__ xp, bool xok, d4& acc) {
+                                               const double* __restrict__ xp, bool xok,
+                                               d4 (&acc)[2]) {
     const int g = (threadIdx.x & 63) >> 4;
-    double lv[8], xv[8], ln[8], xn[8];
-    auto fetch = [&](int q, double (&l)[8], double (&x)[8]) {
+    double lv[2][8], xv[8], ln[2][8], xn[8];
+    auto fetch = [&](int q, double (&l)[2][8], double (&x)[8]) {
         const int64_t o = (int64_t)32 * q + 8 * g;
 #pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            double v4[4];
-            ld4_cls<C>(tile, (int64_t)col * nb + rr + o + 4 * u, v4);
+        for (int ni = 0; ni < 2; ++ni)
 #pragma unroll
-            for (int t = 0; t < 4; ++t) l[4 * u + t] = v4[t];
-        }
+            for (int u = 0; u < 2; ++u) {
+                double v4[4];
+                ld4_cls<C>(tile, (int64_t)(col + 16 * ni) * nb + rr + o + 4 * u, v4);
+#pragma unroll
+                for (int t = 0; t < 4; ++t) l[ni][4 * u + t] = v4[t];
+            }
         if (C != kFP64 && scale != 0) {
 #pragma unroll
-            for (int t = 0; t < 8; ++t) l[t] = ldexp(l[t], scale);
+            for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+                for (int t = 0; t < 8; ++t) l[ni][t] = ldexp(l[ni][t], scale);
         }
 #pragma unroll
         for (int t = 0; t < 8; ++t) x[t] = xok ? xp[xr0 + o + t] : 0.0;
@@ -334,31 +340,39 @@ __device__ __forceinline__ void bwd_mfma_range(const char* tile, int nb, int sca
     for (int q = 0; q < ngroups; ++q) {
         if (q + 1 < ngroups) fetch(q + 1, ln, xn);
 #pragma unroll
-        for (int t = 0; t < 8; ++t) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xv[t], lv[t], acc, 0, 0, 0);
+        for (int t = 0; t < 8; ++t)
+#pragma unroll
+            for (int ni = 0; ni < 2; ++ni)
+                acc[ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(xv[t], lv[ni][t], acc[ni], 0, 0, 0);
         if (q + 1 < ngroups) {
 #pragma unroll
             for (int t = 0; t < 8; ++t) {
-                lv[t] = ln[t];
                 xv[t] = xn[t];
+#pragma unroll
+                for (int ni = 0; ni < 2; ++ni) lv[ni][t] = ln[ni][t];
             }
         }
     }
 }
 
+constexpr int kBwdWaveCols = 32;
 __global__ __launch_bounds__(256) void bwd_partial_mfma_kernel(TileView L, int k, int t0,
-                                                               int64_t rows_per_split,
+                                                               int64_t rows, int64_t rows_per_split,
                                                                const double* __restrict__ X,
                                                                int64_t ldb, int nrhs, int rhs0,
                                                                double* __restrict__ partial) {
     const int nb = L.nb;
     const int lane = threadIdx.x & 63, i = lane & 15, g = lane >> 4;
-    const int col = blockIdx.x * 64 + (threadIdx.x >> 6) * 16 + i;  // this lane's column of L
+    const int cbase = (blockIdx.x * 4 + (threadIdx.x >> 6)) * kBwdWaveCols;  // the wave's columns
+    if (cbase >= nb) return;
+    const int col = cbase + i;  // this lane's columns: col, col + 16
     const int split = blockIdx.y;
     const int nr = nrhs - rhs0 < kNR ? nrhs - rhs0 : kNR;
     const bool xok = i < nr;
     const double* xp = X + (int64_t)(rhs0 + (xok ? i : 0)) * ldb;
-    const int64_t rbeg = (int64_t)split * rows_per_split, rend = rbeg + rows_per_split;
-    d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+    const int64_t rbeg = (int64_t)split * rows_per_split;
+    const int64_t rend = rbeg + rows_per_split < rows ? rbeg + rows_per_split : rows;
+    d4 acc[2] = {d4{0.0, 0.0, 0.0, 0.0}, d4{0.0, 0.0, 0.0, 0.0}};
     for (int64_t ra = rbeg; ra < rend;) {
         const int m = (int)(ra / nb);
         const int64_t tend = (int64_t)(m + 1) * nb < rend ? (int64_t)(m + 1) * nb : rend;
@@ -375,10 +389,13 @@ __global__ __launch_bounds__(256) void bwd_partial_mfma_kernel(TileView L, int k
         }
         ra = tend;
     }
-    // lane l, value v: right-hand side l / 16 + 4 v, column col
-    double* p = partial + ((int64_t)split * nb + col) * kNR;
+    // block ni, lane l, value v: right-hand side l / 16 + 4 v, column col + 16 ni
 #pragma unroll
-    for (int v = 0; v < 4; ++v) p[g + 4 * v] = acc[v];
+    for (int ni = 0; ni < 2; ++ni) {
+        double* p = partial + ((int64_t)split * nb + col + 16 * ni) * kNR;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) p[g + 4 * v] = acc[ni][v];
+    }
 }
 
 __global__ void bwd_reduce_kernel(double* __restrict__ Y, int nb, int64_t ldb, int nrhs, int rhs0,
@@ -551,13 +568,14 @@ hipError_t launch_fwd_update(hipStream_t s, const TileView& L, int k, int t0, in
     }
     return hipSuccess;
 }
-int bwd_splits(int64_t rows) {
-    // rows is a multiple of nb (itself a multiple of 64): up to 64 splits of
-    // at least 128 rows, each a multiple of 64 rows
+// Split of a backward update's rows: up to 64 splits, each a multiple of 64
+// rows long (the last one may be shorter), at least 128 rows where possible.
+int64_t bwd_split_rows(int64_t rows) {
     int64_t s = rows / 128;
     if (s > 64) s = 64;
-    while (s > 1 && rows % (s * 64) != 0) --s;
-    return s < 1 ? 1 : (int)s;
+    if (s < 1) s = 1;
+    const int64_t per = (rows + s - 1) / s;
+    return (per + 63) / 64 * 64;
 }
 
 hipError_t launch_bwd_update(hipStream_t s, const TileView& L, int k, int t0, int tcount,
@@ -567,10 +585,11 @@ hipError_t launch_bwd_update(hipStream_t s, const TileView& L, int k, int t0, in
     if (t0 < 0 || k + 1 + t0 + tcount > L.Nt) return hipErrorInvalidValue;
     const int64_t rows = (int64_t)tcount * L.nb;
     if (L.nb % 64 != 0 || nrhs <= 0) return hipErrorInvalidValue;
-    const int splits = bwd_splits(rows);
+    const int64_t per = bwd_split_rows(rows);
+    const int splits = (int)((rows + per - 1) / per);
     for (int rhs0 = 0; rhs0 < nrhs; rhs0 += kNR) {
-        dim3 grid(L.nb / 64, splits);
-        hipLaunchKernelGGL(bwd_partial_mfma_kernel, grid, dim3(256), 0, s, L, k, t0, rows / splits,
+        dim3 grid((L.nb + 4 * kBwdWaveCols - 1) / (4 * kBwdWaveCols), splits);
+        hipLaunchKernelGGL(bwd_partial_mfma_kernel, grid, dim3(256), 0, s, L, k, t0, rows, per,
                            Xbelow, ldb, nrhs, rhs0, partial);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;

@@ -178,9 +178,9 @@ __device__ __forceinline__ void fetch_block_cls(int cls, const char* tile, int n
 // (16 RHS x 4 k) and B = L^T (4 k x 16 rows). The order of rows and of k
 // inside the MFMA blocks is free, and is chosen so that every load is a
 // short vector: row block mi of lane i is tile row 4 i + mi (the lane's
-// four rows are adjacent in a column), and in k-step t of a 16-column
-// group j0, lane group g takes column j0 + 4 g + t (its four Y rows are
-// adjacent). A wave covers the columns of its K split; with more than one
+// four rows are adjacent in a column), and in k-step t of a 32-column
+// group j0, lane group g takes column j0 + 8 g + t (its eight Y rows are
+// adjacent). The next group is loaded while the current one is multiplied. A wave covers the columns of its K split; with more than one
 // split, each writes its (scaled) partial sums and fwd_reduce subtracts
 // them in split order.
 template <int C>
@@ -212,25 +212,25 @@ __device__ __forceinline__ void fwd_mfma_wave(const char* tile, int nb, int rr0,
     const int lane = threadIdx.x & 63, i = lane & 15, g = lane >> 4;
     const int64_t lofs = (int64_t)rr0 + 4 * i;
     const bool yok = i < nr;
-    const double* yp = Y + (int64_t)(c0 + (yok ? i : 0)) * ldb + 4 * g;
-    double lv[4][4], yv[4], ln[4][4], yn[4];
-    auto fetch = [&](int j0, double (&l)[4][4], double (&y)[4]) {
+    const double* yp = Y + (int64_t)(c0 + (yok ? i : 0)) * ldb + 8 * g;
+    double lv[8][4], yv[8], ln[8][4], yn[8];
+    auto fetch = [&](int j0, double (&l)[8][4], double (&y)[8]) {
 #pragma unroll
-        for (int t = 0; t < 4; ++t) ld4_cls<C>(tile, (int64_t)(j0 + 4 * g + t) * nb + lofs, l[t]);
+        for (int t = 0; t < 8; ++t) ld4_cls<C>(tile, (int64_t)(j0 + 8 * g + t) * nb + lofs, l[t]);
 #pragma unroll
-        for (int t = 0; t < 4; ++t) y[t] = yok ? yp[j0 + t] : 0.0;
+        for (int t = 0; t < 8; ++t) y[t] = yok ? yp[j0 + t] : 0.0;
     };
     fetch(jbeg, lv, yv);
-    for (int j0 = jbeg; j0 < jend; j0 += 16) {
-        if (j0 + 16 < jend) fetch(j0 + 16, ln, yn);
+    for (int j0 = jbeg; j0 < jend; j0 += 32) {
+        if (j0 + 32 < jend) fetch(j0 + 32, ln, yn);
 #pragma unroll
-        for (int t = 0; t < 4; ++t)
+        for (int t = 0; t < 8; ++t)
 #pragma unroll
             for (int mi = 0; mi < 4; ++mi)
                 acc[mi] = __builtin_amdgcn_mfma_f64_16x16x4f64(yv[t], lv[t][mi], acc[mi], 0, 0, 0);
-        if (j0 + 16 < jend) {
+        if (j0 + 32 < jend) {
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
+            for (int t = 0; t < 8; ++t) {
                 yv[t] = yn[t];
 #pragma unroll
                 for (int mi = 0; mi < 4; ++mi) lv[t][mi] = ln[t][mi];
@@ -544,9 +544,9 @@ hipError_t launch_fwd_update(hipStream_t s, const TileView& L, int k, int t0, in
     if (L.nb % kFwdWaveRows != 0 || L.nb % 32 != 0 || nrhs <= 0) return hipErrorInvalidValue;
     // K splits while the launch has few tiles: tcount * splits <= 64 keeps
     // the partials within bwd_partial_doubles(nb), and each split keeps a
-    // whole number of 16-column groups
+    // whole number of 32-column groups
     int splits = 1;
-    while (splits < 8 && tcount * splits * 2 <= 64 && L.nb % (16 * splits * 2) == 0) splits *= 2;
+    while (splits < 8 && tcount * splits * 2 <= 64 && L.nb % (32 * splits * 2) == 0) splits *= 2;
     const int64_t waves = rows / kFwdWaveRows;
     const unsigned wgs = (unsigned)((waves + 3) / 4);
     const int groups = (nrhs + kNR - 1) / kNR;

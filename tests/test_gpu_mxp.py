@@ -106,6 +106,43 @@ def test_refined_solve(tc, case, eps, nrhs):
     assert abs(st["iterations"] - it_o) <= 2
 
 
+def test_bf16_map_factor_and_refined_solve(tc, case):
+    """A map with BF16 in place of FP16 (classes FP64 / FP32 / BF16 / FP8 at
+    target 1e-5: 16 / 52 / 25 / 43 tiles): the factor against the oracle's
+    emulation of the same map, and a refined solve of 20 right-hand sides
+    (two groups of 16 through every solve kernel, K-split forward panels and
+    ragged backward splits included)."""
+    n, nb, Nt, A = case["n"], case["nb"], case["Nt"], case["A"]
+    eps, nrhs = 1e-5, 20
+    cm = tc.precision_map(Nt, case["norms"], case["fro"], eps,
+                          allowed=(tc.FP64, tc.FP32, tc.BF16, tc.FP8E4M3))
+    assert np.count_nonzero(cm == tc.BF16) >= 8
+    ctx = tc.Context(n, nb, nrhs=nrhs)
+    Ad = to_dev(tc.pack_lower(A, nb))
+    F = tc.factorize(ctx, Ad, n, nb, cmap=cm)
+    assert F.stats.info == 0
+    Lg = tc.unpack_lower(tc.export(ctx, F).cpu().numpy(), n, nb)
+    for j in range(Nt):
+        for i in range(j + 1, Nt):
+            t = Lg[i * nb:(i + 1) * nb, j * nb:(j + 1) * nb]
+            c = int(cm[oracle.tile_index(Nt, i, j)])
+            assert np.array_equal(oracle.round_tile(t, c)[0], t), (i, j, c)
+    Lo, info = oracle.mxp_tile_cholesky(A, nb, cm)
+    assert info == 0
+    be_g, be_o = oracle.backward_error(A, Lg), oracle.backward_error(A, Lo)
+    assert be_g <= eps and be_g <= 10 * be_o, (be_g, be_o)
+    diff = np.linalg.norm(Lg - Lo) / np.linalg.norm(Lo)
+    assert diff <= 4 * case["kappa"] * (be_g + be_o) + 1e-13, diff
+    B = si.standard_normal((n, nrhs), seed=si.rhs_seed(5))
+    Bd = to_dev(np.ascontiguousarray(B.T))
+    st = tc.solve_refine(ctx, F, Ad, Bd, max_iter=30, tol=1e-9)
+    X = Bd.cpu().numpy().T
+    rel = np.linalg.norm(B - A @ X, axis=0) / np.linalg.norm(B, axis=0)
+    assert st["converged"] and rel.max() <= 1e-9, (st, rel.max())
+    _, it_o, _ = oracle.refine(A, Lo, B, tol=1e-9)
+    assert abs(st["iterations"] - it_o) <= 2
+
+
 def test_refinement_reports_nonconvergence(tc, case):
     n, nb, Nt, A = case["n"], case["nb"], case["Nt"], case["A"]
     cm = tc.precision_map(Nt, case["norms"], case["fro"], 1e-3)

@@ -23,8 +23,9 @@ Factorization with Static Task Scheduling").
 Pins (what ties each function to something other than itself) live in
 tests/test_oracle_*.py: exact integer factors, the closed-form factor of the
 second-difference matrix, brute force on small matrices, LAPACK's Cholesky,
-closed forms of the Matern function at half-integer smoothness, and the
-norm bound that the precision criterion guarantees.
+closed forms of the Matern function at half-integer smoothness, the
+norm bound that the precision criterion guarantees, and hand-worked
+scalar-tile factors for the low classes' update arithmetic (class_update).
 """
 from __future__ import annotations
 
@@ -310,12 +311,35 @@ def round_tile(t: np.ndarray, c: int) -> tuple[np.ndarray, int]:
 # still stored in binary64.
 # ---------------------------------------------------------------------------
 
+def class_update(C: np.ndarray, ops, q: int) -> np.ndarray:
+    """C - sum_{(a, b) in ops} a b^T in the arithmetic of class q (the
+    reading of Section IV-C above). ops: the stored operand tiles
+    (Lh_mn, Lh_kn) for n = 0 .. k-1, in that order. q = FP64: binary64
+    products and sums. Otherwise each stored operand is first rounded to
+    the output tile's class q with its own per-tile scale (Q_q: an operand
+    stored in a wider class loses its extra bits here), each tile product
+    is a float32 matrix product of the rounded operands, and the products
+    are summed into a float32 accumulator; the accumulated update is
+    subtracted from C in binary64."""
+    if q == FP64:
+        for a, b in ops:
+            C -= a @ b.T
+        return C
+    acc = np.zeros(C.shape, dtype=np.float32)
+    for a, b in ops:
+        ra, _ = round_tile(a, q)
+        rb, _ = round_tile(b, q)
+        acc += (ra.astype(np.float32) @ rb.astype(np.float32).T).astype(np.float32)
+    return C - acc.astype(np.float64)
+
+
 def mxp_tile_cholesky(A: np.ndarray, nb: int, cmap: np.ndarray, fp64_update: int = FP64):
     """Mixed-precision left-looking tile Cholesky. Returns (Lh, info): Lh the
     stored factor as binary64 values (each tile exactly representable in
     its class with its scale), info as in tile_cholesky. fp64_update: the
     class whose arithmetic computes the updates into FP64-class tiles and
-    the diagonal SYRK (FP64, or FP32 for the variant above)."""
+    the diagonal SYRK (FP64, or FP32 for the variant above). Every update
+    goes through class_update."""
     from scipy.linalg import solve_triangular
     n = A.shape[0]
     Nt = n // nb
@@ -325,28 +349,18 @@ def mxp_tile_cholesky(A: np.ndarray, nb: int, cmap: np.ndarray, fp64_update: int
     def T(M, i, j):
         return M[i * nb:(i + 1) * nb, j * nb:(j + 1) * nb]
 
-    def update(C, m, k, q):
-        """C - sum_{n<k} Lh_mn Lh_kn^T in class q's arithmetic."""
-        if q == FP64:
-            for n2 in range(k):
-                C -= T(Lh, m, n2) @ T(Lh, k, n2).T
-            return C
-        acc = np.zeros((nb, nb), dtype=np.float32)
-        for n2 in range(k):
-            a, _ = round_tile(T(Lh, m, n2), q)
-            b, _ = round_tile(T(Lh, k, n2), q)
-            acc += (a.astype(np.float32) @ b.astype(np.float32).T).astype(np.float32)
-        return C - acc.astype(np.float64)
+    def ops(m, k):
+        return [(T(Lh, m, n2), T(Lh, k, n2)) for n2 in range(k)]
 
     for k in range(Nt):
-        C = update(T(As, k, k).copy(), k, k, fp64_update)
+        C = class_update(T(As, k, k).copy(), ops(k, k), fp64_update)
         Lkk, info = tile_cholesky(C, nb)
         if info:
             return Lh, k * nb + info
         T(Lh, k, k)[:] = Lkk
         for m in range(k + 1, Nt):
             p = int(cmap[tile_index(Nt, m, k)])
-            C = update(T(As, m, k).copy(), m, k, fp64_update if p == FP64 else p)
+            C = class_update(T(As, m, k).copy(), ops(m, k), fp64_update if p == FP64 else p)
             X = solve_triangular(Lkk, C.T, lower=True).T  # C L_kk^{-T}
             T(Lh, m, k)[:] = round_tile(X, p)[0]
     return Lh, 0

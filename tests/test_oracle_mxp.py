@@ -8,7 +8,13 @@ IV-C) and its refinement solve.
   below eps, and falls as eps tightens.
 * Refinement with an FP64 factor converges at once; with the mixed factor
   it reaches 1e-9 relative residual and the solution of A x = b.
+* The low classes' update arithmetic: two hand-worked scalar-tile factors
+  pin that operands are rounded to the output tile's class and that the
+  products are summed in FP32; two planted mistakes (binary64 sums,
+  operands in their own stored class) each fail one of them.
 """
+import math
+
 import numpy as np
 import pytest
 
@@ -128,3 +134,124 @@ def test_fp32_update_refines_to_target(mat):
     assert info == 0
     X, it, rel = oracle.refine(A, Lh, B, tol=1e-9)
     assert rel.max() <= 1e-9 and 1 <= it <= 10
+
+
+# --- the low classes' update arithmetic (Section IV-C) ----------------------
+#
+# Two scalar-tile (nb = 1) factors built so that the reading of Section IV-C
+# (operands rounded to the *output* tile's class, products summed in FP32)
+# gives a different stored factor than either plausible alternative
+# (operands kept in their own stored class; sums in binary64). Expected
+# values are worked out by hand below with numpy's own float32 / float16
+# casts, not with the oracle's rounding helpers.
+
+def _accumulation_case():
+    """Nt = 4, nb = 1. L has L20 = L30 = 2^12, L21 = L31 = 1, L32 = 1/2 and a
+    diagonal (1, 1, 1, 2) (L10 = 0; L33 = 2 leaves room for the FP32 error
+    in L32). The update into tile (3, 2) sums the products
+    L30 L20 = 2^24 and L31 L21 = 1: binary64 keeps 2^24 + 1, binary32 rounds
+    the sum to 2^24 (a tie, to even)."""
+    L = np.eye(4)
+    L[2, 0] = L[3, 0] = 2.0 ** 12
+    L[2, 1] = L[3, 1] = 1.0
+    L[3, 2] = 0.5
+    L[3, 3] = 2.0
+    A = L @ L.T  # every entry below 2^53: exact
+    cm = np.full(10, FP32, dtype=np.uint8)
+    for k in range(4):
+        cm[oracle.tile_index(4, k, k)] = FP64
+    return A, cm
+
+
+def _operand_class_case():
+    """Nt = 3, nb = 1. Tiles (1, 0) and (2, 0) are FP32-class and hold
+    1 + 2^-12 (exact in binary32, not in binary16); tile (2, 1) is FP16-class.
+    Its update multiplies the two operands after rounding them to FP16 (to
+    1.0 each), not in their stored binary32 form."""
+    v = 1.0 + 2.0 ** -12
+    L = np.eye(3)
+    L[1, 0] = L[2, 0] = v
+    L[2, 1] = 0.5
+    A = L @ L.T  # entries need at most 26 significant bits: exact
+    cm = np.array([FP64, FP32, FP32, FP64, FP16, FP64], dtype=np.uint8)
+    assert [oracle.tile_index(3, i, j) for (i, j) in ((1, 0), (2, 0), (2, 1))] == [1, 2, 4]
+    return A, cm
+
+
+def pin_fp32_accumulation():
+    A, cm = _accumulation_case()
+    Lh, info = oracle.mxp_tile_cholesky(A, 1, cm)
+    assert info == 0
+    # C = A32 - fl32(fl32(2^24) + fl32(1)) in FP32 arithmetic
+    acc = np.float32(np.float32(2.0 ** 12) * np.float32(2.0 ** 12)) + np.float32(1.0)
+    assert float(acc) == 2.0 ** 24  # the binary32 sum drops the 1
+    c = A[3, 2] - float(acc)
+    expected = float(np.float32(c / 1.0))  # L22 = 1, stored in binary32
+    assert expected == 1.5
+    assert Lh[3, 2] == expected, Lh[3, 2]
+    # the diagonal tiles' SYRK is binary64 (FP64 class), with the stored
+    # L32: L22 = 1 and L33 = sqrt(A33 - 2^24 - 1 - 1.5^2) = sqrt(2)
+    assert Lh[2, 2] == 1.0 and Lh[3, 3] == math.sqrt(2.0)
+
+
+def pin_output_class_operands():
+    A, cm = _operand_class_case()
+    Lh, info = oracle.mxp_tile_cholesky(A, 1, cm)
+    assert info == 0
+    v = 1.0 + 2.0 ** -12
+    assert Lh[1, 0] == v and Lh[2, 0] == v  # FP32 tiles keep the 2^-12 bit
+    q = np.float16(v)  # the operand in the output tile's class
+    assert float(q) == 1.0
+    prod = float(np.float32(q) * np.float32(q))
+    c = A[2, 1] - prod  # = 1/2 + 2^-11 + 2^-24
+    expected = float(np.float16(c / Lh[1, 1]))
+    assert expected == 0.5 + 2.0 ** -11
+    assert Lh[2, 1] == expected, Lh[2, 1]
+
+
+def test_low_class_update_accumulates_in_fp32():
+    pin_fp32_accumulation()
+
+
+def test_low_class_update_rounds_operands_to_output_class():
+    pin_output_class_operands()
+
+
+def _mutant_float64_accumulation(C, ops, q):
+    """Planted mistake: the low classes' products summed in binary64."""
+    if q == FP64:
+        for a, b in ops:
+            C -= a @ b.T
+        return C
+    acc = np.zeros(C.shape)
+    for a, b in ops:
+        acc += oracle.round_tile(a, q)[0] @ oracle.round_tile(b, q)[0].T
+    return C - acc
+
+
+def _mutant_own_class_operands(C, ops, q):
+    """Planted mistake: each operand used in its own stored class (no
+    rounding to the output tile's class), FP32 accumulation kept."""
+    if q == FP64:
+        for a, b in ops:
+            C -= a @ b.T
+        return C
+    acc = np.zeros(C.shape, dtype=np.float32)
+    for a, b in ops:
+        acc += (a.astype(np.float32) @ b.astype(np.float32).T).astype(np.float32)
+    return C - acc.astype(np.float64)
+
+
+@pytest.mark.parametrize("mutant", [_mutant_float64_accumulation, _mutant_own_class_operands])
+def test_pins_catch_planted_update_mistakes(monkeypatch, mutant):
+    """Each planted mistake in the low classes' update arithmetic fails at
+    least one of the two pins above (and the unmutated oracle passes both,
+    see the tests above)."""
+    monkeypatch.setattr(oracle, "class_update", mutant)
+    failed = 0
+    for pin in (pin_fp32_accumulation, pin_output_class_operands):
+        try:
+            pin()
+        except AssertionError:
+            failed += 1
+    assert failed >= 1, mutant.__name__

@@ -333,13 +333,17 @@ def class_update(C: np.ndarray, ops, q: int) -> np.ndarray:
     return C - acc.astype(np.float64)
 
 
-def mxp_tile_cholesky(A: np.ndarray, nb: int, cmap: np.ndarray, fp64_update: int = FP64):
+def mxp_tile_cholesky(A: np.ndarray, nb: int, cmap: np.ndarray, fp64_update: int = FP64,
+                      reverse_sums: bool = False):
     """Mixed-precision left-looking tile Cholesky. Returns (Lh, info): Lh the
     stored factor as binary64 values (each tile exactly representable in
     its class with its scale), info as in tile_cholesky. fp64_update: the
     class whose arithmetic computes the updates into FP64-class tiles and
     the diagonal SYRK (FP64, or FP32 for the variant above). Every update
-    goes through class_update."""
+    goes through class_update. reverse_sums: sum each update's terms from
+    n = k-1 down to 0 instead of upwards -- the reading fixes no order, so
+    the two results differ only by rounding and their difference measures
+    how much of a quantity is rounding-order noise."""
     from scipy.linalg import solve_triangular
     n = A.shape[0]
     Nt = n // nb
@@ -350,7 +354,8 @@ def mxp_tile_cholesky(A: np.ndarray, nb: int, cmap: np.ndarray, fp64_update: int
         return M[i * nb:(i + 1) * nb, j * nb:(j + 1) * nb]
 
     def ops(m, k):
-        return [(T(Lh, m, n2), T(Lh, k, n2)) for n2 in range(k)]
+        order = range(k - 1, -1, -1) if reverse_sums else range(k)
+        return [(T(Lh, m, n2), T(Lh, k, n2)) for n2 in order]
 
     for k in range(Nt):
         C = class_update(T(As, k, k).copy(), ops(k, k), fp64_update)

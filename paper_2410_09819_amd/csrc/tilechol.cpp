@@ -207,6 +207,9 @@ bool make_plan(int64_t n, int nb, const uint8_t* map, Plan& P, int fp64_update) 
         P.toff[t] = (int64_t)off;
         off += align_up(tb * tc::fmt_bytes(P.cls[t]));
     }
+    // no operand copies until a low class needs them (an all-FP64 plan has
+    // none, and the out-of-core mixed path reads this table for it too)
+    P.shoff.assign((size_t)P.ntiles * 4, -1);
     if (!P.mixed) {
         P.total = off;
         return true;
@@ -214,7 +217,6 @@ bool make_plan(int64_t n, int nb, const uint8_t* map, Plan& P, int fp64_update) 
     auto C = [&](int i, int j) { return (int)P.ccls[tc::tile_off(Nt, i, j)]; };
     // compute classes present in each row m left of the diagonal and in each
     // column m on and below it (as bit masks; the diagonal's is the SYRK's)
-    P.shoff.assign((size_t)P.ntiles * 4, -1);
     for (int m = 1; m < Nt; ++m) {
         uint32_t colmask = 0;
         for (int mp = m; mp < Nt; ++mp) colmask |= 1u << C(mp, m);

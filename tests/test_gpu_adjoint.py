@@ -225,7 +225,8 @@ def _lower_matvec(tc, L, z, n, nb):
 
 def test_full_size_gradient_central_differences(tc):
     """The gradient workload: n = 32768, nb = 512, 4000 base points
-    translated, data y = L(theta0) z, gradient at theta_eval."""
+    translated, data y = L(theta0) z, gradient at theta_eval, in binary64
+    and in the FP32-mixed variant."""
     import torch
     w = si.WORKLOADS["grad"]
     n, nb, nu = w["n"], w["nb"], w["nu"]
@@ -260,11 +261,37 @@ def test_full_size_gradient_central_differences(tc):
     torch.cuda.empty_cache()
     print("l =", l0, "grad =", g, "reverse sweep ms =", st.ms_total, flush=True)
     assert np.all(np.isfinite(g))
+    fds = []
     for p in range(3):
         h = 1e-6 * th[p]
         tp, tm = th.copy(), th.copy()
         tp[p] += h
         tm[p] -= h
         fd = (loglik(tp) - loglik(tm)) / (2 * h)
+        fds.append(fd)
         print("p", p, "fd", fd, "adjoint", g[p], flush=True)
         assert abs(fd - g[p]) <= 1e-4 * abs(g[p]), (p, fd, g[p])
+    # the FP32-mixed variant at the same size: {FP64, FP32} map at target
+    # 1e-9 (Section IV-C), the forward factor in mixed precision and the
+    # reverse sweep in binary64 on its upcast tiles; stated bound 1e-4
+    # relative per component against the binary64 gradient and against the
+    # central differences of the binary64 log-likelihood
+    full = (th[0], th[1], nu, th[2])
+    A, tf, fro = tc.matern_tiles(ctx, locs, full, nb)
+    cm = tc.precision_map(n // nb, tf.cpu().numpy(), fro, 1e-9, allowed=(tc.FP64, tc.FP32))
+    n32 = int(np.count_nonzero(cm == tc.FP32))
+    assert n32 > 0
+    Fm = tc.factorize(ctx, A, n, nb, cmap=cm)
+    assert Fm.mixed and Fm.stats.info == 0
+    Lbar = torch.empty_like(A)
+    lm = tc.loglik_seed(ctx, Fm, y, Lbar)
+    tc.factor_adjoint(ctx, Fm, Lbar)
+    gm = tc.matern_grad(ctx, locs, full, nb, Lbar)
+    Fm.close()
+    del A, Lbar
+    torch.cuda.empty_cache()
+    print("FP32-mixed (%d FP32 tiles): l = %r grad = %r" % (n32, lm, gm), flush=True)
+    assert abs(lm - l0) <= 1e-6 * abs(l0), (lm, l0)
+    for p in range(3):
+        assert abs(gm[p] - g[p]) <= 1e-4 * abs(g[p]), (p, gm[p], g[p])
+        assert abs(gm[p] - fds[p]) <= 1e-4 * abs(fds[p]), (p, gm[p], fds[p])

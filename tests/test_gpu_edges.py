@@ -137,3 +137,40 @@ def test_zero_right_hand_sides(tc):
     F = tc.factorize(ctx, to_dev(tc.pack_lower(A, nb)), n, nb)
     B = torch.empty((0, n), dtype=torch.float64, device="cuda")
     tc.solve(ctx, F, B)  # nothing to do, no error
+
+
+@pytest.mark.parametrize("n,nb,upd", [(128, 128, 0), (256, 128, 0), (256, 128, 1)])
+def test_ooc_mixed_all_fp64_map(tc, n, nb, upd):
+    """The mixed out-of-core path with a map that has no low-precision tile
+    (one and two tile columns, the minimal 2 Nt-slot cache): with binary64
+    updates the factor is an all-FP64 factor, the host image holds binary64
+    tiles on 256-byte boundaries followed by zero scale exponents, and the
+    factor matches the oracle's like the in-core FP64 path; with FP32-class
+    updates (upd = 1) it matches the oracle's emulation of that variant."""
+    import torch
+    _, A = matern(n)
+    Nt = n // nb
+    ntiles = Nt * (Nt + 1) // 2
+    cm = np.zeros(ntiles, dtype=np.uint8)
+    assert tc.ooc_mixed_host_bytes(n, nb, cm) == ntiles * nb * nb * 8 + (4 * ntiles + 255) // 256 * 256
+    Ah = torch.empty(ntiles * nb * nb, dtype=torch.float64, pin_memory=True)
+    Ah.copy_(torch.from_numpy(tc.pack_lower(A, nb)))
+    ctx = tc.Context(n, nb)
+    cache = torch.empty(tc.ooc_mixed_cache_bytes(n, nb, cm, 2 * Nt, fp64_update=upd),
+                        dtype=torch.uint8, device="cuda")
+    st, img = tc.factorize_ooc_mixed(ctx, Ah, n, nb, cm, cache, fp64_update=upd)
+    assert st["info"] == 0
+    raw = img.numpy()
+    tiles = raw[:ntiles * nb * nb * 8].view(np.float64)
+    assert np.all(raw[ntiles * nb * nb * 8:][:4 * ntiles].view(np.int32) == 0)
+    L = np.tril(tc.unpack_lower(tiles, n, nb))
+    assert st["bytes_d2h"] == ntiles * nb * nb * 8
+    if upd == 0:
+        Lo, info = oracle.tile_cholesky(A, nb)
+        assert info == 0
+        assert np.linalg.norm(L - Lo) <= 4 * np.linalg.cond(A) * n * U * np.linalg.norm(Lo)
+    else:
+        Lo, info = oracle.mxp_tile_cholesky(A, nb, cm, fp64_update=oracle.FP32)
+        assert info == 0
+        be_g, be_o = oracle.backward_error(A, L), oracle.backward_error(A, Lo)
+        assert be_g <= 10 * be_o + 1e-15, (be_g, be_o)

@@ -158,3 +158,84 @@ def test_ooc_lru_eviction(tc, case, slots):
                                                      res[True][1]["tiles_reloaded"]))
     assert np.array_equal(res[True][0], res[False][0])
     assert res[True][1]["tiles_reloaded"] >= res[False][1]["tiles_reloaded"]
+
+
+@pytest.fixture(scope="module")
+def big_tiles():
+    """The out-of-core workload's tile size (nb = 2048) at n = 12288 (Nt = 6):
+    the peak working set is 13 tiles, so the minimal 2 Nt = 12-slot cache
+    must evict and reload, and a 32-slot cache holds every column's set."""
+    n, nb = 12288, 2048
+    w = si.WORKLOADS["ooc"]
+    return dict(n=n, nb=nb, w=w, pts=si.points(n, seed=w["seed"]))
+
+
+@pytest.mark.parametrize("slots", [12, 32])
+def test_ooc_nb2048_exact_integer_factor(tc, big_tiles, slots):
+    """A = L0 L0^T with a dense small-integer L0 (entries in {-1, 0, 1}
+    below a diagonal from {1, 2, 4}): every partial sum is an integer below
+    2^53, so any summation order is exact and the factor must be L0 bit for
+    bit -- the result the oracle's own exact-integer pin reproduces for any
+    tiling. A is formed on the device in binary64 (exact for the same
+    reason)."""
+    import torch
+    n, nb = big_tiles["n"], big_tiles["nb"]
+    Nt = n // nb
+    L0 = si.integer_factor(n, seed=29, band=n - 1)
+    L0d = torch.from_numpy(L0).cuda()
+    Ad = (L0d @ L0d.t()).cpu().numpy()
+    del L0d
+    Ah = pinned(tc.pack_lower(Ad, nb))
+    ctx = tc.Context(n, nb)
+    cache = torch.empty(slots * nb * nb * 8, dtype=torch.uint8, device="cuda")
+    st = tc.factorize_ooc(ctx, Ah, n, nb, cache)
+    assert st["info"] == 0 and st["cache_slots"] == slots
+    ntiles = Nt * (Nt + 1) // 2
+    tbytes = nb * nb * 8
+    assert st["bytes_d2h"] == ntiles * tbytes
+    if slots == 2 * Nt:
+        assert st["evictions"] > 0 and st["tiles_reloaded"] > 0
+    else:
+        assert st["tiles_reloaded"] == 0 and st["bytes_h2d"] == ntiles * tbytes
+    assert st["bytes_h2d"] == (ntiles + st["tiles_reloaded"]) * tbytes
+    L = np.tril(tc.unpack_lower(Ah.numpy(), n, nb))
+    assert np.array_equal(L, L0)
+
+
+@pytest.mark.parametrize("slots", [12, 32])
+def test_ooc_nb2048_matern_rows(tc, big_tiles, slots):
+    """The out-of-core workload's covariance (nu = 1, range 0.05, nugget
+    1e-4) at nb = 2048: 24 sampled rows of the factor satisfy the
+    componentwise backward-error bound |A - L L^T|_ij <= gamma_{n+1}
+    (|L| |L|^T)_ij against covariance entries computed by the oracle, and
+    the factor agrees with the in-core factor within the perturbation bound
+    (the out-of-core update is summed in chunks of tile columns): both are
+    exact factors of matrices within gamma_{n+1} of A, and kappa(A) <=
+    ||A||_F / nugget (the Matern part is positive semidefinite)."""
+    import torch
+    n, nb, w, pts = big_tiles["n"], big_tiles["nb"], big_tiles["w"], big_tiles["pts"]
+    theta = (w["sigma2"], w["range"], w["nu"], w["nugget"])
+    ctx = tc.Context(n, nb)
+    Ad, _, fro = tc.matern_tiles(ctx, torch.from_numpy(pts).cuda(), theta, nb)
+    Ah = torch.empty(Ad.numel(), dtype=torch.float64, pin_memory=True)
+    Ah.copy_(Ad)
+    Lin = tc.unpack_lower(tc.export(ctx, tc.factorize(ctx, Ad, n, nb)).cpu().numpy(), n, nb)
+    del Ad
+    cache = torch.empty(slots * nb * nb * 8, dtype=torch.uint8, device="cuda")
+    st = tc.factorize_ooc(ctx, Ah, n, nb, cache)
+    assert st["info"] == 0
+    L = np.tril(tc.unpack_lower(Ah.numpy(), n, nb))
+    rows = np.unique(np.concatenate([np.arange(0, n, n // 16),
+                                     np.random.default_rng(41).integers(0, n, 8), [n - 1]]))
+    g = (n + 1) * U / (1 - (n + 1) * U)
+    absL = np.abs(L)
+    for i in rows:
+        J = np.arange(i + 1)
+        a = oracle.matern_entries(pts, np.full(i + 1, i), J, *theta)
+        r = a - L[i, :i + 1] @ L[:i + 1, :i + 1].T
+        bound = g * (absL[i, :i + 1] @ absL[:i + 1, :i + 1].T)
+        assert np.all(np.abs(r) <= bound), (i, float(np.max(np.abs(r) / bound)))
+    be = np.linalg.norm(L - Lin) / np.linalg.norm(Lin)
+    print("slots %d: |L_ooc - L_in| / |L_in| = %.2e, reloads %d" % (slots, be, st["tiles_reloaded"]))
+    kappa_max = fro / theta[3]
+    assert be <= 4 * kappa_max * n * U, (be, kappa_max)

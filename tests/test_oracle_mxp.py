@@ -106,9 +106,10 @@ def test_fp32_update_exact_on_integer_factor():
     for cm in (np.zeros(Nt * (Nt + 1) // 2, dtype=np.uint8),
                np.array([FP32 if i != j else FP64 for j in range(Nt) for i in range(j, Nt)],
                         dtype=np.uint8)):
-        Lh, info = oracle.mxp_tile_cholesky(A, nb, cm, fp64_update=FP32)
-        assert info == 0
-        assert np.array_equal(Lh, L0)
+        for rev in (False, True):  # either summation order is exact here
+            Lh, info = oracle.mxp_tile_cholesky(A, nb, cm, fp64_update=FP32, reverse_sums=rev)
+            assert info == 0
+            assert np.array_equal(Lh, L0)
 
 
 def test_fp32_update_rounds_like_fp32(mat):

@@ -47,20 +47,63 @@ def panel_traffic():
 METRIC = "Cholesky TFLOP/s (n^3/3) + % peak, MxP vs FP64 at stated backward error"
 
 
-def cpu_baseline(w, ns=4096):
-    import numpy as np
+_CPU_SAMPLE = r"""
+import json, sys, time
+sys.path.insert(0, sys.argv[1])
+import oracle
+import seeded_inputs as si
+w = json.loads(sys.argv[2]); ns = int(sys.argv[3]); threads = int(sys.argv[4])
+pts = si.points(w["n"], seed=w["seed"])[:ns]
+A = oracle.matern_matrix(pts, w["sigma2"], w["range"], w["nu"], w["nugget"])
+t0 = time.perf_counter()
+_, info = oracle.tile_cholesky(A, w["nb"], threads=threads)
+print(json.dumps({"seconds": time.perf_counter() - t0, "info": int(info)}))
+"""
 
-    import oracle
-    import seeded_inputs as si
-    pts = si.points(w["n"], seed=w["seed"])[:ns]
-    A = oracle.matern_matrix(pts, w["sigma2"], w["range"], w["nu"], w["nugget"])
-    threads = min(16, os.cpu_count() or 1)
-    t0 = time.perf_counter()
-    _, info = oracle.tile_cholesky(A, w["nb"], threads=threads)
-    dt = time.perf_counter() - t0
-    assert info == 0
+
+def host_cpu():
+    """CPU model, sockets and physical cores of the host (lscpu), and the
+    CPUs this process may run on."""
+    import subprocess
+    info = {"model": None, "sockets": None, "physical_cores": None,
+            "cpus_allowed": len(os.sched_getaffinity(0))}
+    try:
+        txt = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=30).stdout
+        kv = {}
+        for line in txt.splitlines():
+            if ":" in line:
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+        info["model"] = kv.get("Model name")
+        sockets = int(kv.get("Socket(s)", "0") or 0)
+        per = int(kv.get("Core(s) per socket", "0") or 0)
+        info["sockets"] = sockets or None
+        info["physical_cores"] = sockets * per or None
+    except (OSError, ValueError, subprocess.SubprocessError):
+        pass
+    return info
+
+
+def cpu_baseline(w, ns=4096):
+    """The CPU oracle (OpenMP over the tiles of a column) on a bounded sample
+    of the same workload, in a child process with one thread per allowed
+    CPU (the OMP_NUM_THREADS share when it is set), bound one per core."""
+    import subprocess
+    cpu = host_cpu()
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or cpu["cpus_allowed"]
+    threads = max(1, min(threads, cpu["cpus_allowed"]))
+    env = dict(os.environ, OMP_NUM_THREADS=str(threads), OMP_PLACES="cores", OMP_PROC_BIND="close")
+    r = subprocess.run([sys.executable, "-c", _CPU_SAMPLE, ROOT, json.dumps(w), str(ns), str(threads)],
+                       env=env, capture_output=True, text=True, timeout=900)
+    if r.returncode != 0:
+        raise RuntimeError("cpu baseline failed:\n" + r.stderr[-2000:])
+    res = json.loads(r.stdout.strip().splitlines()[-1])
+    assert res["info"] == 0
+    dt = res["seconds"]
     return {"value": ns ** 3 / 3.0 / dt / 1e12, "unit": "TFLOP/s", "cores": threads,
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": cpu["model"], "sockets": cpu["sockets"],
+            "physical_cores_host": cpu["physical_cores"], "cpus_allowed": cpu["cpus_allowed"],
+            "binding": "OMP_PLACES=cores OMP_PROC_BIND=close",
             "sample": "leading %dx%d principal block of the same matrix, nb=%d, factorization only "
                       "(%.1f s)" % (ns, ns, w["nb"], dt)}
 
@@ -69,11 +112,83 @@ def progress(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
-def mxp_comparison(tc, si, dev, n=None, eps=None, extra_eps=(1e-7, 1e-6)):
+# Dense peaks of the arithmetic each class's updates execute (TFLOP/s): the
+# FP32 class runs as three FP16 MFMA products per binary32 product.
+CLASS_PEAK_TFLOPS = {"fp64": 78.6, "fp32": 2500.0 / 3.0, "fp16": 2500.0, "bf16": 2500.0,
+                     "fp8": 5000.0}
+CLASS_NAMES = ("fp64", "fp32", "fp16", "bf16", "fp8")
+
+
+def map_roofline(n, class_flops, factor_ms):
+    """Map-weighted roofline of a mixed factorization: t* = sum_p F_p / peak_p
+    over the update flops F_p executed in each class, plus the POTRF / TRSM
+    remainder of n^3/3 at the FP64 peak; frac = t* / measured time."""
+    upd = sum(class_flops)
+    t_star = (n ** 3 / 3.0 - upd) / (CLASS_PEAK_TFLOPS["fp64"] * 1e12)
+    for name, f in zip(CLASS_NAMES, class_flops):
+        t_star += f / (CLASS_PEAK_TFLOPS[name] * 1e12)
+    return {"t_star_s": t_star, "factor_s": factor_ms * 1e-3, "frac": t_star / (factor_ms * 1e-3),
+            "class_peaks_tflops": CLASS_PEAK_TFLOPS}
+
+
+def _tiles_t_times(T, n, nb, G, diag=True):
+    """U_j = sum_{i >= j} T_ij^T G_i over the packed lower tiles T (tile (i, j)
+    column-major); diag=False leaves out the diagonal tiles."""
+    import torch
+    Nt, nb2, p = n // nb, nb * nb, G.shape[1]
+    out = torch.zeros_like(G)
+    t = 0
+    for j in range(Nt):
+        cnt = Nt - j
+        col = T[t * nb2:(t + cnt) * nb2].view(cnt, nb, nb)  # col[s] = T_{j+s, j}^T
+        s0 = 0 if diag else 1
+        if cnt > s0:
+            Gs = G[(j + s0) * nb:].view(cnt - s0, nb, p)
+            out[j * nb:(j + 1) * nb] += torch.matmul(col[s0:], Gs).sum(0)
+        t += cnt
+    return out
+
+
+def _tiles_times(T, n, nb, U):
+    """V_i = sum_{j <= i} T_ij U_j over the packed lower tiles T (diagonal
+    tiles used as stored, in full)."""
+    import torch
+    Nt, nb2, p = n // nb, nb * nb, U.shape[1]
+    out = torch.zeros_like(U)
+    t = 0
+    for j in range(Nt):
+        cnt = Nt - j
+        col = T[t * nb2:(t + cnt) * nb2].view(cnt, nb, nb)
+        Ut = U[j * nb:(j + 1) * nb].t().contiguous().unsqueeze(0).expand(cnt, p, nb).contiguous()
+        prod = torch.matmul(Ut, col)  # U_j^T T_ij^T = (T_ij U_j)^T
+        out[j * nb:] += prod.transpose(1, 2).reshape(cnt * nb, p)
+        t += cnt
+    return out
+
+
+def probe_backward_error(A, L64, n, nb, nprobe=32, seed=97):
+    """||(A - L L^T) G||_F / ||A G||_F for nprobe seeded N(0,1) columns G.
+    A: packed lower tiles of the symmetric matrix (diagonal tiles in full);
+    L64: packed lower binary64 tiles of the factor, strict upper parts of
+    the diagonal tiles zero. A check outside the timed region, in torch
+    binary64 products over the tile columns."""
+    import torch
+    gen = torch.Generator(device="cpu").manual_seed(seed)
+    G = torch.randn(n, nprobe, generator=gen, dtype=torch.float64).to(A.device)
+    AG = _tiles_times(A, n, nb, G) + _tiles_t_times(A, n, nb, G, diag=False)
+    LLG = _tiles_times(L64, n, nb, _tiles_t_times(L64, n, nb, G))
+    return float(torch.linalg.norm(AG - LLG) / torch.linalg.norm(AG))
+
+
+def mxp_comparison(tc, si, dev, n=None, eps=None, extra_eps=(1e-7, 1e-6), repeats=2, warmup=1,
+                   probes=True):
     """Time-to-solution at n=131072: FP64 = factorization + 16-RHS solve;
     mixed precision = tile norms already known from generation, precision
     map + factorization + refined 16-RHS solve to 1e-9. Same matrix, same
-    right-hand sides, matrix resident in HBM. eps overrides the map's
+    right-hand sides, matrix resident in HBM. Each variant runs `warmup`
+    untimed times and `repeats` timed times (the reported time is their
+    mean). After the timed runs, the probe backward error of the variant's
+    factor is measured outside the timed region. eps overrides the map's
     target accuracy (default: the mxp workload's 1e-9); the refinement
     target stays 1e-9. extra_eps: further maps, timed the same way and
     refined to the same 1e-9 residual (reported separately)."""
@@ -92,86 +207,98 @@ def mxp_comparison(tc, si, dev, n=None, eps=None, extra_eps=(1e-7, 1e-6)):
         si.standard_normal((n, nrhs), seed=si.rhs_seed(w["seed"])).T)).to(dev)
     B = torch.empty_like(B0)
     Nt = n // nb
+    flops = n ** 3 / 3.0
     out = {"workload": "mxp tile Cholesky, n=%d nb=%d, Matern nu=%g range=%g nugget=%g, target %g, "
-                       "%d RHS refined to 1e-9" % (n, nb, w["nu"], w["range"], w["nugget"], w["eps"], nrhs)}
+                       "%d RHS refined to 1e-9" % (n, nb, w["nu"], w["range"], w["nugget"], w["eps"], nrhs),
+           "timing": "%d untimed + %d timed runs per variant, mean of the timed" % (warmup, repeats),
+           "probe_backward_error": "||(A - L L^T) G||_F / ||A G||_F, 32 seeded N(0,1) probe columns, "
+                                   "factor upcast to binary64, outside the timed region"}
+
+    def runs(once):
+        """warmup + repeats calls of once() -> (mean seconds, times, last result)"""
+        for _ in range(warmup):
+            r = once()
+            r[0].close()
+            del r
+        ts, last = [], None
+        for i in range(repeats):
+            if last is not None:
+                last[0].close()
+                last = None
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            last = once()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        return sum(ts) / len(ts), ts, last
+
     # FP64 path
     storage = torch.empty(tc.factor_bytes(n, nb) // 8, dtype=torch.float64, device=dev)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    F = tc.factorize(ctx, A, n, nb, storage=storage)
-    B.copy_(B0)
-    tc.solve(ctx, F, B)
-    torch.cuda.synchronize()
-    t_fp64 = time.perf_counter() - t0
-    ms_f64 = F.stats.ms_total
-    progress("mxp comparison: FP64 factor + solve %.2f s" % t_fp64)
-    F.close()
-    del storage, F
-    torch.cuda.empty_cache()
-    # mixed precision
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    cm = tc.precision_map(Nt, tf_h, fro, w["eps"])
-    storage = torch.empty(tc.factor_bytes(n, nb, cm) // 8, dtype=torch.float64, device=dev)
-    F = tc.factorize(ctx, A, n, nb, cmap=cm, storage=storage)
-    B.copy_(B0)
-    st = tc.solve_refine(ctx, F, A, B, max_iter=30, tol=1e-9)
-    torch.cuda.synchronize()
-    t_mxp = time.perf_counter() - t0
-    progress("mxp comparison: mixed map + factor + refined solve %.2f s" % t_mxp)
-    flops = n ** 3 / 3.0
-    cls = list(F.stats.class_tiles)
-    cf = list(F.stats.class_flops)
-    out.update({
-        "fp64_time_to_solution_s": t_fp64,
-        "fp64_factor_ms": ms_f64,
-        "fp64_tflops": flops / (ms_f64 * 1e-3) / 1e12,
-        "mxp_time_to_solution_s": t_mxp,
-        "mxp_factor_ms": F.stats.ms_total,
-        "mxp_tflops_fp64_equivalent": flops / (F.stats.ms_total * 1e-3) / 1e12,
-        "speedup_time_to_solution": t_fp64 / t_mxp,
-        "ir_iterations": st["iterations"],
-        "ir_rel_residual": st["rel_residual"],
-        "ir_ms": st["ms_total"],
-        "class_tiles": dict(zip(["fp64", "fp32", "fp16", "bf16", "fp8"], cls)),
-        "class_flop_share": dict(zip(["fp64", "fp32", "fp16", "bf16", "fp8"],
-                                     [c / max(sum(cf), 1.0) for c in cf])),
-    })
-    F.close()
-    del storage, F
-    torch.cuda.empty_cache()
-    def timed(e2, fp64_update, label):
-        """map at e2 + factorization + refined solve to 1e-9, timed"""
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        cm = tc.precision_map(Nt, tf_h, fro, e2)
-        storage = torch.empty(tc.factor_bytes(n, nb, cm, fp64_update) // 8, dtype=torch.float64,
-                              device=dev)
-        F = tc.factorize(ctx, A, n, nb, cmap=cm, storage=storage, fp64_update=fp64_update)
+
+    def fp64_once():
+        F = tc.factorize(ctx, A, n, nb, storage=storage)
         B.copy_(B0)
-        st = tc.solve_refine(ctx, F, A, B, max_iter=30, tol=1e-9)
-        torch.cuda.synchronize()
-        t2 = time.perf_counter() - t0
-        progress("mxp comparison: %s, refined to 1e-9: %.2f s" % (label, t2))
+        tc.solve(ctx, F, B)
+        return (F,)
+
+    t_fp64, ts, (F,) = runs(fp64_once)
+    ms_f64 = F.stats.ms_total
+    progress("mxp comparison: FP64 factor + solve %s s" % ["%.2f" % t for t in ts])
+    if probes:
+        tc.export(ctx, F, out=storage)  # in place: zero strict upper parts
+        out["fp64_probe_backward_error"] = probe_backward_error(A, storage, n, nb)
+    F.close()
+    del storage, F
+    torch.cuda.empty_cache()
+    out.update({"fp64_time_to_solution_s": t_fp64, "fp64_times_s": ts, "fp64_factor_ms": ms_f64,
+                "fp64_tflops": flops / (ms_f64 * 1e-3) / 1e12})
+
+    def mixed(e2, fp64_update, label):
+        """map at e2 + factorization + refined solve to 1e-9, timed"""
+        holder = {}
+
+        def once():
+            holder.pop("storage", None)
+            cm = tc.precision_map(Nt, tf_h, fro, e2)
+            holder["storage"] = storage = torch.empty(
+                tc.factor_bytes(n, nb, cm, fp64_update) // 8, dtype=torch.float64, device=dev)
+            F = tc.factorize(ctx, A, n, nb, cmap=cm, storage=storage, fp64_update=fp64_update)
+            B.copy_(B0)
+            st = tc.solve_refine(ctx, F, A, B, max_iter=30, tol=1e-9)
+            return F, st
+
+        t2, ts, (F, st) = runs(once)
+        progress("mxp comparison: %s, refined to 1e-9: %s s" % (label, ["%.2f" % t for t in ts]))
         cf = list(F.stats.class_flops)
-        r = {"map_eps": e2, "mxp_time_to_solution_s": t2, "mxp_factor_ms": F.stats.ms_total,
+        r = {"map_eps": e2, "fp64_update": "fp64" if fp64_update == tc.FP64 else "fp32",
+             "mxp_time_to_solution_s": t2, "mxp_times_s": ts, "mxp_factor_ms": F.stats.ms_total,
              "mxp_tflops_fp64_equivalent": flops / (F.stats.ms_total * 1e-3) / 1e12,
              "speedup_time_to_solution": t_fp64 / t2, "ir_iterations": st["iterations"],
              "ir_rel_residual": st["rel_residual"], "converged": st["converged"],
              "ir_ms": st["ms_total"],
-             "class_flop_share": dict(zip(["fp64", "fp32", "fp16", "bf16", "fp8"],
-                                           [c / max(sum(cf), 1.0) for c in cf]))}
+             "class_tiles": dict(zip(CLASS_NAMES, list(F.stats.class_tiles))),
+             "class_flop_share": dict(zip(CLASS_NAMES, [c / max(sum(cf), 1.0) for c in cf])),
+             "map_roofline": map_roofline(n, cf, F.stats.ms_total)}
+        if probes:
+            L64 = torch.empty_like(A)
+            tc.export(ctx, F, out=L64)
+            r["probe_backward_error"] = probe_backward_error(A, L64, n, nb)
+            del L64
         F.close()
-        del storage, F
+        del F
+        holder.clear()
         torch.cuda.empty_cache()
         return r
 
+    # the paper's four-precision scheme: binary64 updates into FP64 tiles
+    out.update(mixed(w["eps"], tc.FP64, "mixed map, binary64 updates into FP64 tiles"))
+    out["roofline_frac"] = out["map_roofline"]["frac"]
     # the same map with the updates into its FP64 tiles (diagonal SYRK
     # included) in the FP32 class's arithmetic: binary64 arithmetic only in
     # POTRF, TRSM and the refinement residuals
-    out["fp32_updates_same_map"] = timed(w["eps"], tc.FP32, "same map, FP32 updates into FP64 tiles")
+    out["fp32_updates_same_map"] = mixed(w["eps"], tc.FP32, "same map, FP32 updates into FP64 tiles")
     # the same refined-solve target (1e-9) reached from looser maps
-    out["looser_maps_same_residual_target"] = [timed(e2, tc.FP64, "map at %g" % e2)
+    out["looser_maps_same_residual_target"] = [mixed(e2, tc.FP64, "map at %g" % e2)
                                                for e2 in extra_eps]
     del A
     torch.cuda.empty_cache()
@@ -719,6 +846,11 @@ def main():
         },
         "cpu_baseline": None,
     }
+    tc.export(ctx, F, out=storage)  # the factor in place, strict upper parts zero
+    out["backward_error"] = {
+        "probe": probe_backward_error(A, storage, n, nb), "bound": 1e-12,
+        "definition": "||(A - L L^T) G||_F / ||A G||_F, 32 seeded N(0,1) probe columns, "
+                      "last timed step's factor, outside the timed region"}
     F.close()
     del storage, A, F
     torch.cuda.empty_cache()

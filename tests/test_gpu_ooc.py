@@ -162,15 +162,18 @@ def test_ooc_lru_eviction(tc, case, slots):
 
 @pytest.fixture(scope="module")
 def big_tiles():
-    """The out-of-core workload's tile size (nb = 2048) at n = 12288 (Nt = 6):
-    the peak working set is 13 tiles, so the minimal 2 Nt = 12-slot cache
-    must evict and reload, and a 32-slot cache holds every column's set."""
-    n, nb = 12288, 2048
+    """The out-of-core workload's tile size (nb = 2048) at n = 20480 (Nt = 10).
+    The cache holds finished factor tiles only (the working columns live in
+    the context workspace): during column k the live tiles are (r, n) with
+    r >= k > n, (Nt - k) k of them, 25 at k = 5. So the minimal 2 Nt =
+    20-slot cache must evict and reload, and a 32-slot cache holds every
+    column's set (after column k, (Nt - k - 1)(k + 1) <= 30 tiles)."""
+    n, nb = 20480, 2048
     w = si.WORKLOADS["ooc"]
     return dict(n=n, nb=nb, w=w, pts=si.points(n, seed=w["seed"]))
 
 
-@pytest.mark.parametrize("slots", [12, 32])
+@pytest.mark.parametrize("slots", [20, 32])
 def test_ooc_nb2048_exact_integer_factor(tc, big_tiles, slots):
     """A = L0 L0^T with a dense small-integer L0 (entries in {-1, 0, 1}
     below a diagonal from {1, 2, 4}): every partial sum is an integer below
@@ -202,7 +205,7 @@ def test_ooc_nb2048_exact_integer_factor(tc, big_tiles, slots):
     assert np.array_equal(L, L0)
 
 
-@pytest.mark.parametrize("slots", [12, 32])
+@pytest.mark.parametrize("slots", [20, 32])
 def test_ooc_nb2048_matern_rows(tc, big_tiles, slots):
     """The out-of-core workload's covariance (nu = 1, range 0.05, nugget
     1e-4) at nb = 2048: 24 sampled rows of the factor satisfy the

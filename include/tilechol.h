@@ -369,6 +369,32 @@ tc_status tc_factor_adjoint(tc_ctx *ctx, const tc_factor *L, double *Lbar, void 
 tc_status tc_matern_grad(tc_ctx *ctx, int64_t n, int32_t nb, const double *locs,
                          const tc_matern *th, const double *Abar, double grad[3]);
 
+/* ---- Factorization without device allocation --------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc. The FP64
+ * factorization of tc_factorize (NULL map, default opts) with its scratch
+ * (failure flag, split-K partial sums of the panel updates and of the
+ * in-tile POTRF) in one fixed device array of TC_NOALLOC_SCRATCH_BYTES per
+ * GPU, which the library holds from the first context on that GPU until the
+ * process ends; the context's workspace is not used. Every column runs in
+ * Algorithm 1's order on the context's compute stream (no lookahead stream,
+ * no events); when the partial sums of a late column's split-K would not
+ * fit, fewer splits are used, so any n, nb that tc_factorize accepts is
+ * accepted (TC_ENOMEM if a tile size ever needed more in-tile scratch than
+ * the array holds). Calls no allocating routine on the device or host
+ * (except to format an error message).
+ * A: device packed lower tiles (n, nb), binary64, read (may equal L).
+ * L: device packed lower tiles receiving the factor (diagonal tiles' strict
+ *    upper triangles undefined, as with tc_factorize).
+ * info: host, receives 0 or LAPACK's info (also returned).
+ * All calls on one GPU share its array, which keeps the last call's
+ * contents (the failure flag is cleared at the start of each call): calls
+ * that overlap on one GPU, from any thread or stream, race and must not be
+ * made. Returns after the factorization has completed. */
+#define TC_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+tc_status tc_factorize_noalloc(tc_ctx *ctx, int64_t n, int32_t nb, const double *A, double *L,
+                               int32_t *info);
+
 /* Free the handle (not the caller's storage). NULL is accepted. */
 tc_status tc_factor_destroy(tc_factor *L);
 

@@ -121,6 +121,7 @@ def lib():
         "tc_ooc_mixed_cache_bytes": (_sz, [_i64, _i32, _vp, _i64, ctypes.POINTER(Opts)]),
         "tc_factorize_ooc_mixed": (_i32, [_vp, _i64, _i32, _vp, _vp, _vp, _sz, _vp, _sz,
                                           ctypes.POINTER(Opts), ctypes.POINTER(OocStats)]),
+        "tc_factorize_noalloc": (_i32, [_vp, _i64, _i32, _vp, _vp, ctypes.POINTER(_i32)]),
         "tc_factor_export": (_i32, [_vp, _vp, _vp]),
         "tc_factor_destroy": (_i32, [_vp]),
         "tc_loglik_seed": (_i32, [_vp, _vp, _vp, _vp, ctypes.POINTER(ctypes.c_double)]),
@@ -313,6 +314,19 @@ def factorize(ctx: Context, A, n: int, nb: int, cmap=None, inplace: bool = False
             F.close()
         _check(status)
     return F
+
+
+def factorize_noalloc(ctx: Context, A, n: int, nb: int, out) -> int:
+    """FP64 factorization of the packed lower tiles A (device float64) into
+    `out` (device float64 of A's size; may be A) with the library's fixed
+    per-GPU scratch instead of the context workspace (no device allocation).
+    Returns 0; raises NotPositiveDefinite like factorize."""
+    Nt = n // nb if nb > 0 else 0
+    assert out.numel() >= Nt * (Nt + 1) // 2 * nb * nb and out.dtype == A.dtype
+    info = _i32(0)
+    _check(lib().tc_factorize_noalloc(ctx.handle, n, nb, A.data_ptr(), out.data_ptr(),
+                                      ctypes.byref(info)))
+    return info.value
 
 
 def solve(ctx: Context, F: Factor, B):

@@ -14,7 +14,7 @@ LIBDIR = os.path.join(HERE, "lib")
 LIB = os.path.join(LIBDIR, "libtilechol.so")
 SOURCES = ["tilechol.cpp", "matern.hip", "gemm_f64.hip", "trsm_f64.hip", "potrf.hip", "solve.hip",
            "mxp.hip", "ir.hip", "ooc.hip", "ooc_host.cpp", "ooc_mixed_host.cpp", "adjoint.hip",
-           "adjoint_host.cpp"]
+           "adjoint_host.cpp", "noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -58,8 +58,9 @@ hipError_t launch_panel_reduce(hipStream_t s, double* L, int Nt, int nb, int k, 
                                const double* partial);
 // Number of workgroups of one panel launch (before split-K).
 int64_t panel_blocks(int Nt, int nb, int k);
-// Split count for column k's update over ncols tile columns.
-int panel_splits(int Nt, int nb, int k, int ncols);
+// Split count for column k's update over ncols tile columns, with the
+// partial sums held to cap_bytes.
+int panel_splits(int Nt, int nb, int k, int ncols, size_t cap_bytes = (size_t)512 << 20);
 
 // In-tile update for the recursive POTRF (column-major sub-blocks, ld):
 //   C (m x m, lower blocks) -= A A^T, A is m x kdim.

@@ -211,18 +211,18 @@ int64_t panel_blocks(int Nt, int nb, int k) {
 }
 
 // Split K for columns whose panel has few output blocks. Each split keeps
-// >= 512 of K and the partial sums stay under 512 MiB. The count minimises
+// >= 512 of K and the partial sums stay under cap_bytes. The count minimises
 // an estimate of the column's time: rounds of 512 resident workgroups
 // (2 per CU) times one workgroup's K/S share at the FP64 MFMA rate, plus
 // writing and re-reading the partial sums at HBM speed; fewer splits win
 // unless clearly faster.
-int panel_splits(int Nt, int nb, int k, int ncols) {
+int panel_splits(int Nt, int nb, int k, int ncols, size_t cap_bytes) {
     const int64_t W = panel_blocks(Nt, nb, k);
     const int64_t K = (int64_t)ncols * nb;
     const double panel_bytes = (double)(Nt - k) * nb * nb * sizeof(double);
     int64_t smax = K / 512;
     if (smax > 32) smax = 32;
-    while (smax > 1 && smax * panel_bytes > 512.0 * 1024 * 1024) --smax;
+    while (smax > 1 && smax * panel_bytes > (double)cap_bytes) --smax;
     if (smax < 1) return 1;
     const int64_t slots = 512;
     const double slot_flops = 78.6e12 / slots;

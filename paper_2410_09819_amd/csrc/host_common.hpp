@@ -106,8 +106,12 @@ void class_lists(const Plan& P, std::vector<int>& lists, std::vector<int>& count
 tc::TileView factor_view(const tc_factor* F);
 // POTRF of the s x s block at offset o of a diagonal tile (leading dim nb),
 // recursive halving down to 128 x 128 leaves; failures set *info.
-tc_status potrf_rec(tc_ctx* ctx, double* T, int nb, int o, int s, int64_t col0, int* info,
+tc_status potrf_rec(hipStream_t st, double* T, int nb, int o, int s, int64_t col0, int* info,
                     double* big);
+
+// Device address of `device`'s fixed scratch array of tc_factorize_noalloc,
+// taken once per device with the device current (context creation).
+tc_status noalloc_scratch_init(int device);
 
 struct DeviceGuard {
     int prev = -1;

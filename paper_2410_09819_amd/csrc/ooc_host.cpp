@@ -251,7 +251,7 @@ extern "C" tc_status tc_factorize_ooc(tc_ctx* ctx, int64_t n, int32_t nb, const 
                 st.chunks++;
             }
         }
-        if (tc_status s = potrf_rec(ctx, W, nb, 0, nb, (int64_t)k * nb, d_info, pot)) return s;
+        if (tc_status s = potrf_rec(ctx->stream, W, nb, 0, nb, (int64_t)k * nb, d_info, pot)) return s;
         if (rows > 1) TC_HIP(tc::launch_trsm(cs, W + nb2, W, nb, (int64_t)(rows - 1) * nb, nb));
         if (no_reuse) {  // every operand tile is loaded again in the next column
             std::vector<std::pair<int, int>> all(cached.begin(), cached.end());

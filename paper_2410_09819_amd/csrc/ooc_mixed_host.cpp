@@ -413,7 +413,7 @@ extern "C" tc_status tc_factorize_ooc_mixed(tc_ctx* ctx, int64_t n, int32_t nb, 
                 st.chunks++;
             }
         }
-        if (tc_status s = potrf_rec(ctx, W, nb, 0, nb, (int64_t)k * nb, d_info, pot)) return s;
+        if (tc_status s = potrf_rec(ctx->stream, W, nb, 0, nb, (int64_t)k * nb, d_info, pot)) return s;
         if (rows > 1)
             TC_HIP(tc::launch_trsm_blockinv(cs, W + nb2, W, nb, (int64_t)(rows - 1) * nb, pot));
         // new tiles: free slots (used again in the next column) or staging

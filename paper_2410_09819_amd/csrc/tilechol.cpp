@@ -279,22 +279,20 @@ void class_lists(const Plan& P, std::vector<int>& lists, std::vector<int>& count
 }
 
 // Recursive POTRF of the s x s block at offset o of a diagonal tile.
-tc_status potrf_rec(tc_ctx* ctx, double* T, int nb, int o, int s, int64_t col0, int* info,
+tc_status potrf_rec(hipStream_t st, double* T, int nb, int o, int s, int64_t col0, int* info,
                     double* big) {
     if (s <= 128) {
-        TC_HIP(tc::launch_potrf_leaf(ctx->stream, T + o + (int64_t)o * nb, nb, s, info, col0 + o));
+        TC_HIP(tc::launch_potrf_leaf(st, T + o + (int64_t)o * nb, nb, s, info, col0 + o));
         return TC_OK;
     }
     const int h = ((s / 2 + 127) / 128) * 128;
-    tc_status st = potrf_rec(ctx, T, nb, o, h, col0, info, big);
-    if (st != TC_OK) return st;
+    if (tc_status r = potrf_rec(st, T, nb, o, h, col0, info, big)) return r;
     double* L11 = T + o + (int64_t)o * nb;
     double* A21 = T + (o + h) + (int64_t)o * nb;
     double* A22 = T + (o + h) + (int64_t)(o + h) * nb;
-    TC_HIP(tc::launch_trsm(ctx->stream, A21, L11, nb, s - h, h));
-    TC_HIP(tc::launch_syrk_sub(ctx->stream, A22, A21, nb, s - h, h, big,
-                               tc::syrk_sub_splits(s - h, h)));
-    return potrf_rec(ctx, T, nb, o + h, s - h, col0, info, big);
+    TC_HIP(tc::launch_trsm(st, A21, L11, nb, s - h, h));
+    TC_HIP(tc::launch_syrk_sub(st, A22, A21, nb, s - h, h, big, tc::syrk_sub_splits(s - h, h)));
+    return potrf_rec(st, T, nb, o + h, s - h, col0, info, big);
 }
 
 }  // namespace host
@@ -514,6 +512,10 @@ tc_status tc_ctx_create(tc_ctx** out, int device, void* workspace, size_t worksp
     c->aux[1] = ds[1];
     c->h2d = ds[2];
     c->d2h = ds[0];
+    if (tc_status s = noalloc_scratch_init(device)) {
+        tc_ctx_destroy(c);
+        return s;
+    }
     *out = c;
     return TC_OK;
 }
@@ -680,7 +682,7 @@ tc_status factorize_fp64(tc_ctx* ctx, int64_t n, int nb, const double* A, double
             tail_flops += (double)nb * nb * (double)nb * (1.0 + 2.0 * (Nt - k - 1));
         }
         double* Tkk = L + tc::tile_off(Nt, k, k) * nb2;
-        if (tc_status s = potrf_rec(ctx, Tkk, nb, 0, nb, (int64_t)k * nb, d_info, pot)) return s;
+        if (tc_status s = potrf_rec(ctx->stream, Tkk, nb, 0, nb, (int64_t)k * nb, d_info, pot)) return s;
         if (k + 1 < Nt)
             TC_HIP(tc::launch_trsm(sm, L + tc::tile_off(Nt, k + 1, k) * nb2, Tkk, nb,
                                    (int64_t)(Nt - k - 1) * nb, nb));
@@ -830,7 +832,7 @@ tc_status factorize_mixed(tc_ctx* ctx, int64_t n, int nb, const double* A, const
                                                d_tscl, nullptr, 0));
             if (tc_status s = low_groups(sm, k, k - 1, k)) return s;
         }
-        if (tc_status s = potrf_rec(ctx, Wk, nb, 0, nb, (int64_t)k * nb, d_info, pot)) return s;
+        if (tc_status s = potrf_rec(ctx->stream, Wk, nb, 0, nb, (int64_t)k * nb, d_info, pot)) return s;
         if (k + 1 < Nt)
             TC_HIP(tc::launch_trsm_blockinv(sm, Wk + nb2, Wk, nb, (int64_t)(Nt - k - 1) * nb, pot));
         TC_HIP(hipMemcpyAsync(storage + P.toff[tc::tile_off(Nt, k, k)], Wk, nb2 * sizeof(double),

@@ -646,9 +646,11 @@ def ooc_ablation(tc, si, dev, n=81920, nb=2048, cache_gib=40, small_gib=8):
     one MI355X, FP64, the ooc workload's parameters at n=81920, nb=2048, a
     40 GiB tile cache (holds the working set): the full schedule
     (asynchronous copies, resident accumulator V1, operand reuse V2,
-    diagonal tile kept through the TRSMs V3), without operand reuse across
-    columns (V1 only), with every copy on the compute stream (no overlap),
-    and both reductions; against the in-core factorization. Then, with an
+    diagonal tile kept through the TRSMs V3), without V3 (the diagonal
+    factor written back after POTRF and reloaded for each TRSM), without
+    operand reuse across columns (V1 only), with every copy on the compute
+    stream (no overlap), and the combinations; against the in-core
+    factorization. Then, with an
     8 GiB cache (below the ~13 GiB peak working set), next-use eviction
     against least-recently-used eviction."""
     import torch
@@ -674,15 +676,17 @@ def ooc_ablation(tc, si, dev, n=81920, nb=2048, cache_gib=40, small_gib=8):
     Ah = Abuf.view(torch.float64)
     cache = torch.empty(cache_gib << 30, dtype=torch.uint8, device=dev)
     small = cache[:small_gib << 30]
-    for name, sync, no_reuse, lru, cbuf in (
-            ("async, V1+V2+V3 (default)", False, False, False, cache),
-            ("async, V1 (no operand reuse)", False, True, False, cache),
-            ("sync, V1+V2+V3", True, False, False, cache),
-            ("sync, V1 (no operand reuse)", True, True, False, cache),
-            ("%d GiB cache, next-use eviction (default)" % small_gib, False, False, False, small),
-            ("%d GiB cache, LRU eviction" % small_gib, False, False, True, small)):
+    for name, sync, no_reuse, lru, no_v3, cbuf in (
+            ("async, V1+V2+V3 (default)", False, False, False, False, cache),
+            ("async, V1+V2 (no V3: diagonal tile reloaded per TRSM)", False, False, False, True, cache),
+            ("async, V1 (no operand reuse)", False, True, False, False, cache),
+            ("sync, V1+V2+V3", True, False, False, False, cache),
+            ("sync, V1+V2 (no V3)", True, False, False, True, cache),
+            ("sync, V1 (no operand reuse)", True, True, False, False, cache),
+            ("%d GiB cache, next-use eviction (default)" % small_gib, False, False, False, False, small),
+            ("%d GiB cache, LRU eviction" % small_gib, False, False, True, False, small)):
         Ah.copy_(A)
-        c2 = tc.Context(n, nb, ooc_sync=sync, ooc_no_reuse=no_reuse, ooc_lru=lru)
+        c2 = tc.Context(n, nb, ooc_sync=sync, ooc_no_reuse=no_reuse, ooc_lru=lru, ooc_no_v3=no_v3)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         st = tc.factorize_ooc(c2, Ah, n, nb, cbuf)

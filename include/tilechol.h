@@ -154,7 +154,11 @@ size_t tc_workspace_bytes(int64_t n, int32_t nb, int32_t nrhs);
  * resident, V1, but operands are not reused across columns, no V2).
  * Bit 3 (TC_CTX_OOC_EVICT_LRU) replaces the next-use eviction of
  * tc_factorize_ooc by least-recently-used eviction (the paper's "least
- * utilized" tiles, Section IV-B), for the same comparison.
+ * utilized" tiles, Section IV-B), for the same comparison. Bit 4
+ * (TC_CTX_OOC_NO_V3) drops V3 (Section IV-B: the diagonal tile kept in HBM
+ * through its column's TRSMs): tc_factorize_ooc writes the diagonal factor
+ * back after POTRF and loads it again from host memory for each tile's
+ * TRSM, through two extra cache slots (so the cache needs 2 * Nt + 2).
  *
  * Besides the caller's stream the library uses three streams of its own per
  * device (non-blocking, default priority), created by the first context on
@@ -172,6 +176,7 @@ size_t tc_workspace_bytes(int64_t n, int32_t nb, int32_t nrhs);
 #define TC_CTX_OOC_SYNC 2u
 #define TC_CTX_OOC_NO_REUSE 4u
 #define TC_CTX_OOC_EVICT_LRU 8u
+#define TC_CTX_OOC_NO_V3 16u
 tc_status tc_ctx_create(tc_ctx **ctx, int device, void *workspace, size_t workspace_bytes,
                         void *compute_stream, uint32_t flags);
 tc_status tc_ctx_destroy(tc_ctx *ctx);

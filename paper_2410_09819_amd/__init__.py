@@ -223,7 +223,7 @@ class Context:
 
     def __init__(self, n: int, nb: int, device: int = 0, stream=None, timed: bool = False,
                  nrhs: int = 16, ooc_sync: bool = False, ooc_no_reuse: bool = False,
-                 ooc_lru: bool = False):
+                 ooc_lru: bool = False, ooc_no_v3: bool = False):
         import torch
         self.device = device
         self.dev = torch.device("cuda", device)
@@ -236,7 +236,7 @@ class Context:
         _check(lib().tc_ctx_create(ctypes.byref(h), device, self.workspace.data_ptr(), nbytes,
                                    self.stream.cuda_stream,
                                    (1 if timed else 0) | (2 if ooc_sync else 0) | (4 if ooc_no_reuse else 0)
-                                   | (8 if ooc_lru else 0)))
+                                   | (8 if ooc_lru else 0) | (16 if ooc_no_v3 else 0)))
         self.handle = h
 
     def close(self):

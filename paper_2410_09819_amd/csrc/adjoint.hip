@@ -21,12 +21,6 @@ namespace {
 
 constexpr int kPB = 128;  // output block of the panel kernel
 
-__device__ __forceinline__ int64_t xcd_remap_a(int64_t hw, int64_t total) {
-    const int64_t xcd = hw % 8, idx = hw / 8;
-    const int64_t q = total / 8, r = total % 8;
-    return xcd * q + (xcd < r ? xcd : r) + idx;
-}
-
 // Row block r0 of tile row m of S, K index kk counted from tile column n+1.
 struct SymOp {
     const double* Ab;  // Abar (lower packed tiles)
@@ -53,7 +47,7 @@ __global__ __launch_bounds__(kGemmThreads, 2) void adj_panel_kernel(
     int nb, int n, int splits, int64_t nblocks, int64_t kchunk, double* __restrict__ partial) {
     using Tl = MfmaTile<kPB, kPB>;
     __shared__ double lds[Tl::LDS_DOUBLES];
-    const int64_t logical = xcd_remap_a(blockIdx.x, nblocks * splits);
+    const int64_t logical = xcd_remap(blockIdx.x, nblocks * splits);
     const int split = (int)(logical / nblocks);
     const int64_t b = logical - (int64_t)split * nblocks;
     const int T = nb / kPB;
@@ -113,7 +107,7 @@ __global__ __launch_bounds__(kGemmThreads, 2) void adj_gemm_kernel(
     int splits, int64_t kchunk, int64_t nbm, int64_t nblocks, double* __restrict__ partial) {
     using Tl = MfmaTile<B, B>;
     __shared__ double lds[Tl::LDS_DOUBLES];
-    const int64_t logical = xcd_remap_a(blockIdx.x, nblocks * splits);
+    const int64_t logical = xcd_remap(blockIdx.x, nblocks * splits);
     const int split = (int)(logical / nblocks);
     const int64_t b = logical - (int64_t)split * nblocks;
     int64_t br, bc;

@@ -11,6 +11,16 @@ __host__ __device__ inline int64_t tile_off(int64_t Nt, int64_t i, int64_t j) {
     return j * Nt - j * (j - 1) / 2 + (i - j);
 }
 
+// Workgroup ids are dealt round-robin to the 8 XCDs (each with its own L2).
+// Logical block of hardware id hw out of `total`: each XCD takes a contiguous
+// run of logical blocks, so neighbouring blocks (which share operand rows)
+// run under one L2.
+__device__ __forceinline__ int64_t xcd_remap(int64_t hw, int64_t total) {
+    const int64_t xcd = hw % 8, idx = hw / 8;
+    const int64_t q = total / 8, r = total % 8;
+    return xcd * q + (xcd < r ? xcd : r) + idx;
+}
+
 typedef double d2 __attribute__((ext_vector_type(2)));
 typedef double d4 __attribute__((ext_vector_type(4)));
 
@@ -150,6 +160,13 @@ hipError_t launch_mxp_copies(hipStream_t s, int nb, const int* list, int count, 
 // upd[2i + 1] (copy class c at + coff[c - 1] when bit c of need[t] is set).
 hipError_t launch_slot_tables(hipStream_t s, const int64_t* upd, int count, const uint8_t* need,
                               const int64_t* coff, int64_t* toff, int64_t* shoff);
+// Host image of column k of an out-of-core mixed factor in dst: the new
+// tiles (k+1.., k), read at cache offsets toff[t] in their classes (tcls),
+// written at dst + htoff[t] - htoff[(k, k)] (their host-image offsets
+// relative to the diagonal tile, which is already at dst).
+hipError_t launch_image_gather(hipStream_t s, const char* cache, const int64_t* toff,
+                               const int64_t* htoff, const uint8_t* tcls, int Nt, int nb, int k,
+                               char* dst);
 hipError_t launch_mxp_finalize(hipStream_t s, const double* W, int Nt, int nb, int k, double* part,
                                char* storage, const int64_t* toff, const uint8_t* tcls, int* tscl,
                                const int64_t* shoff, int* cscl);

@@ -24,12 +24,6 @@ namespace {
 constexpr int kPanelBM = 128;
 constexpr int kSubB = 64;
 
-__device__ __forceinline__ int64_t xcd_remap(int64_t hw, int64_t total) {
-    const int64_t xcd = hw % 8, idx = hw / 8;
-    const int64_t q = total / 8, r = total % 8;
-    return xcd * q + (xcd < r ? xcd : r) + idx;
-}
-
 // Decode logical block b of a panel into (global block-row gb, block-col bc).
 // Blocks of the diagonal tile come first, lower triangle only, row by row.
 __device__ __forceinline__ void panel_block(int64_t b, int T, int64_t& gb, int& bc) {

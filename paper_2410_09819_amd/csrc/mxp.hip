@@ -34,12 +34,6 @@ constexpr int kB = 128;       // output block
 constexpr int kStrips = 16;   // strips per tile for amax / cast
 constexpr int kThreads = 256;
 
-__device__ __forceinline__ int64_t xcd_remap_m(int64_t hw, int64_t total) {
-    const int64_t xcd = hw % 8, idx = hw / 8;
-    const int64_t q = total / 8, r = total % 8;
-    return xcd * q + (xcd < r ? xcd : r) + idx;
-}
-
 // ---------------------------------------------------------------------------
 // FP64 main loop over operands stored in any class (upcast while staging).
 //
@@ -254,7 +248,7 @@ __global__ __launch_bounds__(kGemmThreads, 2) void mxp_gemm_f64_kernel(
     __shared__ double lds[Tl::LDS_DOUBLES];
     const int T = nb / kB;
     const int64_t nblocks = (diag ? (int64_t)T * (T + 1) / 2 : 0) + (int64_t)nrows * T * T;
-    const int64_t logical = xcd_remap_m(blockIdx.x, nblocks * splits);
+    const int64_t logical = xcd_remap(blockIdx.x, nblocks * splits);
     const int split = (int)(logical / nblocks);
     const int64_t b = logical - (int64_t)split * nblocks;
     int64_t rt;
@@ -544,7 +538,7 @@ __global__ __launch_bounds__(kGemmThreads, 2) void mxp_gemm_narrow_kernel(
     __shared__ __attribute__((aligned(16))) uint8_t lds[2][2][2 * kPlane];  // [buf][A, B][plane]
     const int T = nb / kB;
     const int64_t total = (int64_t)nrows * T * T;
-    const int64_t b = xcd_remap_m(blockIdx.x, total);
+    const int64_t b = xcd_remap(blockIdx.x, total);
     int64_t rt;
     int br, bc;
     group_block(b, T, false, rows, rt, br, bc);
@@ -699,7 +693,7 @@ __global__ __launch_bounds__(kGemmThreads, 2) void mxp_gemm_split_kernel(
     __shared__ __attribute__((aligned(16))) uint8_t lds[2][4][kPlane];
     const int T = nb / kB;
     const int64_t total = (int64_t)nrows * T * T;
-    const int64_t b = xcd_remap_m(blockIdx.x, total);
+    const int64_t b = xcd_remap(blockIdx.x, total);
     int64_t rt;
     int br, bc;
     group_block(b, T, false, rows, rt, br, bc);

@@ -9,18 +9,13 @@
 //   W[rt] -= sum_{q < nc} L(k + rt, n0 + q) L(k, n0 + q)^T
 // with the FP64 MFMA main loop of the in-core kernel, lower blocks only in
 // the diagonal tile, and optional split-K (partials reduced in fixed order).
+#include "formats.hpp"
 #include "gemm_f64.hpp"
 
 namespace tc {
 namespace {
 
 constexpr int kB = 128;
-
-__device__ __forceinline__ int64_t xcd_remap_o(int64_t hw, int64_t total) {
-    const int64_t xcd = hw % 8, idx = hw / 8;
-    const int64_t q = total / 8, r = total % 8;
-    return xcd * q + (xcd < r ? xcd : r) + idx;
-}
 
 struct TabOp {
     const double* const* tab;
@@ -39,7 +34,7 @@ __global__ __launch_bounds__(kGemmThreads, 2) void ooc_panel_kernel(
     const int T = nb / kB;
     const int64_t tri = (int64_t)T * (T + 1) / 2;
     const int64_t nblocks = tri + (int64_t)(rows - 1) * T * T;
-    const int64_t logical = xcd_remap_o(blockIdx.x, nblocks * splits);
+    const int64_t logical = xcd_remap(blockIdx.x, nblocks * splits);
     const int split = (int)(logical / nblocks);
     const int64_t b = logical - (int64_t)split * nblocks;
     int64_t rt;
@@ -101,7 +96,33 @@ __global__ void ooc_reduce_kernel(double* __restrict__ W, int rows, int nb, int 
     *c = *c - s;
 }
 
+// One row of blocks per new tile; 16 bytes per thread and step (tile sizes
+// in every class are multiples of 16 bytes, offsets multiples of 256).
+__global__ __launch_bounds__(256) void image_gather_kernel(const char* __restrict__ cache,
+                                                          const int64_t* __restrict__ toff,
+                                                          const int64_t* __restrict__ htoff,
+                                                          const uint8_t* __restrict__ tcls, int Nt,
+                                                          int nb, int k, char* __restrict__ dst) {
+    const int m = k + 1 + (int)blockIdx.y;
+    const int64_t t = tile_off(Nt, m, k), tkk = tile_off(Nt, k, k);
+    const int64_t chunks = (int64_t)nb * nb * fmt_bytes(tcls[t]) / 16;
+    const uint4* src = reinterpret_cast<const uint4*>(cache + toff[t]);
+    uint4* out = reinterpret_cast<uint4*>(dst + (htoff[t] - htoff[tkk]));
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < chunks; i += (int64_t)gridDim.x * 256)
+        out[i] = src[i];
+}
+
 }  // namespace
+
+hipError_t launch_image_gather(hipStream_t s, const char* cache, const int64_t* toff,
+                               const int64_t* htoff, const uint8_t* tcls, int Nt, int nb, int k,
+                               char* dst) {
+    const int rows = Nt - k - 1;
+    if (rows <= 0) return hipSuccess;
+    hipLaunchKernelGGL(image_gather_kernel, dim3(64, rows), dim3(256), 0, s, cache, toff, htoff, tcls,
+                       Nt, nb, k, dst);
+    return hipGetLastError();
+}
 
 int64_t ooc_blocks(int rows, int nb) {
     const int64_t T = nb / kB;

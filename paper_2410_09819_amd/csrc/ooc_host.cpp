@@ -10,7 +10,8 @@
 //      reused (V2), a missing one is loaded from the host copy of L;
 //   2. POTRF of the diagonal tile and TRSM of the tiles below run on the
 //      working column (the diagonal factor stays in the working column until
-//      every TRSM of the column is done: V3);
+//      every TRSM of the column is done: V3; TC_CTX_OOC_NO_V3 instead writes
+//      it back after POTRF and reloads it for each tile's TRSM);
 //   3. the new column is written back to host memory once (write-through),
 //      and its off-diagonal tiles enter the cache when a slot is free (they
 //      are needed again in every later column up to their row);
@@ -85,10 +86,14 @@ extern "C" tc_status tc_factorize_ooc(tc_ctx* ctx, int64_t n, int32_t nb, const 
     const int Nt = (int)(n / nb);
     const int64_t nb2 = (int64_t)nb * nb;
     const size_t tbytes = (size_t)nb2 * sizeof(double);
-    const int64_t slots = (int64_t)(cache_bytes / tbytes);
+    // without V3 two slots stage the reloaded diagonal tile of the TRSMs
+    const bool no_v3 = (ctx->flags & TC_CTX_OOC_NO_V3) != 0;
+    const int64_t stage_slots = no_v3 ? 2 : 0;
+    const int64_t slots = (int64_t)(cache_bytes / tbytes) - stage_slots;
     if (slots < 2 * (int64_t)Nt)
-        return fail(TC_ENOMEM, "tile cache too small: need at least " + std::to_string(2 * Nt) +
-                                   " tiles of " + std::to_string(tbytes) + " bytes");
+        return fail(TC_ENOMEM, "tile cache too small: need at least " +
+                                   std::to_string(2 * Nt + stage_slots) + " tiles of " +
+                                   std::to_string(tbytes) + " bytes");
     DeviceGuard g(ctx->device);
     const Layout Ly = layout(n, nb);
     int* d_info = reinterpret_cast<int*>(ctx->ws + Ly.info);
@@ -122,6 +127,7 @@ extern "C" tc_status tc_factorize_ooc(tc_ctx* ctx, int64_t n, int32_t nb, const 
     for (int64_t s = slots - 1; s >= 0; --s) free_slots.push_back((int)s);
     std::set<std::pair<int, int>> cached;  // (n, m) of cached tiles
     std::vector<int> col_d2h(Nt, -1), col_done(Nt, -1);
+    int stage_reader[2] = {-1, -1};
     int evW[2] = {-1, -1};
     tc_ooc_stats st;
     std::memset(&st, 0, sizeof(st));
@@ -252,7 +258,41 @@ extern "C" tc_status tc_factorize_ooc(tc_ctx* ctx, int64_t n, int32_t nb, const 
             }
         }
         if (tc_status s = potrf_rec(ctx->stream, W, nb, 0, nb, (int64_t)k * nb, d_info, pot)) return s;
-        if (rows > 1) TC_HIP(tc::launch_trsm(cs, W + nb2, W, nb, (int64_t)(rows - 1) * nb, nb));
+        if (rows > 1 && !no_v3) {
+            // V3: the diagonal factor stays in the working column for the
+            // one TRSM launch over the tiles below it
+            TC_HIP(tc::launch_trsm(cs, W + nb2, W, nb, (int64_t)(rows - 1) * nb, nb));
+        } else if (rows > 1) {
+            // without V3 the diagonal factor goes back to host memory after
+            // POTRF and each tile's TRSM loads it again (two staging slots)
+            int ep, ed;
+            if (tc_status r = E.get(ep)) return r;
+            TC_HIP(hipEventRecord(E.ev[ep], cs));
+            TC_HIP(hipStreamWaitEvent(ds, E.ev[ep], 0));
+            TC_HIP(hipMemcpyAsync(L_host + tc::tile_off(Nt, k, k) * nb2, W, tbytes,
+                                  hipMemcpyDeviceToHost, ds));
+            st.bytes_d2h += tbytes;
+            if (tc_status r = E.get(ed)) return r;
+            TC_HIP(hipEventRecord(E.ev[ed], ds));
+            for (int m = k + 1; m < Nt; ++m) {
+                const int b = (m - k - 1) & 1;
+                double* Lkk = reinterpret_cast<double*>(cbase + (size_t)(slots + b) * tbytes);
+                TC_HIP(hipStreamWaitEvent(hs, E.ev[ed], 0));
+                if (stage_reader[b] >= 0) TC_HIP(hipStreamWaitEvent(hs, E.ev[stage_reader[b]], 0));
+                TC_HIP(hipMemcpyAsync(Lkk, L_host + tc::tile_off(Nt, k, k) * nb2, tbytes,
+                                      hipMemcpyHostToDevice, hs));
+                st.bytes_h2d += tbytes;
+                st.tiles_reloaded++;
+                int el, er;
+                if (tc_status r = E.get(el)) return r;
+                TC_HIP(hipEventRecord(E.ev[el], hs));
+                TC_HIP(hipStreamWaitEvent(cs, E.ev[el], 0));
+                TC_HIP(tc::launch_trsm(cs, W + (size_t)(m - k) * nb2, Lkk, nb, nb, nb));
+                if (tc_status r = E.get(er)) return r;
+                TC_HIP(hipEventRecord(E.ev[er], cs));
+                stage_reader[b] = er;
+            }
+        }
         if (no_reuse) {  // every operand tile is loaded again in the next column
             std::vector<std::pair<int, int>> all(cached.begin(), cached.end());
             for (const auto& nm : all) release(tc::tile_off(Nt, nm.second, nm.first), nm.first, nm.second);
@@ -274,11 +314,13 @@ extern "C" tc_status tc_factorize_ooc(tc_ctx* ctx, int64_t n, int32_t nb, const 
         TC_HIP(hipEventRecord(E.ev[col_done[k]], cs));
         for (int m = k + 1; m < k + 1 + cached_new; ++m)
             slot_reader[tile_slot[tc::tile_off(Nt, m, k)]] = col_done[k];
-        // write-back of column k (contiguous in packed order)
+        // write-back of column k (contiguous in packed order; without V3 the
+        // diagonal tile went back already)
         TC_HIP(hipStreamWaitEvent(ds, E.ev[col_done[k]], 0));
-        TC_HIP(hipMemcpyAsync(L_host + tc::tile_off(Nt, k, k) * nb2, W, (size_t)rows * tbytes,
-                              hipMemcpyDeviceToHost, ds));
-        st.bytes_d2h += (uint64_t)rows * tbytes;
+        const int wb0 = (no_v3 && rows > 1) ? 1 : 0;
+        TC_HIP(hipMemcpyAsync(L_host + (tc::tile_off(Nt, k, k) + wb0) * nb2, W + (size_t)wb0 * nb2,
+                              (size_t)(rows - wb0) * tbytes, hipMemcpyDeviceToHost, ds));
+        st.bytes_d2h += (uint64_t)(rows - wb0) * tbytes;
         if (tc_status s = E.get(col_d2h[k])) return s;
         TC_HIP(hipEventRecord(E.ev[col_d2h[k]], ds));
         // prefetch the accumulators of column k+1 into the other working column

@@ -20,9 +20,10 @@
 // group and the low-class groups of the chunk); (2) POTRF and TRSM on the
 // working column; (3) finalize rounds the new tiles into their classes,
 // straight into free slots (they are used again in the next column) or into
-// a staging area (two halves, alternating by column); (4) the diagonal tile
-// (copied out of the working column first) and the new tiles are written
-// back in their classes. The low-class groups of a chunk run on a side stream,
+// a staging area (two halves, alternating by column); (4) the new tiles are
+// gathered in their classes' bytes behind the binary64 diagonal tile in the
+// working column, which then goes to the host image in one copy. The
+// low-class groups of a chunk run on a side stream,
 // concurrently with its FP64 group. Eviction is the farthest next use under
 // the static schedule, as in the FP64 path; row k's tiles are dead after
 // column k.
@@ -96,7 +97,7 @@ size_t tiles_end(const Plan& P) {
 
 // Device tables at the front of the cache buffer.
 struct Tables {
-    size_t toff, shoff, tscl, tcls, cscl, need, lists, ring, total;
+    size_t toff, shoff, tscl, tcls, cscl, need, lists, htoff, ring, total;
 };
 
 constexpr int kRing = 16;
@@ -119,6 +120,8 @@ Tables tables_of(const Plan& P, size_t ring_entries) {
     off += align_up((size_t)P.ntiles);
     T.lists = off;
     off += align_up((size_t)5 * P.Nt * P.Nt * sizeof(int));
+    T.htoff = off;  // byte offsets of the tiles in the host image
+    off += align_up((size_t)P.ntiles * sizeof(int64_t));
     T.ring = off;  // kRing x (ring_entries pairs of int64 + ring_entries int)
     off += (size_t)kRing * align_up(ring_entries * (2 * sizeof(int64_t) + sizeof(int)));
     T.total = off;
@@ -143,9 +146,8 @@ extern "C" size_t tc_ooc_mixed_cache_bytes(int64_t n, int32_t nb, const uint8_t*
     const Bundle B = bundle_of(P);
     const Tables T = tables_of(P, (size_t)Nt * Nt + 2 * (size_t)Nt);
     const size_t half = (size_t)(Nt > 1 ? Nt - 1 : 1) * B.bytes;
-    const size_t dbytes = align_up((size_t)P.nb * P.nb * sizeof(double));
     const size_t colmax = align_up((size_t)Nt * P.nb * P.nb * sizeof(double));
-    return T.total + 2 * half + 2 * dbytes + kWork * colmax + (size_t)slots * B.bytes;
+    return T.total + 2 * half + kWork * colmax + (size_t)slots * B.bytes;
 }
 
 extern "C" tc_status tc_factorize_ooc_mixed(tc_ctx* ctx, int64_t n, int32_t nb, const double* A_host,
@@ -170,11 +172,9 @@ extern "C" tc_status tc_factorize_ooc_mixed(tc_ctx* ctx, int64_t n, int32_t nb, 
     // slots: what is left after the tables and the staging of one column
     const size_t ring_entries = (size_t)Nt * Nt + 2 * (size_t)Nt;
     const Tables T = tables_of(P, ring_entries);
-    // staging: two halves (columns alternate) of Nt - 1 bundles, then two
-    // binary64 buffers for the diagonal tile's write-back
+    // staging: two halves (columns alternate) of Nt - 1 bundles
     const size_t half = (size_t)(Nt > 1 ? Nt - 1 : 1) * B.bytes;
-    const size_t dbytes = align_up((size_t)nb2 * sizeof(double));
-    const size_t staging = 2 * half + 2 * dbytes;
+    const size_t staging = 2 * half;
     const size_t colmax = align_up((size_t)Nt * nb2 * sizeof(double));
     const size_t fixed = T.total + staging + kWork * colmax;
     const int64_t slots = cache_bytes > fixed ? (int64_t)((cache_bytes - fixed) / B.bytes) : 0;
@@ -198,10 +198,10 @@ extern "C" tc_status tc_factorize_ooc_mixed(tc_ctx* ctx, int64_t n, int32_t nb, 
     int* d_cscl = reinterpret_cast<int*>(cbase + T.cscl);
     uint8_t* d_need = reinterpret_cast<uint8_t*>(cbase + T.need);
     int* d_lists = reinterpret_cast<int*>(cbase + T.lists);
+    int64_t* d_htoff = reinterpret_cast<int64_t*>(cbase + T.htoff);
     char* d_ring = cbase + T.ring;
     const size_t ring_bytes = align_up(ring_entries * (2 * sizeof(int64_t) + sizeof(int)));
     const size_t stage0 = T.total;          // staging bundles, half h at stage0 + h * half
-    const size_t diag0 = T.total + 2 * half;  // diagonal write-back buffer d at diag0 + d * dbytes
     const size_t work0 = T.total + staging;  // working column of column k at work0 + (k % kWork) * colmax
     const size_t slot0 = work0 + kWork * colmax;  // slot s at slot0 + s * B.bytes
     auto work = [&](int c) { return reinterpret_cast<double*>(cbase + work0 + (size_t)(c % kWork) * colmax); };
@@ -309,6 +309,8 @@ extern "C" tc_status tc_factorize_ooc_mixed(tc_ctx* ctx, int64_t n, int32_t nb, 
         TC_HIP(hipMemcpyAsync(d_tscl, zeros.data(), (size_t)P.ntiles * sizeof(int), hipMemcpyHostToDevice, cs));
         TC_HIP(hipMemcpyAsync(d_cscl, zeros.data(), zeros.size() * sizeof(int), hipMemcpyHostToDevice, cs));
         TC_HIP(hipMemcpyAsync(d_lists, lists.data(), lists.size() * sizeof(int), hipMemcpyHostToDevice, cs));
+        TC_HIP(hipMemcpyAsync(d_htoff, P.toff.data(), P.toff.size() * sizeof(int64_t),
+                              hipMemcpyHostToDevice, cs));
         TC_HIP(hipStreamSynchronize(cs));  // host vectors go out of scope
     }
     int e0;
@@ -422,7 +424,6 @@ extern "C" tc_status tc_factorize_ooc_mixed(tc_ctx* ctx, int64_t n, int32_t nb, 
         bool staged = false;
         upd.clear();
         rebuild.clear();
-        std::vector<size_t> where(rows, 0);
         std::vector<int> new_slot(rows, -1);
         for (int m = k + 1; m < Nt; ++m) {
             const int64_t t = tc::tile_off(Nt, m, k);
@@ -440,35 +441,29 @@ extern "C" tc_status tc_factorize_ooc_mixed(tc_ctx* ctx, int64_t n, int32_t nb, 
                 o = stage0 + (size_t)h * half + (size_t)(m - k - 1) * B.bytes;
                 staged = true;
             }
-            where[m - k] = o;
             upd.push_back(t);
             upd.push_back((int64_t)o);
         }
         if (staged && stage_last[h] >= 0) TC_HIP(hipStreamWaitEvent(cs, E.ev[col_d2h[stage_last[h]]], 0));
         if (staged) stage_last[h] = k;
         if (tc_status r = apply(upd, rebuild)) return r;
-        // the diagonal tile leaves the working column on the device, so the
-        // next prefetch into it does not wait for the write-back
-        if (k >= 2) TC_HIP(hipStreamWaitEvent(cs, E.ev[col_d2h[k - 2]], 0));
-        TC_HIP(hipMemcpyAsync(cbase + diag0 + (size_t)h * dbytes, W, (size_t)nb2 * sizeof(double),
-                              hipMemcpyDeviceToDevice, cs));
         TC_HIP(tc::launch_mxp_finalize(cs, W, Nt, nb, k, part, cbase, d_toff, d_tcls, d_tscl, d_shoff,
                                        d_cscl));
+        // the column's image in the working column: the binary64 diagonal
+        // tile is already at its start, the new tiles follow in their
+        // classes' bytes at their host-image offsets (W is free once
+        // finalized; the next prefetch into it runs on the write-back stream,
+        // after this column's copy)
+        TC_HIP(tc::launch_image_gather(cs, cbase, d_toff, d_htoff, d_tcls, Nt, nb, k,
+                                       reinterpret_cast<char*>(W)));
         if (tc_status s = E.get(col_done[k])) return s;
         TC_HIP(hipEventRecord(E.ev[col_done[k]], cs));
-        // write-back of column k in its classes: the diagonal tile from W,
-        // the others from their slots or the staging area
+        // write-back of column k in its classes: one contiguous copy
         TC_HIP(hipStreamWaitEvent(ds, E.ev[col_done[k]], 0));
-        const int64_t tkk = tc::tile_off(Nt, k, k);
-        TC_HIP(hipMemcpyAsync(Lh + P.toff[tkk], cbase + diag0 + (size_t)h * dbytes,
-                              (size_t)nb2 * sizeof(double), hipMemcpyDeviceToHost, ds));
-        st.bytes_d2h += (uint64_t)nb2 * sizeof(double);
-        for (int m = k + 1; m < Nt; ++m) {
-            const int64_t t = tc::tile_off(Nt, m, k);
-            TC_HIP(hipMemcpyAsync(Lh + P.toff[t], cbase + where[m - k], tile_bytes(t),
-                                  hipMemcpyDeviceToHost, ds));
-            st.bytes_d2h += tile_bytes(t);
-        }
+        const int64_t tkk = tc::tile_off(Nt, k, k), tlast = tc::tile_off(Nt, Nt - 1, k);
+        const size_t col_bytes = (size_t)(P.toff[tlast] - P.toff[tkk]) + tile_bytes(tlast);
+        TC_HIP(hipMemcpyAsync(Lh + P.toff[tkk], W, col_bytes, hipMemcpyDeviceToHost, ds));
+        st.bytes_d2h += col_bytes;
         if (tc_status s = E.get(col_d2h[k])) return s;
         TC_HIP(hipEventRecord(E.ev[col_d2h[k]], ds));
         for (int m = k + 1; m < Nt; ++m)

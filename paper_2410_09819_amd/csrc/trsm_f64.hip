@@ -120,12 +120,6 @@ struct StridedOp {
     __device__ const double* operator()(int64_t kk) const { return base + kk * ld; }
 };
 
-__device__ __forceinline__ int64_t xcd_remap_t(int64_t hw, int64_t total) {
-    const int64_t xcd = hw % 8, idx = hw / 8;
-    const int64_t q = total / 8, r = total % 8;
-    return xcd * q + (xcd < r ? xcd : r) + idx;
-}
-
 __global__ __launch_bounds__(kGemmThreads, 2) void strided_gemm_kernel(
     double* __restrict__ C, const double* __restrict__ A, const double* __restrict__ B, int nb,
     int64_t M, int N, int K) {
@@ -133,7 +127,7 @@ __global__ __launch_bounds__(kGemmThreads, 2) void strided_gemm_kernel(
     __shared__ double lds[Tl::LDS_DOUBLES];
     const int nbc = N / kGB;
     const int64_t total = (M / kGB) * nbc;
-    const int64_t logical = xcd_remap_t(blockIdx.x, total);
+    const int64_t logical = xcd_remap(blockIdx.x, total);
     const int64_t br = logical / nbc;
     const int bc = (int)(logical - br * nbc);
     const int64_t r0 = br * kGB;

@@ -103,12 +103,16 @@ def test_ooc_errors(tc, case):
     assert e.value.info == 701
 
 
-@pytest.mark.parametrize("sync,no_reuse", [(True, False), (False, True), (True, True)])
-def test_ooc_strategy_variants(tc, case, sync, no_reuse):
+@pytest.mark.parametrize("sync,no_reuse,no_v3", [(True, False, False), (False, True, False),
+                                                  (True, True, False), (False, False, True),
+                                                  (True, False, True)])
+def test_ooc_strategy_variants(tc, case, sync, no_reuse, no_v3):
     """The reduced strategies (copies on the compute stream; no operand
-    reuse across columns) run the same kernels in the same order, so the
-    factor is bitwise the default's; without reuse every column reloads its
-    operand tiles."""
+    reuse across columns; no diagonal tile kept through the TRSMs) compute
+    every entry with the same kernels in the same order, so the factor is
+    bitwise the default's; without reuse every column reloads its operand
+    tiles, and without V3 every TRSM reloads the diagonal factor (written
+    back once, right after POTRF)."""
     import torch
     n, nb, A = case["n"], case["nb"], case["A"]
     Nt = n // nb
@@ -119,12 +123,17 @@ def test_ooc_strategy_variants(tc, case, sync, no_reuse):
     st0 = tc.factorize_ooc(tc.Context(n, nb), Ah, n, nb, cache)
     L0 = Ah.numpy().copy()
     Ah = pinned(tc.pack_lower(A, nb))
-    ctx = tc.Context(n, nb, ooc_sync=sync, ooc_no_reuse=no_reuse)
+    ctx = tc.Context(n, nb, ooc_sync=sync, ooc_no_reuse=no_reuse, ooc_no_v3=no_v3)
     st = tc.factorize_ooc(ctx, Ah, n, nb, cache)
     assert st["info"] == 0
     assert np.array_equal(Ah.numpy(), L0)
     assert st["bytes_d2h"] == st0["bytes_d2h"] == ntiles * tbytes
-    if no_reuse:
+    if no_v3:
+        diag_loads = Nt * (Nt - 1) // 2  # one per tile below the diagonal
+        assert st["tiles_reloaded"] == st0["tiles_reloaded"] + diag_loads
+        assert st["bytes_h2d"] == st0["bytes_h2d"] + diag_loads * tbytes
+        assert st["cache_slots"] == st0["cache_slots"] - 2
+    elif no_reuse:
         # operands (m, n), m >= k > n, loaded in every column k
         loads = sum((Nt - k) * k for k in range(1, Nt))
         assert st["tiles_reloaded"] == loads

@@ -37,12 +37,15 @@ constexpr int kThreads = 256;
 // ---------------------------------------------------------------------------
 // FP64 main loop over operands stored in any class (upcast while staging).
 //
-// Each thread moves 8 consecutive rows of one column of a 128 x 16 operand
-// slab per stage: one to four 16-byte loads of the stored bits (8 doubles,
-// 8 floats, 8 halves or 8 e4m3 bytes). The raw bits stay in registers while
-// the current stage's MFMAs run and are decoded, scaled by 2^scale (exact)
-// and written to LDS only after them, so the loads overlap the math as in
-// the all-FP64 main loop.
+// A stage is a 128 x 16 operand slab (16 columns of the tile, 128 rows),
+// loaded with consecutive lanes on consecutive bytes: a binary64 slab as
+// four 16-byte pieces per thread (2 rows each), the other classes as two
+// pieces of 4 consecutive rows (16, 8, 8 or 4 bytes). The raw bits stay in
+// registers while the current stage's MFMAs run; after them they are
+// decoded, scaled by 2^scale (exact) and written to LDS. An operand's class
+// changes only between tile columns, so each tile column's stages run in a
+// loop specialized for its (A class, B class) pair: straight-line loads,
+// decodes and waits, as in the all-binary64 main loop.
 // ---------------------------------------------------------------------------
 struct MixedTile {
     const char* base;  // tile start
@@ -51,163 +54,217 @@ struct MixedTile {
 };
 
 struct RawSlab {
-    uint4 w[4];
+    uint4 w[2];
 };
 
-__device__ __forceinline__ void raw_load(const MixedTile& t, int64_t idx, RawSlab& r) {
-    switch (t.cls) {
-        case kFP64: {
-            const uint4* p = reinterpret_cast<const uint4*>(reinterpret_cast<const double*>(t.base) + idx);
-            r.w[0] = p[0];
-            r.w[1] = p[1];
-            r.w[2] = p[2];
-            r.w[3] = p[3];
-            break;
-        }
-        case kFP32: {
-            const uint4* p = reinterpret_cast<const uint4*>(reinterpret_cast<const float*>(t.base) + idx);
-            r.w[0] = p[0];
-            r.w[1] = p[1];
-            break;
-        }
-        case kFP16:
-        case kBF16:
-            r.w[0] = *reinterpret_cast<const uint4*>(reinterpret_cast<const uint16_t*>(t.base) + idx);
-            break;
-        default: {
-            const uint2 v = *reinterpret_cast<const uint2*>(reinterpret_cast<const uint8_t*>(t.base) + idx);
-            r.w[0].x = v.x;
-            r.w[0].y = v.y;
-            break;
-        }
+// The FP64-group kernel: 512 threads (8 waves, 2 x 4, each 64 rows x 32
+// columns of the 128 x 128 block), so each wave holds half the
+// accumulators of the 4-wave binary64 kernels and every class pair's loop
+// fits in registers.
+constexpr int kF64Threads = 512;
+constexpr int kF64MI = 4, kF64NI = 2;  // 16 x 16 MFMA blocks per wave
+
+// A thread's pieces of a slab: element offsets in the tile (leading
+// dimension nb) and LDS offsets (leading dimension LD) of its 2 binary64
+// pieces of 2 rows (e2, s2) or its piece of 4 rows of the narrower classes
+// (e4, s4).
+struct SlabMap {
+    int e2[2], s2[2], e4, s4;
+};
+
+template <int LD>
+__device__ __forceinline__ SlabMap slab_map(int tid, int nb) {
+    SlabMap m;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int e = (q * kF64Threads + tid) * 2, col = e >> 7, row = e & 127;
+        m.e2[q] = col * nb + row;
+        m.s2[q] = col * LD + row;
+    }
+    const int e = tid * 4, col = e >> 7, row = e & 127;
+    m.e4 = col * nb + row;
+    m.s4 = col * LD + row;
+    return m;
+}
+
+// Raw bits of a thread's pieces of the class-C slab starting at element idx.
+template <int C>
+__device__ __forceinline__ void raw_load(const char* base, int64_t idx, const SlabMap& m, RawSlab& r) {
+    if constexpr (C == kFP64) {
+        const double* p = reinterpret_cast<const double*>(base) + idx;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) r.w[q] = *reinterpret_cast<const uint4*>(p + m.e2[q]);
+    } else if constexpr (C == kFP32) {
+        r.w[0] = *reinterpret_cast<const uint4*>(reinterpret_cast<const float*>(base) + idx + m.e4);
+    } else if constexpr (C == kFP16 || C == kBF16) {
+        const uint2 v = *reinterpret_cast<const uint2*>(reinterpret_cast<const uint16_t*>(base) + idx + m.e4);
+        r.w[0].x = v.x;
+        r.w[0].y = v.y;
+    } else {
+        r.w[0].x = *reinterpret_cast<const uint32_t*>(reinterpret_cast<const uint8_t*>(base) + idx + m.e4);
     }
 }
 
 typedef float f2v __attribute__((ext_vector_type(2)));
 
-// Decode the 8 stored values of a run to binary64 and write them to LDS.
-// Conversions are exact: FP8 (OCP e4m3, which the gfx950 packed conversion
-// implements) and FP16 through binary32, the tile scale applied afterwards
-// with ldexp in binary64, and only for the scaled classes.
-__device__ __forceinline__ void raw_store(const RawSlab& r, int cls, int scale, double* dst) {
-    double v[8];
-    const uint32_t* w = reinterpret_cast<const uint32_t*>(r.w);
-    switch (cls) {
-        case kFP64:
+// Decode a thread's pieces of a class-C slab to binary64 and write them to
+// the LDS stage `dst`. Conversions are exact: FP8 (OCP e4m3, which the
+// gfx950 packed conversion implements) and FP16 through binary32, the tile
+// scale applied afterwards with ldexp in binary64 (scaled classes only).
+template <int C>
+__device__ __forceinline__ void raw_store(const RawSlab& r, int scale, const SlabMap& m, double* dst) {
+    if constexpr (C == kFP64) {
 #pragma unroll
-            for (int i = 0; i < 8; ++i) v[i] = __hiloint2double((int)w[2 * i + 1], (int)w[2 * i]);
-            break;
-        case kFP32:
+        for (int q = 0; q < 2; ++q) {
+            const uint4 w = r.w[q];
+            *reinterpret_cast<d2*>(dst + m.s2[q]) =
+                d2{__hiloint2double((int)w.y, (int)w.x), __hiloint2double((int)w.w, (int)w.z)};
+        }
+    } else {
+        const uint4 w = r.w[0];
+        double v[4];
+        if constexpr (C == kFP32) {
+            v[0] = (double)__uint_as_float(w.x);
+            v[1] = (double)__uint_as_float(w.y);
+            v[2] = (double)__uint_as_float(w.z);
+            v[3] = (double)__uint_as_float(w.w);
+        } else if constexpr (C == kFP16) {
 #pragma unroll
-            for (int i = 0; i < 8; ++i) v[i] = (double)__uint_as_float(w[i]);
-            break;
-        case kFP16:
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const uint16_t h = (uint16_t)(w[i >> 1] >> (16 * (i & 1)));
-                v[i] = (double)(float)__builtin_bit_cast(_Float16, h);
+            for (int i = 0; i < 4; ++i) {
+                const uint32_t h = ((i < 2 ? w.x : w.y) >> (16 * (i & 1))) & 0xFFFFu;
+                v[i] = (double)(float)__builtin_bit_cast(_Float16, (uint16_t)h);
             }
-            break;
-        case kBF16:
+        } else if constexpr (C == kBF16) {
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const uint32_t h = (w[i >> 1] >> (16 * (i & 1))) & 0xFFFFu;
+            for (int i = 0; i < 4; ++i) {
+                const uint32_t h = ((i < 2 ? w.x : w.y) >> (16 * (i & 1))) & 0xFFFFu;
                 v[i] = (double)__uint_as_float(h << 16);
             }
-            break;
-        default:
+        } else {
+            const f2v lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)w.x, false);
+            const f2v hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)w.x, true);
+            v[0] = lo.x;
+            v[1] = lo.y;
+            v[2] = hi.x;
+            v[3] = hi.y;
+        }
+        if constexpr (C == kFP16 || C == kFP8) {
+            if (scale != 0) {
 #pragma unroll
-            for (int q = 0; q < 2; ++q) {
-                const f2v lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)w[q], false);
-                const f2v hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)w[q], true);
-                v[4 * q] = lo.x;
-                v[4 * q + 1] = lo.y;
-                v[4 * q + 2] = hi.x;
-                v[4 * q + 3] = hi.y;
+                for (int i = 0; i < 4; ++i) v[i] = ldexp(v[i], scale);
             }
-            break;
+        }
+        *reinterpret_cast<d2*>(dst + m.s4) = d2{v[0], v[1]};
+        *reinterpret_cast<d2*>(dst + m.s4 + 2) = d2{v[2], v[3]};
     }
-    if (scale != 0) {
-#pragma unroll
-        for (int i = 0; i < 8; ++i) v[i] = ldexp(v[i], scale);
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) *reinterpret_cast<d2*>(dst + 2 * i) = d2{v[2 * i], v[2 * i + 1]};
 }
 
-template <class AOp, class BOp>
-__device__ __forceinline__ void mixed_mainloop(d4 (&acc)[kB / 32][kB / 32], const AOp& aop,
-                                               const BOp& bop, int64_t nb, int64_t kbeg,
-                                               int64_t kend, double* lds) {
+typedef d4 F64Acc[kF64MI][kF64NI];
+
+// Stages c0, c0 + 16, ... < c1 (columns of tile column n) with A of class CA
+// and B of class CB: the double-buffered loop of the all-binary64 main loop,
+// its first stage loaded without overlap. a0, b0: element offsets of the
+// slabs' first row in column 0 of their tiles.
+template <int CA, int CB>
+__device__ __forceinline__ void mixed_run(F64Acc& acc, const MixedTile ta, const MixedTile tb,
+                                          int64_t a0, int64_t b0, int64_t nb, int c0, int c1,
+                                          const SlabMap& map, double* lds) {
     using T = MfmaTile<kB, kB>;
-    static_assert(kB * T::BK == 8 * kGemmThreads, "one 8-row run per thread per operand");
-    if (kbeg >= kend) return;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
     const int wm = wave & 1, wn = wave >> 1;
     double* As = lds;
     double* Bs = lds + 2 * T::BK * T::LDA;
-    const int col = tid >> 4, row0 = (tid & 15) * 8;
     RawSlab ra, rb;
-    int acls, bcls, ascl, bscl;
-    auto gload = [&](int64_t kk) {
-        int64_t ia, ib;
-        const MixedTile ta = aop(kk, ia), tb = bop(kk, ib);
-        raw_load(ta, ia + (int64_t)col * nb + row0, ra);
-        raw_load(tb, ib + (int64_t)col * nb + row0, rb);
-        acls = ta.cls;
-        bcls = tb.cls;
-        ascl = ta.scale;
-        bscl = tb.scale;
-    };
-    auto sstore = [&](int buf) {
-        raw_store(ra, acls, ascl, As + buf * T::BK * T::LDA + col * T::LDA + row0);
-        raw_store(rb, bcls, bscl, Bs + buf * T::BK * T::LDB + col * T::LDB + row0);
-    };
-    gload(kbeg);
-    sstore(0);
+    raw_load<CA>(ta.base, a0 + (int64_t)c0 * nb, map, ra);
+    raw_load<CB>(tb.base, b0 + (int64_t)c0 * nb, map, rb);
+    raw_store<CA>(ra, ta.scale, map, As);
+    raw_store<CB>(rb, tb.scale, map, Bs);
     __syncthreads();
     int buf = 0;
     const int li = lane & 15, lk = lane >> 4;
-    for (int64_t kk = kbeg; kk < kend; kk += T::BK) {
-        const bool more = kk + T::BK < kend;
-        if (more) gload(kk + T::BK);
-        const double* as = As + buf * T::BK * T::LDA + wm * (kB / 2) + li;
-        const double* bs = Bs + buf * T::BK * T::LDB + wn * (kB / 2) + li;
+    for (int c = c0; c < c1; c += T::BK) {
+        const bool more = c + T::BK < c1;
+        if (more) {
+            raw_load<CA>(ta.base, a0 + (int64_t)(c + T::BK) * nb, map, ra);
+            raw_load<CB>(tb.base, b0 + (int64_t)(c + T::BK) * nb, map, rb);
+        }
+        const double* as = As + buf * T::BK * T::LDA + wm * 64 + li;
+        const double* bs = Bs + buf * T::BK * T::LDB + wn * 32 + li;
 #pragma unroll
         for (int ks = 0; ks < T::BK / 4; ++ks) {
             const int k = ks * 4 + lk;
-            double a[T::MI], b[T::NI];
+            double a[kF64MI], b[kF64NI];
 #pragma unroll
-            for (int mi = 0; mi < T::MI; ++mi) a[mi] = as[k * T::LDA + mi * 16];
+            for (int mi = 0; mi < kF64MI; ++mi) a[mi] = as[k * T::LDA + mi * 16];
 #pragma unroll
-            for (int ni = 0; ni < T::NI; ++ni) b[ni] = bs[k * T::LDB + ni * 16];
+            for (int ni = 0; ni < kF64NI; ++ni) b[ni] = bs[k * T::LDB + ni * 16];
 #pragma unroll
-            for (int mi = 0; mi < T::MI; ++mi)
+            for (int mi = 0; mi < kF64MI; ++mi)
 #pragma unroll
-                for (int ni = 0; ni < T::NI; ++ni)
+                for (int ni = 0; ni < kF64NI; ++ni)
                     acc[mi][ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[ni], a[mi], acc[mi][ni],
                                                                       0, 0, 0);
         }
-        if (more) sstore(buf ^ 1);
+        if (more) {
+            raw_store<CA>(ra, ta.scale, map, As + (buf ^ 1) * T::BK * T::LDA);
+            raw_store<CB>(rb, tb.scale, map, Bs + (buf ^ 1) * T::BK * T::LDB);
+        }
         __syncthreads();
         buf ^= 1;
     }
 }
 
-// Stored tile (m, n) as a MixedTile; idx = element offset of column kk % nb
-// plus the first row r0.
+template <int CA>
+__device__ __forceinline__ void mixed_run_b(F64Acc& acc, const MixedTile& ta, const MixedTile& tb,
+                                            int64_t a0, int64_t b0, int64_t nb, int c0, int c1,
+                                            const SlabMap& map, double* lds) {
+    switch (tb.cls) {
+        case kFP64: mixed_run<CA, kFP64>(acc, ta, tb, a0, b0, nb, c0, c1, map, lds); break;
+        case kFP32: mixed_run<CA, kFP32>(acc, ta, tb, a0, b0, nb, c0, c1, map, lds); break;
+        case kFP16: mixed_run<CA, kFP16>(acc, ta, tb, a0, b0, nb, c0, c1, map, lds); break;
+        case kBF16: mixed_run<CA, kBF16>(acc, ta, tb, a0, b0, nb, c0, c1, map, lds); break;
+        default: mixed_run<CA, kFP8>(acc, ta, tb, a0, b0, nb, c0, c1, map, lds); break;
+    }
+}
+
+// acc += A B^T over the K range [kbeg, kend) (a multiple of 16 long, kbeg
+// a multiple of 16): tile column by tile column, each in the loop of its
+// classes.
+template <class AOp, class BOp>
+__device__ __forceinline__ void mixed_mainloop(F64Acc& acc, const AOp& aop, const BOp& bop,
+                                               int64_t nb, int64_t kbeg, int64_t kend, double* lds) {
+    using T = MfmaTile<kB, kB>;
+    static_assert(kB * T::BK == 4 * kF64Threads, "four slab elements per thread per operand");
+    static_assert(T::LDA == T::LDB, "one slab map for both operands");
+    const SlabMap map = slab_map<T::LDA>(threadIdx.x, (int)nb);
+    for (int64_t kk = kbeg; kk < kend;) {
+        const int64_t n = kk / nb;
+        const int c0 = (int)(kk - n * nb);
+        const int c1 = (int)((kend - n * nb) < nb ? (kend - n * nb) : nb);
+        const MixedTile ta = aop.tile(n), tb = bop.tile(n);
+        switch (ta.cls) {
+            case kFP64: mixed_run_b<kFP64>(acc, ta, tb, aop.r0, bop.r0, nb, c0, c1, map, lds); break;
+            case kFP32: mixed_run_b<kFP32>(acc, ta, tb, aop.r0, bop.r0, nb, c0, c1, map, lds); break;
+            case kFP16: mixed_run_b<kFP16>(acc, ta, tb, aop.r0, bop.r0, nb, c0, c1, map, lds); break;
+            case kBF16: mixed_run_b<kBF16>(acc, ta, tb, aop.r0, bop.r0, nb, c0, c1, map, lds); break;
+            default: mixed_run_b<kFP8>(acc, ta, tb, aop.r0, bop.r0, nb, c0, c1, map, lds); break;
+        }
+        kk += c1 - c0;
+    }
+}
+
+// Stored tiles (row_tile, n) of the factor as MixedTiles; r0 = the slab's
+// first row inside the tile.
 struct StoredOp {
     const char* storage;
     const int64_t* toff;
     const uint8_t* tcls;
     const int* tscl;
     int64_t Nt, nb, row_tile, r0;
-    __device__ MixedTile operator()(int64_t kk, int64_t& idx) const {
-        const int64_t n = kk / nb;
+    __device__ MixedTile tile(int64_t n) const {
         const int64_t t = tile_off(Nt, row_tile, n);
-        idx = (kk - n * nb) * nb + r0;
         return MixedTile{storage + toff[t], (int)tcls[t], tscl[t]};
     }
 };
@@ -239,7 +296,7 @@ __device__ __forceinline__ void group_block(int64_t b, int T, bool diag, const i
 // (lower blocks, when diag) and the listed row tiles. splits > 1: split s
 // covers [K0 + s*kchunk, K0 + (s+1)*kchunk) and writes its 128 x 128 block
 // to partial[(s * nblocks + b) * 128^2] (column-major).
-__global__ __launch_bounds__(kGemmThreads, 2) void mxp_gemm_f64_kernel(
+__global__ __launch_bounds__(kF64Threads, 1) void mxp_gemm_f64_kernel(
     double* __restrict__ W, int Nt, int nb, int k, int64_t K0, int64_t K1,
     const int* __restrict__ rows, int nrows, int diag, const char* __restrict__ storage,
     const int64_t* __restrict__ toff, const uint8_t* __restrict__ tcls,
@@ -256,11 +313,11 @@ __global__ __launch_bounds__(kGemmThreads, 2) void mxp_gemm_f64_kernel(
     group_block(b, T, diag != 0, rows, rt, br, bc);
     const int64_t kbeg = K0 + (int64_t)split * kchunk;
     const int64_t kend = kbeg + kchunk < K1 ? kbeg + kchunk : K1;
-    d4 acc[Tl::MI][Tl::NI];
+    F64Acc acc;
 #pragma unroll
-    for (int mi = 0; mi < Tl::MI; ++mi)
+    for (int mi = 0; mi < kF64MI; ++mi)
 #pragma unroll
-        for (int ni = 0; ni < Tl::NI; ++ni) acc[mi][ni] = d4{0.0, 0.0, 0.0, 0.0};
+        for (int ni = 0; ni < kF64NI; ++ni) acc[mi][ni] = d4{0.0, 0.0, 0.0, 0.0};
     const StoredOp aop{storage, toff, tcls, tscl, Nt, nb, k + rt, (int64_t)br * kB};
     const StoredOp bop{storage, toff, tcls, tscl, Nt, nb, k, (int64_t)bc * kB};
     mixed_mainloop(acc, aop, bop, nb, kbeg, kend, lds);
@@ -273,13 +330,20 @@ __global__ __launch_bounds__(kGemmThreads, 2) void mxp_gemm_f64_kernel(
         out = partial + ((int64_t)split * nblocks + b) * kB * kB;
         ldo = kB;
     }
+    // element v of block (mi, ni): row 64 wm + 16 mi + l % 16, column
+    // 32 wn + 16 ni + l / 16 + 4 v (the transposed-block layout of the
+    // binary64 kernels)
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wm = wave & 1, wn = wave >> 1;
 #pragma unroll
-    for (int mi = 0; mi < Tl::MI; ++mi)
+    for (int mi = 0; mi < kF64MI; ++mi)
 #pragma unroll
-        for (int ni = 0; ni < Tl::NI; ++ni)
+        for (int ni = 0; ni < kF64NI; ++ni)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                double* p = out + (int64_t)acc_col<kB, kB>(ni, v) * ldo + acc_row<kB, kB>(mi);
+                const int row = wm * 64 + mi * 16 + (lane & 15);
+                const int col = wn * 32 + ni * 16 + (lane >> 4) + 4 * v;
+                double* p = out + (int64_t)col * ldo + row;
                 if (splits == 1)
                     *p -= acc[mi][ni][v];
                 else
@@ -822,20 +886,21 @@ __global__ __launch_bounds__(kGemmThreads, 2) void mxp_gemm_split_kernel(
 }  // namespace
 
 // Split count of an FP64 group launch: the forward panel's time model
-// (rounds of 512 resident workgroups at the FP64 MFMA rate, plus the
-// partial blocks' traffic), each split keeping >= 1024 of K and the
-// partials within `cap` doubles.
+// (rounds of 256 resident workgroups, one 512-thread workgroup per CU, at
+// the FP64 MFMA rate, plus the partial blocks' traffic), each split keeping
+// >= 1024 of K and the partials within `cap` doubles.
 static int mxp_f64_splits(int64_t nblocks, int64_t K, size_t cap) {
     int64_t smax = K / 1024;
     if (smax > 16) smax = 16;
     while (smax > 1 && (size_t)smax * nblocks * kB * kB > cap) --smax;
     if (smax <= 1) return 1;
-    const double slot_flops = 78.6e12 / 512;
+    const int64_t slots = 256;
+    const double slot_flops = 78.6e12 / slots;
     const double blk_bytes = (double)kB * kB * sizeof(double);
     double best = 1e300;
     int bests = 1;
     for (int64_t s = 1; s <= smax; ++s) {
-        const double rounds = (double)((nblocks * s + 511) / 512);
+        const double rounds = (double)((nblocks * s + slots - 1) / slots);
         double t = rounds * (2.0 * kB * kB * ((double)K / s)) / slot_flops;
         if (s > 1) t += 3.0 * s * nblocks * blk_bytes / 5e12;
         if (t < best * 0.97) {
@@ -856,7 +921,7 @@ hipError_t launch_mxp_gemm_f64(hipStream_t s, double* W, int Nt, int nb, int k, 
     const int64_t K0 = (int64_t)nbeg * nb, K1 = (int64_t)nend * nb, K = K1 - K0;
     const int splits = mxp_f64_splits(total, K, partial_cap);
     const int64_t kchunk = (((K + splits - 1) / splits + 15) / 16) * 16;
-    hipLaunchKernelGGL(mxp_gemm_f64_kernel, dim3((unsigned)(total * splits)), dim3(kGemmThreads), 0,
+    hipLaunchKernelGGL(mxp_gemm_f64_kernel, dim3((unsigned)(total * splits)), dim3(kF64Threads), 0,
                        s, W, Nt, nb, k, K0, K1, rows, nrows, diag ? 1 : 0, storage, toff, tcls, tscl,
                        splits, kchunk, partial);
     hipError_t e = hipGetLastError();

@@ -121,7 +121,10 @@ typedef struct {
 } tc_ooc_stats;
 
 /* Tiles stored before lower tile (i,j), i >= j, in packed lower order:
- * j*Nt - j*(j-1)/2 + (i-j). Returns -1 if the indices are out of range. */
+ * j*Nt - j*(j-1)/2 + (i-j) (Section III-A: the matrix as tiles A_ij, of
+ * which the left-looking factorization reads and writes the lower
+ * triangle, column of tiles by column of tiles). Returns -1 if the indices
+ * are out of range. */
 int64_t tc_tile_offset(int32_t Nt, int32_t i, int32_t j);
 
 /* Pinned (page-locked) host memory of exactly `bytes` bytes for the
@@ -234,7 +237,8 @@ tc_status tc_factorize(tc_ctx *ctx, int64_t n, int32_t nb, const double *A, cons
                        tc_factor **L, tc_stats *stats);
 
 /* Solve Sigma X = B with the factor: B <- L^{-T} L^{-1} B (tiles used as
- * stored, upcast to binary64). For a mixed factor with ldb == n and
+ * stored, upcast to binary64). Section III-D: applying Sigma^{-1}, the
+ * y^T Sigma^{-1} y term of Eq. 1, through the Cholesky factor. For a mixed factor with ldb == n and
  * nrhs <= 16 the diagonal steps multiply by the stored L_kk^{-1} and
  * L_kk^{-T} (through an intermediate vector in the workspace); otherwise
  * they substitute with the diagonal tiles.
@@ -320,7 +324,8 @@ tc_status tc_factorize_ooc_mixed(tc_ctx *ctx, int64_t n, int32_t nb, const doubl
                                  tc_ooc_stats *stats);
 
 /* Copy the factor into L64 (device, packed lower tiles, binary64; each tile
- * upcast from its class) with the strict upper triangle of every diagonal
+ * upcast from its class, Section IV-C: one precision per tile, stored with
+ * its power-of-two scale) with the strict upper triangle of every diagonal
  * tile set to zero. For an all-FP64 factor L64 may be the factor's own
  * storage; otherwise it must be a separate buffer. */
 tc_status tc_factor_export(tc_ctx *ctx, const tc_factor *L, double *L64);

@@ -33,14 +33,14 @@ FP64_PEAK_TFLOPS = 78.6
 # HBM bytes per bulk panel-GEMM launch from the calibrated FETCH_SIZE and
 # WRITE_SIZE counter passes (profiles/panel_update_fp64_counters_n65536_nb1024.md),
 # valid for the kernel sources they were taken with.
-PANEL_TRAFFIC = {"bytes_per_launch": 3.1966e10,
-                 "sources_sha256": "3eadc1a05943b844d7c744a89ebedd8ead96dfcadddd4121edb5ab5755f45f61"}
+PANEL_TRAFFIC = {"bytes_per_launch": 3.2001e10,
+                 "sources_sha256": "a3a2e6f80fd4f414d3d6c84471ac64bceb8326259573d0e1ca6903d74fb9dc90"}
 
 
 def panel_traffic():
     import hashlib
     h = hashlib.sha256()
-    for f in ("gemm_f64.hip", "gemm_f64.hpp"):
+    for f in ("gemm_f64.hip", "gemm_f64.hpp", "common.hpp"):
         with open(os.path.join(ROOT, "paper_2410_09819_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return PANEL_TRAFFIC["bytes_per_launch"] if h.hexdigest() == PANEL_TRAFFIC["sources_sha256"] else None
@@ -723,6 +723,10 @@ def main():
     ap.add_argument("--mxp-eps", type=float, default=0.0,
                     help="target accuracy of the comparison's precision map (default: the mxp "
                          "workload's 1e-9; the refinement target stays 1e-9)")
+    ap.add_argument("--mxp-repeats", type=int, default=2,
+                    help="timed runs per variant of the mixed-precision comparison")
+    ap.add_argument("--mxp-warmup", type=int, default=1,
+                    help="untimed runs per variant of the mixed-precision comparison")
     ap.add_argument("--pmc-copy-gib", type=int, default=0,
                     help="before the steps, copy this many GiB device to device (the calibration "
                          "copy for HBM byte counters)")
@@ -759,7 +763,7 @@ def main():
             res = ooc_ablation(tc, si, dev)
         elif args.mxp_only:
             res = mxp_comparison(tc, si, dev, args.mxp_n or None, args.mxp_eps or None,
-                                 extra_eps=())
+                                 extra_eps=(), repeats=args.mxp_repeats, warmup=args.mxp_warmup)
         elif args.grad_only:
             res = grad_leg(tc, si, dev)
         elif args.ooc_only:

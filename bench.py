@@ -338,26 +338,41 @@ def grad_leg(tc, si, dev):
     th = w["theta_eval"]
     full = (th[0], th[1], nu, th[2])
     Lbar = torch.empty(tc.num_tiles(n, nb) * nb * nb, dtype=torch.float64, device=dev)
-    scratch = torch.empty(tc.adjoint_bytes(n, nb), dtype=torch.uint8, device=dev)
     A = torch.empty_like(Lbar)
+    # scratch of the full and the memory-short reverse sweep, for binary64
+    # and for mixed-precision factors
+    scr = {(m, sh): torch.empty((tc.adjoint_min_bytes if sh else tc.adjoint_bytes)(n, nb, m),
+                                dtype=torch.uint8, device=dev)
+           for m in (False, True) for sh in (False, True)}
+    mixed_tiles = {}
 
-    def once():
-        tc.matern_tiles(ctx, locs, full, nb, out=A, norms=False)
-        F = tc.factorize(ctx, A, n, nb, inplace=True)
+    def once(mixed=False, short=False):
+        if mixed:  # the FP32-mixed variant: {FP64, FP32} map at 1e-9 per evaluation
+            _, tf, fro = tc.matern_tiles(ctx, locs, full, nb, out=A, norms=True)
+            cm = tc.precision_map(n // nb, tf.cpu().numpy(), fro, 1e-9,
+                                  allowed=(tc.FP64, tc.FP32))
+            mixed_tiles.update(fp64=int(np.count_nonzero(cm == tc.FP64)),
+                               fp32=int(np.count_nonzero(cm == tc.FP32)))
+            F = tc.factorize(ctx, A, n, nb, cmap=cm)
+        else:
+            tc.matern_tiles(ctx, locs, full, nb, out=A, norms=False)
+            F = tc.factorize(ctx, A, n, nb, inplace=True)
         ll = tc.loglik_seed(ctx, F, y, Lbar)
-        st = tc.factor_adjoint(ctx, F, Lbar, scratch=scratch)
+        st = tc.factor_adjoint(ctx, F, Lbar, scratch=scr[(mixed, short)])
         g = tc.matern_grad(ctx, locs, full, nb, Lbar)
         F.close()
         return ll, g, st
 
-    once()
-    torch.cuda.synchronize()
-    reps = 3
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        ll, g, st = once()
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / reps
+    def timed(mixed=False, short=False, reps=3):
+        once(mixed, short)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            ll, g, st = once(mixed, short)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps, ll, g, st
+
+    dt, ll, g, st = timed()
     fwd = n ** 3 / 3.0
     out = {"workload": "loglik + gradient, n=%d nb=%d, Matern nu=%g, 4000 base points translated, "
                        "theta=(%g, %g, %g)" % (n, nb, nu, th[0], th[1], th[2]),
@@ -366,8 +381,28 @@ def grad_leg(tc, si, dev):
            "reverse_sweep_tflops": st.flops_total / (st.ms_total * 1e-3) / 1e12,
            "reverse_panel_tflops": (st.gemm_flops / (st.ms_gemm * 1e-3) / 1e12
                                     if st.ms_gemm > 0 else None),
-           "forward_plus_reverse_tflops": (fwd + st.flops_total) / dt / 1e12}
-    del A, Lbar, scratch
+           "forward_plus_reverse_tflops": (fwd + st.flops_total) / dt / 1e12,
+           "scratch_bytes": tc.adjoint_bytes(n, nb)}
+    # memory-short reverse sweep (no transposed copy of Abar): same gradient
+    dts, lls, gs, sts = timed(short=True, reps=2)
+    out["memory_short"] = {
+        "s_per_eval": dts, "reverse_sweep_ms": sts.ms_total,
+        "reverse_panel_tflops": (sts.gemm_flops / (sts.ms_gemm * 1e-3) / 1e12
+                                 if sts.ms_gemm > 0 else None),
+        "scratch_bytes": tc.adjoint_min_bytes(n, nb),
+        "grad_equal_to_full_form": bool(np.array_equal(gs, g))}
+    # FP32-mixed variant, full and memory-short sweeps
+    dtm, llm, gm, stm = timed(mixed=True, reps=2)
+    dtms, _, gms, stms = timed(mixed=True, short=True, reps=2)
+    out["fp32_mixed"] = {
+        "map": "{FP64, FP32} at target 1e-9 (Section IV-C)", "tiles": dict(mixed_tiles),
+        "s_per_eval": dtm, "loglik": llm, "grad": [float(v) for v in gm],
+        "grad_max_rel_diff_vs_fp64": float(np.max(np.abs(gm - g) / np.abs(g))),
+        "reverse_sweep_ms": stm.ms_total, "scratch_bytes": tc.adjoint_bytes(n, nb, True),
+        "memory_short": {"s_per_eval": dtms, "reverse_sweep_ms": stms.ms_total,
+                         "scratch_bytes": tc.adjoint_min_bytes(n, nb, True),
+                         "grad_equal_to_full_form": bool(np.array_equal(gms, gm))}}
+    del A, Lbar, scr
     torch.cuda.empty_cache()
     return out
 

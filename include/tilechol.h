@@ -341,16 +341,23 @@ tc_status tc_factor_export(tc_ctx *ctx, const tc_factor *L, double *L64);
 /* With z = L^{-1} y and alpha = L^{-T} z: *loglik = -n/2 log(2 pi) -
  * sum_i log L_ii - 1/2 z^T z (host), and Lbar (device, packed lower tiles
  * (n, nb), binary64, overwritten, strict upper triangle of the diagonal
- * tiles zero) receives dl/dL = tril(alpha z^T) - diag(1 / L_ii).
+ * tiles zero) receives dl/dL = tril(alpha z^T) - diag(1 / L_ii); Lbar NULL:
+ * only *loglik (no seed written).
  * y: device, n binary64. L: any factor (the solves read mixed-precision
  * tiles upcast to binary64). */
 tc_status tc_loglik_seed(tc_ctx *ctx, const tc_factor *L, const double *y, double *Lbar,
                          double *loglik);
 
-/* Bytes of device scratch tc_factor_adjoint needs (about the size of the
- * factor plus two tile columns; mixed != 0 adds room for the binary64
- * upcast of a mixed-precision factor); 0 for an invalid shape. */
+/* Bytes of device scratch tc_factor_adjoint needs in its full form (about
+ * the size of the factor plus two tile columns; mixed != 0 adds room for
+ * the binary64 upcast of a mixed-precision factor); 0 for an invalid shape. */
 size_t tc_adjoint_bytes(int64_t n, int32_t nb, int32_t mixed);
+
+/* Bytes of device scratch for the memory-short form of tc_factor_adjoint
+ * (three tile columns plus the split-K partial sums, which the panel
+ * products cap at 512 MiB; mixed != 0 adds one decoded tile column); 0 for
+ * an invalid shape. */
+size_t tc_adjoint_min_bytes(int64_t n, int32_t nb, int32_t mixed);
 
 /* Reverse sweep of the tile Cholesky. On input Lbar (device, packed lower
  * tiles, binary64) holds d(phi)/dL for a scalar phi of the factor (lower
@@ -362,8 +369,16 @@ size_t tc_adjoint_bytes(int64_t n, int32_t nb, int32_t mixed);
  * binary64 and the sweep is the exact reverse of the binary64 Cholesky at
  * that factor (an approximation of the gradient at the accuracy of the
  * precision map).
- * scratch: device buffer of at least tc_adjoint_bytes(n, nb, mixed) bytes,
- * mixed = whether L is a mixed-precision factor.
+ * scratch: device buffer, mixed = whether L is a mixed-precision factor.
+ * With at least tc_adjoint_bytes(n, nb, mixed) bytes the sweep keeps a
+ * transposed copy of every Abar tile for the later panel products (and the
+ * binary64 upcast of a mixed factor). With less, but at least
+ * tc_adjoint_min_bytes(n, nb, mixed), it runs in its memory-short form:
+ * the panel products read Abar's transposed tiles from Lbar itself, and a
+ * mixed factor's tiles are decoded to binary64 again, one tile column at a
+ * time, when the sweep reaches that column (recomputed, not stored).
+ * Both forms give the same Abar bit for bit; the short form is slower
+ * (strided reads of the transposed tiles). Fewer bytes: TC_ENOMEM.
  * stats: NULL or filled (ms_total, flops_total; ms_gemm, gemm_flops and
  * gemm_launches for the panel GEMMs when the context is timed). */
 tc_status tc_factor_adjoint(tc_ctx *ctx, const tc_factor *L, double *Lbar, void *scratch,

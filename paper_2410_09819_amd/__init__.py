@@ -126,6 +126,7 @@ def lib():
         "tc_factor_destroy": (_i32, [_vp]),
         "tc_loglik_seed": (_i32, [_vp, _vp, _vp, _vp, ctypes.POINTER(ctypes.c_double)]),
         "tc_adjoint_bytes": (_sz, [_i64, _i32, _i32]),
+        "tc_adjoint_min_bytes": (_sz, [_i64, _i32, _i32]),
         "tc_factor_adjoint": (_i32, [_vp, _vp, _vp, _vp, _sz, ctypes.POINTER(Stats)]),
         "tc_matern_grad": (_i32, [_vp, _i64, _i32, _vp, ctypes.POINTER(Matern), _vp,
                                   ctypes.POINTER(ctypes.c_double)]),
@@ -460,24 +461,32 @@ def export(ctx: Context, F: Factor, out=None):
 # --- log-likelihood gradient (reverse mode through the tile Cholesky) ------
 
 def adjoint_bytes(n: int, nb: int, mixed: bool = False) -> int:
+    """Scratch bytes of the full form of the reverse sweep."""
     return lib().tc_adjoint_bytes(n, nb, 1 if mixed else 0)
 
 
-def loglik_seed(ctx: Context, F: Factor, y, Lbar) -> float:
+def adjoint_min_bytes(n: int, nb: int, mixed: bool = False) -> int:
+    """Scratch bytes of the memory-short form of the reverse sweep."""
+    return lib().tc_adjoint_min_bytes(n, nb, 1 if mixed else 0)
+
+
+def loglik_seed(ctx: Context, F: Factor, y, Lbar=None) -> float:
     """Eq. 1's log-likelihood from the factor and y (device float64, n);
-    fills Lbar (device, packed lower tiles) with dl/dL."""
+    fills Lbar (device, packed lower tiles) with dl/dL unless it is None."""
     assert y.is_contiguous() and y.numel() == F.n
     out = ctypes.c_double(0.0)
-    _check(lib().tc_loglik_seed(ctx.handle, F.handle, y.data_ptr(), Lbar.data_ptr(),
-                                ctypes.byref(out)))
+    _check(lib().tc_loglik_seed(ctx.handle, F.handle, y.data_ptr(),
+                                None if Lbar is None else Lbar.data_ptr(), ctypes.byref(out)))
     return out.value
 
 
-def factor_adjoint(ctx: Context, F: Factor, Lbar, scratch=None) -> Stats:
+def factor_adjoint(ctx: Context, F: Factor, Lbar, scratch=None, short: bool = False) -> Stats:
     """In place: Lbar (dphi/dL, packed lower tiles) <- dphi/dA (lower
-    triangle). Returns the sweep's statistics."""
+    triangle). Returns the sweep's statistics. Without a scratch buffer one
+    is allocated: the full form's size, or the memory-short form's with
+    short=True (the library picks the form from the scratch size)."""
     import torch
-    nbytes = adjoint_bytes(F.n, F.nb, F.mixed)
+    nbytes = (adjoint_min_bytes if short else adjoint_bytes)(F.n, F.nb, F.mixed)
     if scratch is None:
         scratch = torch.empty(nbytes, dtype=torch.uint8, device=Lbar.device)
     st = Stats()
@@ -500,6 +509,16 @@ def matern_grad(ctx: Context, locs, theta, nb: int, Abar):
 def _autograd_function():
     import torch
 
+    def make_factor(ctx, locs, full, nb, cm, A=None):
+        """Factor of the covariance tiles A (generated when None): binary64
+        in place, or mixed under the map cm."""
+        n = locs.shape[0]
+        if A is None:
+            A, _, _ = matern_tiles(ctx, locs, full, nb, norms=False)
+        if cm is None:
+            return factorize(ctx, A, n, nb, inplace=True)
+        return factorize(ctx, A, n, nb, cmap=cm)
+
     class MaternLogLik(torch.autograd.Function):
         """l(theta) of Eq. 1 for the Matern covariance with nugget, theta =
         (sigma2, range, nugget) as a float64 tensor, nu fixed. Forward:
@@ -507,35 +526,63 @@ def _autograd_function():
         seed. Backward: the blocked reverse sweep and the contraction with
         the covariance derivatives. With eps set, the factorization uses the
         {FP64, FP32} precision map at target accuracy eps (Section IV-C) and
-        the gradient is that of the mixed-precision factor."""
+        the gradient is that of the mixed-precision factor.
+
+        memory: "store" keeps the factor and the seed dl/dL (a binary64 copy
+        of the lower triangle) from forward to backward and sweeps in the
+        full form; "recompute" keeps neither: backward regenerates the
+        covariance tiles, factorizes again under the same map, seeds, and
+        sweeps in the memory-short form (device memory of about the factor
+        plus one triangle plus a few tile columns at its peak, none between
+        the passes, for one more factorization); "auto" takes "recompute"
+        when the free device memory at forward time cannot hold what
+        "store" needs."""
 
         @staticmethod
-        def forward(fctx, theta, locs, y, nu, nb, ctx, eps=None):
+        def forward(fctx, theta, locs, y, nu, nb, ctx, eps=None, memory="store"):
+            if memory not in ("store", "recompute", "auto"):
+                raise ValueError("memory must be 'store', 'recompute' or 'auto'")
             th = [float(v) for v in theta.detach().cpu().tolist()]
             n = locs.shape[0]
             full = (th[0], th[1], float(nu), th[2])
-            if eps is None:
-                A, _, _ = matern_tiles(ctx, locs, full, nb, norms=False)
-                F = factorize(ctx, A, n, nb, inplace=True)
-            else:
+            cm, A = None, None
+            if eps is not None:
                 A, tf, fro = matern_tiles(ctx, locs, full, nb, norms=True)
                 cm = precision_map(n // nb, tf.cpu().numpy(), fro, eps, allowed=(FP64, FP32))
-                F = factorize(ctx, A, n, nb, cmap=cm)
-                del A
-            Lbar = torch.empty(num_tiles(n, nb) * nb * nb, dtype=torch.float64, device=locs.device)
-            ll = loglik_seed(ctx, F, y, Lbar)
-            fctx.state = (ctx, F, Lbar, locs, full, nb)
+            F = make_factor(ctx, locs, full, nb, cm, A)
+            del A
+            tri = num_tiles(n, nb) * nb * nb * 8
+            if memory == "auto":  # room for the seed and the full sweep's scratch?
+                torch.cuda.empty_cache()
+                free, _ = torch.cuda.mem_get_info(locs.device)
+                memory = "store" if free >= tri + adjoint_bytes(n, nb, F.mixed) else "recompute"
+            if memory == "store":
+                Lbar = torch.empty(tri // 8, dtype=torch.float64, device=locs.device)
+                ll = loglik_seed(ctx, F, y, Lbar)
+                fctx.state = (ctx, F, Lbar, locs, y, full, nb, cm)
+            else:
+                ll = loglik_seed(ctx, F, y, None)
+                F.close()
+                fctx.state = (ctx, None, None, locs, y, full, nb, cm)
+            fctx.memory = memory
             return torch.tensor(ll, dtype=torch.float64, device=theta.device)
 
         @staticmethod
         def backward(fctx, gout):
-            ctx, F, Lbar, locs, full, nb = fctx.state
+            ctx, F, Lbar, locs, y, full, nb, cm = fctx.state
             fctx.state = None
-            factor_adjoint(ctx, F, Lbar)
+            if F is None:  # recompute: factor and seed again, short sweep
+                F = make_factor(ctx, locs, full, nb, cm)
+                Lbar = torch.empty(num_tiles(F.n, nb) * nb * nb, dtype=torch.float64,
+                                   device=locs.device)
+                loglik_seed(ctx, F, y, Lbar)
+                factor_adjoint(ctx, F, Lbar, short=True)
+            else:
+                factor_adjoint(ctx, F, Lbar)
             g = matern_grad(ctx, locs, full, nb, Lbar)
             F.close()
             grad = torch.from_numpy(g).to(device=gout.device, dtype=gout.dtype) * gout
-            return grad, None, None, None, None, None, None
+            return grad, None, None, None, None, None, None, None
 
     return MaternLogLik
 
@@ -543,12 +590,13 @@ def _autograd_function():
 _MLL = None
 
 
-def matern_loglik(theta, locs, y, nu: float, nb: int, ctx: Context, eps=None):
+def matern_loglik(theta, locs, y, nu: float, nb: int, ctx: Context, eps=None,
+                  memory: str = "store"):
     """Differentiable log-likelihood (torch.autograd): see MaternLogLik."""
     global _MLL
     if _MLL is None:
         _MLL = _autograd_function()
-    return _MLL.apply(theta, locs, y, nu, nb, ctx, eps)
+    return _MLL.apply(theta, locs, y, nu, nb, ctx, eps, memory)
 
 
 def __getattr__(name):

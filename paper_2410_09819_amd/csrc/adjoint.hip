@@ -14,6 +14,13 @@
 // Every contraction is the FP64 MFMA "A B^T" main loop: transposed copies
 // of L's column panel and of Abar's columns (kept for the later panels)
 // make all operands column-major with unit row stride.
+//
+// Memory-short form: no transposed copy of Abar is kept. The panel (a)
+// reads the chunks of S_mk with k > m as Abar_km transposed straight from
+// Lbar (each 16-column K chunk of the operand loaded row by row and written
+// transposed into LDS, the same LDS image as the copy gives), and H_m
+// lives in a one-tile-column array. Its products equal those of the full
+// form bit for bit: same operand values, same chunking and MFMA order.
 #include "gemm_f64.hpp"
 
 namespace tc {
@@ -39,6 +46,157 @@ struct ColOp {
     int64_t ld;
     __device__ const double* operator()(int64_t kk) const { return p + kk * ld; }
 };
+
+// Memory-short operand of (a): chunk (row block r0 of tile row m, K index
+// kk). Sets `tr` when the chunk is Abar_km with k > m, read transposed:
+// element (row, col) at p + row * nb + col; otherwise p + col * nb + row.
+struct SymOpShort {
+    const double* Ab;  // Abar (lower packed tiles, in place in Lbar)
+    const double* Hd;  // H_m for tile row m at Hd + m * nb^2
+    int64_t Nt, nb, nb2, m, n, r0;
+    __device__ const double* operator()(int64_t kk, bool& tr) const {
+        const int64_t q = kk / nb;
+        const int64_t k = n + 1 + q;
+        const int64_t j = kk - q * nb;
+        tr = k > m;
+        if (k < m) return Ab + tile_off(Nt, m, k) * nb2 + j * nb + r0;
+        if (k == m) return Hd + m * nb2 + j * nb + r0;
+        return Ab + tile_off(Nt, k, m) * nb2 + r0 * nb + j;
+    }
+};
+
+// mfma_mainloop<kPB, kPB> with the A operand of SymOpShort: a chunk read
+// transposed is loaded as 128 rows of 16 consecutive K values (eight
+// threads per 128-byte row run) and stored column by column into the
+// k-major LDS tile, so the MFMA reads are those of the natural chunks.
+__device__ __forceinline__ void sym_short_mainloop(d4 (&acc)[kPB / 32][kPB / 32],
+                                                   const SymOpShort& aop, const ColOp& bop,
+                                                   int64_t ld, int64_t kbeg, int64_t kend,
+                                                   double* lds) {
+    using T = MfmaTile<kPB, kPB>;
+    if (kbeg >= kend) return;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int wm = wave & 1, wn = wave >> 1;
+    double* As = lds;
+    double* Bs = lds + 2 * T::BK * T::LDA;
+
+    int64_t a_goff[T::A_LOADS], t_goff[T::A_LOADS];
+    int a_soff[T::A_LOADS], t_soff[T::A_LOADS];
+#pragma unroll
+    for (int q = 0; q < T::A_LOADS; ++q) {
+        const int e = (q * kGemmThreads + tid) * 2;
+        const int col = e / kPB, row = e % kPB;
+        a_goff[q] = (int64_t)col * ld + row;
+        a_soff[q] = col * T::LDA + row;
+        const int e2 = q * kGemmThreads + tid;  // d2 index: row e2 / 8, columns 2 (e2 % 8) + {0, 1}
+        const int trow = e2 >> 3, tcol = (e2 & 7) * 2;
+        t_goff[q] = (int64_t)trow * ld + tcol;
+        t_soff[q] = tcol * T::LDA + trow;
+    }
+    int64_t b_goff[T::B_LOADS];
+    int b_soff[T::B_LOADS];
+#pragma unroll
+    for (int q = 0; q < T::B_LOADS; ++q) {
+        const int e = (q * kGemmThreads + tid) * 2;
+        const int col = e / kPB, row = e % kPB;
+        b_goff[q] = (int64_t)col * ld + row;
+        b_soff[q] = col * T::LDB + row;
+    }
+
+    d2 ra[T::A_LOADS], rb[T::B_LOADS];
+    bool rtr = false;  // the chunk in ra was read transposed
+    auto gload = [&](int64_t kk) {
+        bool tr;
+        const double* pa = aop(kk, tr);
+        const double* pb = bop(kk);
+        rtr = tr;
+        if (tr) {
+#pragma unroll
+            for (int q = 0; q < T::A_LOADS; ++q)
+                ra[q] = *reinterpret_cast<const d2*>(pa + t_goff[q]);
+        } else {
+#pragma unroll
+            for (int q = 0; q < T::A_LOADS; ++q)
+                ra[q] = *reinterpret_cast<const d2*>(pa + a_goff[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < T::B_LOADS; ++q) rb[q] = *reinterpret_cast<const d2*>(pb + b_goff[q]);
+    };
+    auto sstore = [&](int buf) {
+        double* as = As + buf * T::BK * T::LDA;
+        double* bs = Bs + buf * T::BK * T::LDB;
+        if (rtr) {
+#pragma unroll
+            for (int q = 0; q < T::A_LOADS; ++q) {
+                as[t_soff[q]] = ra[q].x;
+                as[t_soff[q] + T::LDA] = ra[q].y;
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < T::A_LOADS; ++q) *reinterpret_cast<d2*>(as + a_soff[q]) = ra[q];
+        }
+#pragma unroll
+        for (int q = 0; q < T::B_LOADS; ++q) *reinterpret_cast<d2*>(bs + b_soff[q]) = rb[q];
+    };
+
+    gload(kbeg);
+    sstore(0);
+    __syncthreads();
+    int buf = 0;
+    const int li = lane & 15, lk = lane >> 4;
+    for (int64_t kk = kbeg; kk < kend; kk += T::BK) {
+        const bool more = kk + T::BK < kend;
+        if (more) gload(kk + T::BK);
+        const double* as = As + buf * T::BK * T::LDA + wm * (kPB / 2) + li;
+        const double* bs = Bs + buf * T::BK * T::LDB + wn * (kPB / 2) + li;
+#pragma unroll
+        for (int ks = 0; ks < T::BK / 4; ++ks) {
+            const int k = ks * 4 + lk;
+            double a[T::MI], b[T::NI];
+#pragma unroll
+            for (int mi = 0; mi < T::MI; ++mi) a[mi] = as[k * T::LDA + mi * 16];
+#pragma unroll
+            for (int ni = 0; ni < T::NI; ++ni) b[ni] = bs[k * T::LDB + ni * 16];
+#pragma unroll
+            for (int mi = 0; mi < T::MI; ++mi)
+#pragma unroll
+                for (int ni = 0; ni < T::NI; ++ni)
+                    acc[mi][ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[ni], a[mi], acc[mi][ni],
+                                                                      0, 0, 0);
+        }
+        if (more) sstore(buf ^ 1);
+        __syncthreads();
+        buf ^= 1;
+    }
+}
+
+// Output block of (a): subtract into Lbar (one split) or store the split's
+// partial sums.
+__device__ __forceinline__ void panel_store(const d4 (&acc)[kPB / 32][kPB / 32],
+                                            double* __restrict__ Lb, double* __restrict__ partial,
+                                            int Nt, int nb, int n, int splits, int split,
+                                            int64_t rt, int br, int bc) {
+    using Tl = MfmaTile<kPB, kPB>;
+    const int64_t R = Nt - n - 1;
+    const int64_t nb2 = (int64_t)nb * nb;
+    double* out = splits == 1 ? Lb + tile_off(Nt, n + 1 + rt, n) * nb2
+                              : partial + ((int64_t)split * R + rt) * nb2;
+    out += (int64_t)bc * kPB * nb + br * kPB;
+#pragma unroll
+    for (int mi = 0; mi < Tl::MI; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < Tl::NI; ++ni)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                double* p = out + (int64_t)acc_col<kPB, kPB>(ni, v) * nb + acc_row<kPB, kPB>(mi);
+                if (splits == 1)
+                    *p -= acc[mi][ni][v];
+                else
+                    *p = acc[mi][ni][v];
+            }
+}
 
 // (a): output tiles (n+1+rt, n), rt < R = Nt-n-1, all nb/128 x nb/128 blocks.
 // PL: nb x R*nb column-major (ld nb), PL(c, kk) = L_{n+1+kk/nb, n}(kk % nb, c).
@@ -68,22 +226,38 @@ __global__ __launch_bounds__(kGemmThreads, 2) void adj_panel_kernel(
     const SymOp aop{Lb, Tt, Nt, nb, nb2, n + 1 + rt, n, (int64_t)br * kPB};
     const ColOp bop{PL + (int64_t)bc * kPB, nb};
     mfma_mainloop<kPB, kPB>(acc, aop, bop, nb, kbeg, kend, lds);
+    panel_store(acc, Lb, partial, Nt, nb, n, splits, split, rt, br, bc);
+}
 
-    double* out = splits == 1 ? Lb + tile_off(Nt, n + 1 + rt, n) * nb2
-                              : partial + ((int64_t)split * R + rt) * nb2;
-    out += (int64_t)bc * kPB * nb + br * kPB;
+// (a) in the memory-short form: Hd holds H_m per tile row, Abar_km^T is
+// read from Lbar itself. Same blocks, splits and output as adj_panel_kernel.
+__global__ __launch_bounds__(kGemmThreads, 2) void adj_panel_short_kernel(
+    double* __restrict__ Lb, const double* __restrict__ Hd, const double* __restrict__ PL, int Nt,
+    int nb, int n, int splits, int64_t nblocks, int64_t kchunk, double* __restrict__ partial) {
+    using Tl = MfmaTile<kPB, kPB>;
+    __shared__ double lds[Tl::LDS_DOUBLES];
+    const int64_t logical = xcd_remap(blockIdx.x, nblocks * splits);
+    const int split = (int)(logical / nblocks);
+    const int64_t b = logical - (int64_t)split * nblocks;
+    const int T = nb / kPB;
+    const int64_t rt = b / (T * T);
+    const int w = (int)(b - rt * T * T);
+    const int br = w / T, bc = w % T;
+    const int64_t R = Nt - n - 1;
+    const int64_t nb2 = (int64_t)nb * nb;
+    const int64_t K = R * nb;
+    const int64_t kbeg = (int64_t)split * kchunk;
+    const int64_t kend = kbeg + kchunk < K ? kbeg + kchunk : K;
+
+    d4 acc[Tl::MI][Tl::NI];
 #pragma unroll
     for (int mi = 0; mi < Tl::MI; ++mi)
 #pragma unroll
-        for (int ni = 0; ni < Tl::NI; ++ni)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                double* p = out + (int64_t)acc_col<kPB, kPB>(ni, v) * nb + acc_row<kPB, kPB>(mi);
-                if (splits == 1)
-                    *p -= acc[mi][ni][v];
-                else
-                    *p = acc[mi][ni][v];
-            }
+        for (int ni = 0; ni < Tl::NI; ++ni) acc[mi][ni] = d4{0.0, 0.0, 0.0, 0.0};
+    const SymOpShort aop{Lb, Hd, Nt, nb, nb2, n + 1 + rt, n, (int64_t)br * kPB};
+    const ColOp bop{PL + (int64_t)bc * kPB, nb};
+    sym_short_mainloop(acc, aop, bop, nb, kbeg, kend, lds);
+    panel_store(acc, Lb, partial, Nt, nb, n, splits, split, rt, br, bc);
 }
 
 __global__ void adj_panel_reduce_kernel(double* __restrict__ Lb, int Nt, int nb, int n, int splits,
@@ -275,14 +449,19 @@ int adj_panel_splits(int Nt, int nb, int n) {
     return bests;
 }
 
-hipError_t launch_adj_panel(hipStream_t s, double* Lb, const double* Tt, const double* PL, int Nt,
-                            int nb, int n, int splits, double* partial) {
+hipError_t launch_adj_panel(hipStream_t s, double* Lb, const double* Tt, const double* Hd,
+                            const double* PL, int Nt, int nb, int n, int splits, double* partial) {
     const int64_t W = adj_panel_blocks(Nt, nb, n);
     if (W == 0) return hipSuccess;
+    if ((Tt == nullptr) == (Hd == nullptr)) return hipErrorInvalidValue;
     const int64_t K = (int64_t)(Nt - n - 1) * nb;
     const int64_t kchunk = (((K + splits - 1) / splits + 15) / 16) * 16;
-    hipLaunchKernelGGL(adj_panel_kernel, dim3((unsigned)(W * splits)), dim3(kGemmThreads), 0, s, Lb,
-                       Tt, PL, Nt, nb, n, splits, W, kchunk, partial);
+    if (Tt)
+        hipLaunchKernelGGL(adj_panel_kernel, dim3((unsigned)(W * splits)), dim3(kGemmThreads), 0, s,
+                           Lb, Tt, PL, Nt, nb, n, splits, W, kchunk, partial);
+    else
+        hipLaunchKernelGGL(adj_panel_short_kernel, dim3((unsigned)(W * splits)), dim3(kGemmThreads),
+                           0, s, Lb, Hd, PL, Nt, nb, n, splits, W, kchunk, partial);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || splits == 1) return e;
     const int64_t elems = (int64_t)(Nt - n - 1) * nb * nb / 2;

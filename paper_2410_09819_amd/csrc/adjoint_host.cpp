@@ -9,6 +9,14 @@
 //   Abar_nn = tril(H), diagonal halved.
 // Scratch (caller's device buffer): Tt (packed lower tiles), PL, Tb (one
 // column panel each), five nb x nb tiles, and the split-K partial sums.
+//
+// Memory-short form, taken when the scratch holds less than the full form
+// needs: Abar stays only in Lbar (the panel reads Abar_km^T from there),
+// the H_m tiles go to a one-column array instead of Tt's diagonal, and a
+// mixed-precision factor is not upcast as a whole: each column's tiles are
+// decoded to binary64 again when the sweep reaches that column. Scratch
+// shrinks from about one factor (two, for a mixed factor) to about three
+// tile columns plus the partial sums; Abar is the same bit for bit.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -24,7 +32,11 @@ using namespace tc::host;
 namespace {
 
 struct AdjLayout {
-    size_t tt, pl, tb, sq, part, l64, total;  // offsets in doubles, total in bytes
+    // offsets in doubles, total in bytes; full form: tt (packed lower
+    // tiles) and l64 (mixed upcast); memory-short form: hd (one tile per
+    // tile row) and lc (one decoded column, mixed)
+    size_t tt, pl, tb, sq, part, l64, total;
+    bool short_form;
 };
 
 size_t adj_partial_doubles(int Nt, int nb) {
@@ -43,19 +55,24 @@ size_t adj_partial_doubles(int Nt, int nb) {
     return mx;
 }
 
-AdjLayout adj_layout(int64_t n, int nb, bool mixed) {
+AdjLayout adj_layout(int64_t n, int nb, bool mixed, bool short_form) {
     const int64_t Nt = n / nb;
     const int64_t nb2 = (int64_t)nb * nb;
     const int64_t panel = std::max<int64_t>(Nt - 1, 1) * nb2;
+    // full: every Abar tile transposed; short: H_m per tile row
+    const size_t tt_tiles = short_form ? (size_t)Nt : (size_t)(Nt * (Nt + 1) / 2);
+    // a mixed-precision factor is swept in binary64: its upcast tiles, all
+    // of them (full) or one column at a time (short)
+    const size_t l64_tiles = !mixed ? 0 : short_form ? (size_t)Nt : (size_t)(Nt * (Nt + 1) / 2);
     AdjLayout L;
+    L.short_form = short_form;
     L.tt = 0;
-    L.pl = L.tt + (size_t)(Nt * (Nt + 1) / 2) * nb2;
+    L.pl = L.tt + tt_tiles * nb2;
     L.tb = L.pl + panel;
     L.sq = L.tb + panel;
     L.part = L.sq + 5 * nb2;
     L.l64 = L.part + adj_partial_doubles((int)Nt, nb) + 32;
-    // a mixed-precision factor is swept in binary64: room for its upcast tiles
-    L.total = (L.l64 + (mixed ? (size_t)(Nt * (Nt + 1) / 2) * nb2 : 0)) * sizeof(double);
+    L.total = (L.l64 + l64_tiles * nb2) * sizeof(double);
     return L;
 }
 
@@ -72,7 +89,12 @@ extern "C" {
 
 size_t tc_adjoint_bytes(int64_t n, int32_t nb, int32_t mixed) {
     if (!valid_shape(n, nb)) return 0;
-    return adj_layout(n, nb, mixed != 0).total;
+    return adj_layout(n, nb, mixed != 0, false).total;
+}
+
+size_t tc_adjoint_min_bytes(int64_t n, int32_t nb, int32_t mixed) {
+    if (!valid_shape(n, nb)) return 0;
+    return adj_layout(n, nb, mixed != 0, true).total;
 }
 
 tc_status tc_factor_adjoint(tc_ctx* ctx, const tc_factor* F, double* Lbar, void* scratch,
@@ -81,10 +103,13 @@ tc_status tc_factor_adjoint(tc_ctx* ctx, const tc_factor* F, double* Lbar, void*
     if (F->info > 0) return fail(TC_EINVAL, "factor is not valid (factorization failed)");
     const int64_t n = F->n;
     const int nb = F->nb, Nt = F->Nt;
-    const AdjLayout Ly = adj_layout(n, nb, F->mixed);
+    AdjLayout Ly = adj_layout(n, nb, F->mixed, false);
+    if (scratch_bytes < Ly.total) Ly = adj_layout(n, nb, F->mixed, true);
     if (scratch_bytes < Ly.total)
         return fail(TC_ENOMEM, "adjoint scratch too small: need " + std::to_string(Ly.total) +
-                                   " bytes, have " + std::to_string(scratch_bytes));
+                                   " bytes (memory-short form) or " +
+                                   std::to_string(adj_layout(n, nb, F->mixed, false).total) +
+                                   ", have " + std::to_string(scratch_bytes));
     if (tc_status s = check_ws(ctx, n, nb)) return s;
     DeviceGuard g(ctx->device);
     hipStream_t st = ctx->stream;
@@ -99,11 +124,14 @@ tc_status tc_factor_adjoint(tc_ctx* ctx, const tc_factor* F, double* Lbar, void*
     double* P = W2 + nb2;
     double* Y = P + nb2;
     double* part = S + Ly.part;
+    const bool sf = Ly.short_form;
+    double* Tfull = sf ? nullptr : Tt;  // transposed Abar tiles (full form)
+    double* Hd = sf ? Tt : nullptr;     // H_m per tile row (memory-short form)
     const double* L = F->tiles;
-    if (F->mixed) {  // sweep the upcast factor
-        double* L64 = S + Ly.l64;
-        TC_HIP(tc::launch_export(st, factor_view(F), L64));
-        L = L64;
+    double* Lc = S + Ly.l64;  // one decoded column (memory-short form, mixed)
+    if (F->mixed && !sf) {    // sweep the upcast factor
+        TC_HIP(tc::launch_export(st, factor_view(F), Lc));
+        L = Lc;
     }
     const bool timed = (ctx->flags & 1u) != 0;
     while (timed && ctx->gemm_ev.size() < (size_t)2 * Nt) {
@@ -116,19 +144,25 @@ tc_status tc_factor_adjoint(tc_ctx* ctx, const tc_factor* F, double* Lbar, void*
     TC_HIP(hipEventRecord(ctx->ev0, st));
     for (int nn = Nt - 1; nn >= 0; --nn) {
         const int64_t R = Nt - nn - 1;
-        const double* Lnn = L + tc::tile_off(Nt, nn, nn) * nb2;
-        double* Lbnn = Lbar + tc::tile_off(Nt, nn, nn) * nb2;
+        const int64_t dg = tc::tile_off(Nt, nn, nn);
+        const double* Lnn = L + dg * nb2;  // column nn of L from here on
+        if (F->mixed && sf) {  // decode the column again (no stored upcast)
+            TC_HIP(tc::launch_export_range(st, factor_view(F), dg, R + 1, Lc));
+            Lnn = Lc;
+        }
+        double* Lbnn = Lbar + dg * nb2;
         TC_HIP(tc::launch_set_identity(st, X, nb));
         TC_HIP(tc::launch_trsm(st, X, Lnn, nb, nb, nb));  // X = L_nn^{-T}
         flops += (double)nb * nb * nb;
         if (R > 0) {
             const int64_t off = tc::tile_off(Nt, nn + 1, nn) * nb2;
             double* Lbp = Lbar + off;
-            double* Ttp = Tt + off;
-            TC_HIP(tc::launch_transpose_tiles(st, L + off, PL, nb, R, false));
+            // transposed Abar column: kept in Tt (full) or only for (c) in Tb
+            double* Ttp = sf ? Tb : Tt + off;
+            TC_HIP(tc::launch_transpose_tiles(st, Lnn + nb2, PL, nb, R, false));
             const int sp = tc::adj_panel_splits(Nt, nb, nn);
             if (timed) TC_HIP(hipEventRecord(ctx->gemm_ev[2 * launches], st));
-            TC_HIP(tc::launch_adj_panel(st, Lbar, Tt, PL, Nt, nb, nn, sp, part));
+            TC_HIP(tc::launch_adj_panel(st, Lbar, Tfull, Hd, PL, Nt, nb, nn, sp, part));
             if (timed) TC_HIP(hipEventRecord(ctx->gemm_ev[2 * launches + 1], st));
             ++launches;
             const double pf = 2.0 * (double)(R * nb) * nb * (double)(R * nb);
@@ -140,7 +174,7 @@ tc_status tc_factor_adjoint(tc_ctx* ctx, const tc_factor* F, double* Lbar, void*
             flops += 2.0 * (double)(R * nb) * nb * nb;
             TC_HIP(hipMemcpyAsync(Lbp, Tb, (size_t)R * nb2 * sizeof(double),
                                   hipMemcpyDeviceToDevice, st));
-            TC_HIP(tc::launch_transpose_tiles(st, Tb, Ttp, nb, R, false));
+            TC_HIP(tc::launch_transpose_tiles(st, Lbp, Ttp, nb, R, false));
             // Lbar_nn -= tril(sum_m Abar_mn^T L_mn)
             TC_HIP(tc::launch_adj_gemm(st, plain_mat(Lbnn, nb), plain_mat(Ttp, nb),
                                        plain_mat(PL, nb), nb, nb, R * nb, true, true, part));
@@ -154,7 +188,7 @@ tc_status tc_factor_adjoint(tc_ctx* ctx, const tc_factor* F, double* Lbar, void*
         TC_HIP(tc::launch_mirror_lower(st, P, nb));
         TC_HIP(tc::launch_adj_gemm(st, plain_mat(Y, nb), plain_mat(X, nb), plain_mat(P, nb), nb,
                                    nb, nb, false, false, part));
-        double* H = Tt + tc::tile_off(Nt, nn, nn) * nb2;
+        double* H = sf ? Hd + (int64_t)nn * nb2 : Tt + dg * nb2;
         TC_HIP(tc::launch_adj_gemm(st, plain_mat(H, nb), plain_mat(Y, nb), plain_mat(X, nb), nb,
                                    nb, nb, false, false, part));
         TC_HIP(tc::launch_finish_diag(st, H, Lbnn, nb));

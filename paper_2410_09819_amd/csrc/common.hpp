@@ -171,6 +171,9 @@ hipError_t launch_mxp_finalize(hipStream_t s, const double* W, int Nt, int nb, i
                                char* storage, const int64_t* toff, const uint8_t* tcls, int* tscl,
                                const int64_t* shoff, int* cscl);
 hipError_t launch_export(hipStream_t s, const TileView& L, double* out);
+// Tiles [t0, t0 + count) of the packed lower order as binary64 into out.
+hipError_t launch_export_range(hipStream_t s, const TileView& L, int64_t t0, int64_t count,
+                               double* out);
 
 // Refinement (ir.hip).
 size_t residual_partial_doubles(int Nt, int nb, int nrhs);
@@ -203,8 +206,10 @@ struct AdjGemmPlan {
     size_t partial_doubles;
 };
 // Lbar_mn -= sum_{k>n} S_mk L_kn for the tiles below (n, n) (see adjoint.hip).
-hipError_t launch_adj_panel(hipStream_t s, double* Lb, const double* Tt, const double* PL, int Nt,
-                            int nb, int n, int splits, double* partial);
+// Exactly one of Tt (transposed copies of Abar, H_m on the diagonal) and Hd
+// (memory-short form: H_m per tile row; Abar_km^T read from Lb) is non-null.
+hipError_t launch_adj_panel(hipStream_t s, double* Lb, const double* Tt, const double* Hd,
+                            const double* PL, int Nt, int nb, int n, int splits, double* partial);
 int64_t adj_panel_blocks(int Nt, int nb, int n);
 int adj_panel_splits(int Nt, int nb, int n);
 // C = A B^T (sub: C -= A B^T); A: M x K, B: N x K, all AdjMat with the same

@@ -510,16 +510,17 @@ __global__ __launch_bounds__(256) void logdet_kernel(TileView L, double* __restr
 // Factor tiles as binary64 (packed lower order), strict upper triangle of
 // diagonal tiles zero.
 constexpr int kExpStrips = 16;
-__global__ __launch_bounds__(256) void export_kernel(TileView L, double* __restrict__ out) {
+__global__ __launch_bounds__(256) void export_kernel(TileView L, int64_t t0,
+                                                     double* __restrict__ out) {
     const int nb = L.nb, Nt = L.Nt;
-    const int64_t t = blockIdx.y;
+    const int64_t t = t0 + blockIdx.y;
     int64_t j = 0;
     while (tile_off(Nt, Nt - 1, j) < t) ++j;
     const int64_t i = j + (t - tile_off(Nt, j, j));
     int cls, scale;
     const char* tile = view_tile(L, (int)i, (int)j, cls, scale);
     const int64_t per = (int64_t)nb * nb / kExpStrips;
-    double* o = out + t * (int64_t)nb * nb;
+    double* o = out + (int64_t)blockIdx.y * nb * nb;
     for (int64_t e = blockIdx.x * per + threadIdx.x; e < (blockIdx.x + 1) * per; e += 256) {
         const int64_t c = e / nb, r = e - c * nb;
         o[e] = (i == j && r < c) ? 0.0 : load_elem(tile, e, cls, scale);
@@ -639,10 +640,18 @@ hipError_t launch_logdet_partials(hipStream_t s, const TileView& L, double* part
     return hipGetLastError();
 }
 
-hipError_t launch_export(hipStream_t s, const TileView& L, double* out) {
+hipError_t launch_export_range(hipStream_t s, const TileView& L, int64_t t0, int64_t count,
+                               double* out) {
     const int64_t ntiles = (int64_t)L.Nt * (L.Nt + 1) / 2;
-    hipLaunchKernelGGL(export_kernel, dim3(kExpStrips, (unsigned)ntiles), dim3(256), 0, s, L, out);
+    if (t0 < 0 || count < 0 || t0 + count > ntiles) return hipErrorInvalidValue;
+    if (count == 0) return hipSuccess;
+    hipLaunchKernelGGL(export_kernel, dim3(kExpStrips, (unsigned)count), dim3(256), 0, s, L, t0,
+                       out);
     return hipGetLastError();
+}
+
+hipError_t launch_export(hipStream_t s, const TileView& L, double* out) {
+    return launch_export_range(s, L, 0, (int64_t)L.Nt * (L.Nt + 1) / 2, out);
 }
 
 }  // namespace tc

@@ -1027,7 +1027,7 @@ tc_status tc_logdet(tc_ctx* ctx, const tc_factor* F, double* out) {
 
 tc_status tc_loglik_seed(tc_ctx* ctx, const tc_factor* F, const double* y, double* Lbar,
                          double* loglik) {
-    if (!ctx || !F || !y || !Lbar || !loglik) return fail(TC_EINVAL, "NULL argument");
+    if (!ctx || !F || !y || !loglik) return fail(TC_EINVAL, "NULL argument");
     if (F->info > 0) return fail(TC_EINVAL, "factor is not valid (factorization failed)");
     if (tc_status s = check_ws(ctx, F->n, F->nb)) return s;
     DeviceGuard g(ctx->device);
@@ -1039,9 +1039,11 @@ tc_status tc_loglik_seed(tc_ctx* ctx, const tc_factor* F, const double* y, doubl
     double* alpha = z + n;
     TC_HIP(tc::launch_copy_cols(ctx->stream, z, n, y, n, n, 1));
     if (tc_status s = fwd_enqueue(ctx, F, z, n, 1, big, nullptr)) return s;
-    TC_HIP(tc::launch_copy_cols(ctx->stream, alpha, n, z, n, n, 1));
-    if (tc_status s = bwd_enqueue(ctx, F, alpha, n, 1, big, nullptr)) return s;
-    TC_HIP(tc::launch_loglik_seed(ctx->stream, view_of(F), alpha, z, Lbar, F->Nt, F->nb));
+    if (Lbar) {  // alpha = L^{-T} z only for the seed
+        TC_HIP(tc::launch_copy_cols(ctx->stream, alpha, n, z, n, n, 1));
+        if (tc_status s = bwd_enqueue(ctx, F, alpha, n, 1, big, nullptr)) return s;
+        TC_HIP(tc::launch_loglik_seed(ctx->stream, view_of(F), alpha, z, Lbar, F->Nt, F->nb));
+    }
     std::vector<double> zn;
     if (tc_status s = colnorms(ctx, z, n, n, 1, part, zn)) return s;
     double ld = 0.0;

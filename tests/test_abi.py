@@ -67,6 +67,26 @@ def test_sizes_and_validation():
     assert L.tc_version().startswith(b"tilechol")
 
 
+def test_adjoint_scratch_sizes():
+    """Full form: transposed copies of every Abar tile (+ the binary64
+    upcast of a mixed factor); memory-short form: H_m per tile row (+ one
+    decoded column). Both share three tile columns' worth of panels and
+    tiles and the same split-K partials, so their difference is exact."""
+    tc = _lib()
+    for n, nb in [(32768, 512), (4096, 256), (512, 512)]:
+        Nt = n // nb
+        tri = Nt * (Nt + 1) // 2 * nb * nb * 8
+        col = Nt * nb * nb * 8
+        full, short = tc.adjoint_bytes(n, nb), tc.adjoint_min_bytes(n, nb)
+        fullm, shortm = tc.adjoint_bytes(n, nb, True), tc.adjoint_min_bytes(n, nb, True)
+        assert full - short == tri - col
+        assert fullm - full == tri and shortm - short == col
+        assert short < full or Nt == 1
+    # the gradient workload: about 0.9 GiB instead of 4.8 GiB of scratch
+    assert tc.adjoint_min_bytes(32768, 512) < tc.adjoint_bytes(32768, 512) / 4
+    assert tc.adjoint_min_bytes(2000, 256) == 0 == tc.adjoint_bytes(2000, 256)
+
+
 def test_pack_unpack_roundtrip():
     tc = _lib()
     rng = np.random.default_rng(0)

@@ -19,6 +19,12 @@ What pins what:
     gradient equals central differences of the GPU log-likelihood within
     1e-4 relative (step 1e-6 relative: truncation ~1e-12, rounding of l
     divided by the step ~1e-6 relative).
+  * The memory-short form of the sweep (scratch of tc_adjoint_min_bytes:
+    no transposed copy of Abar, mixed factors decoded one column at a time)
+    gives the full form's Abar bit for bit, for binary64 and mixed factors
+    over every class, at small sizes and at the full gradient size; the
+    autograd function's "recompute" mode (factor and seed recomputed in
+    backward) gives the "store" mode's log-likelihood and gradient.
 """
 import numpy as np
 import pytest
@@ -158,20 +164,109 @@ def test_errors(tc):
     ctx = tc.Context(n, nb)
     F = tc.factorize(ctx, to_dev(tc.pack_lower(L0 @ L0.T, nb)), n, nb)
     Lbar = torch.zeros(tc.num_tiles(n, nb) * nb * nb, dtype=torch.float64, device=dev())
-    small = torch.empty(tc.adjoint_bytes(n, nb) - 8, dtype=torch.uint8, device=dev())
+    small = torch.empty(tc.adjoint_min_bytes(n, nb) - 8, dtype=torch.uint8, device=dev())
     with pytest.raises(tc.TileCholError) as e:
         tc.factor_adjoint(ctx, F, Lbar, scratch=small)
     assert e.value.status == tc.TC_ENOMEM
-    # a mixed-precision factor needs room for its binary64 upcast
+    # a mixed-precision factor needs room for its binary64 column decode
     cm = np.zeros(tc.num_tiles(n, nb), dtype=np.uint8)
     cm[1] = tc.FP32
     Fm = tc.factorize(ctx, to_dev(tc.pack_lower(L0 @ L0.T, nb)), n, nb, cmap=cm)
     assert Fm.mixed
-    fp64_sized = torch.empty(tc.adjoint_bytes(n, nb), dtype=torch.uint8, device=dev())
-    assert tc.adjoint_bytes(n, nb, True) > tc.adjoint_bytes(n, nb)
+    fp64_sized = torch.empty(tc.adjoint_min_bytes(n, nb), dtype=torch.uint8, device=dev())
+    assert tc.adjoint_min_bytes(n, nb, True) > tc.adjoint_min_bytes(n, nb)
     with pytest.raises(tc.TileCholError) as e:
         tc.factor_adjoint(ctx, Fm, Lbar, scratch=fp64_sized)
     assert e.value.status == tc.TC_ENOMEM
+
+
+def _random_seed_lbar(tc, n, nb, seed):
+    """Random lower seed, packed, with garbage in the strict upper triangle
+    of the diagonal tiles (which the sweep ignores)."""
+    Lb = np.tril(np.asarray(si.standard_normal((n, n), seed=seed)))
+    P = tc.pack_lower(Lb, nb)
+    Nt = n // nb
+    for k in range(Nt):
+        t = oracle.tile_index(Nt, k, k)
+        tile = P[t * nb * nb:(t + 1) * nb * nb].reshape(nb, nb).T
+        tile[np.triu_indices(nb, 1)] = -3.0
+    return P
+
+
+@pytest.mark.parametrize("n,nb,eps,bf16", [(2048, 128, None, False), (1536, 256, None, False),
+                                           (512, 512, None, False), (2048, 128, 1e-4, False),
+                                           (1024, 256, 1e-6, False), (1536, 128, 1e-4, True)])
+def test_short_form_equals_full_form(tc, n, nb, eps, bf16):
+    """Memory-short sweep (scratch of exactly tc_adjoint_min_bytes, and one
+    just below the full size) against the full form on the same factor and
+    seed: Abar bit for bit. eps: a mixed factor under the map at that
+    target over FP64/FP32/FP16/FP8 (bf16: BF16 in place of FP16), every
+    stored class decoded column by column."""
+    import torch
+    pts = si.points(n, seed=11)
+    A = oracle.matern_matrix(pts, 1.0, 0.03, 0.5, 1e-4)
+    ctx = tc.Context(n, nb)
+    Ad = to_dev(tc.pack_lower(A, nb))
+    if eps is None:
+        F = tc.factorize(ctx, Ad, n, nb)
+    else:
+        norms = oracle.tile_norms(A, nb)
+        allowed = ((tc.FP64, tc.FP32, tc.BF16, tc.FP8E4M3) if bf16 else
+                   (tc.FP64, tc.FP32, tc.FP16, tc.FP8E4M3))
+        cm = tc.precision_map(n // nb, norms, oracle.fro_norm(norms, n // nb), eps,
+                              allowed=allowed)
+        assert len(set(cm.tolist())) >= 3 and (not bf16 or tc.BF16 in cm)
+        F = tc.factorize(ctx, Ad, n, nb, cmap=cm)
+        assert F.mixed
+    assert F.stats.info == 0
+    P = to_dev(_random_seed_lbar(tc, n, nb, seed=n + nb))
+    full = P.clone()
+    st_f = tc.factor_adjoint(ctx, F, full)
+    lo = tc.adjoint_min_bytes(n, nb, F.mixed)
+    hi = tc.adjoint_bytes(n, nb, F.mixed)
+    assert lo < hi or n == nb
+    for nbytes in sorted({lo, max(lo, hi - 8)}):
+        short = P.clone()
+        scratch = torch.empty(nbytes, dtype=torch.uint8, device=dev())
+        st_s = tc.factor_adjoint(ctx, F, short, scratch=scratch)
+        assert torch.equal(full, short), (nbytes, float((full - short).abs().max()))
+        assert st_s.flops_total == st_f.flops_total
+    F.close()
+
+
+@pytest.mark.parametrize("eps", [None, 1e-7])
+def test_autograd_recompute_mode(tc, eps):
+    """memory="recompute": nothing kept between the passes; backward
+    factorizes again and sweeps in the memory-short form. Same
+    log-likelihood and gradient as "store" (both binary64 and the
+    FP32-mixed variant), and the FP64 oracle's gradient within 1e-8
+    (binary64) or the stated 1e-4 (FP32-mixed)."""
+    import torch
+    n, nb = 1536, 128
+    pts, y = data(n)
+    th = (1.2, 0.08, 2e-4)
+    ctx = tc.Context(n, nb)
+    locs, yd = to_dev(pts), to_dev(y)
+    out = {}
+    for mode in ("store", "recompute", "auto"):
+        theta = torch.tensor(th, dtype=torch.float64, requires_grad=True)
+        ll = tc.matern_loglik(theta, locs, yd, 0.5, nb, ctx, eps=eps, memory=mode)
+        resolved = ll.grad_fn.memory
+        ll.backward()
+        out[mode] = (float(ll.detach()), theta.grad.numpy().copy(), resolved)
+    assert out["store"][2] == "store" and out["recompute"][2] == "recompute"
+    assert out["auto"][2] == "store"  # ample free memory at this size
+    ls, gs, _ = out["store"]
+    lr, gr, _ = out["recompute"]
+    assert lr == ls
+    assert np.allclose(gr, gs, rtol=1e-13, atol=0), (gr, gs)
+    print("recompute vs store gradient bitwise equal:", np.array_equal(gr, gs), flush=True)
+    lo, go = oracle.loglik_grad(pts, y, th[0], th[1], 0.5, th[2], nb=nb)
+    tol = 1e-8 if eps is None else 1e-4
+    assert np.all(np.abs(gr - go) <= tol * np.abs(go)), (gr, go)
+    with pytest.raises(ValueError):
+        tc.matern_loglik(torch.tensor(th, dtype=torch.float64), locs, yd, 0.5, nb, ctx,
+                         memory="never")
 
 
 def test_fp32_mixed_gradient(tc):
@@ -254,12 +349,17 @@ def test_full_size_gradient_central_differences(tc):
     F = tc.factorize(ctx, A, n, nb, inplace=True)
     Lbar = torch.empty_like(A)
     l0 = tc.loglik_seed(ctx, F, y, Lbar)
+    Lshort = Lbar.clone()
     st = tc.factor_adjoint(ctx, F, Lbar)
     g = tc.matern_grad(ctx, locs, (th[0], th[1], nu, th[2]), nb, Lbar)
+    # the memory-short form at this size: the same Abar bit for bit
+    st_s = tc.factor_adjoint(ctx, F, Lshort, short=True)
+    assert torch.equal(Lshort, Lbar)
     F.close()
-    del A, Lbar
+    del A, Lbar, Lshort
     torch.cuda.empty_cache()
-    print("l =", l0, "grad =", g, "reverse sweep ms =", st.ms_total, flush=True)
+    print("l =", l0, "grad =", g, "reverse sweep ms = %.1f (full), %.1f (memory-short)"
+          % (st.ms_total, st_s.ms_total), flush=True)
     assert np.all(np.isfinite(g))
     fds = []
     for p in range(3):
@@ -283,12 +383,16 @@ def test_full_size_gradient_central_differences(tc):
     assert n32 > 0
     Fm = tc.factorize(ctx, A, n, nb, cmap=cm)
     assert Fm.mixed and Fm.stats.info == 0
-    Lbar = torch.empty_like(A)
+    del A
+    Lbar = torch.empty(tc.num_tiles(n, nb) * nb * nb, dtype=torch.float64, device=dev())
     lm = tc.loglik_seed(ctx, Fm, y, Lbar)
+    Lshort = Lbar.clone()
     tc.factor_adjoint(ctx, Fm, Lbar)
     gm = tc.matern_grad(ctx, locs, full, nb, Lbar)
+    tc.factor_adjoint(ctx, Fm, Lshort, short=True)  # columns decoded one at a time
+    assert torch.equal(Lshort, Lbar)
     Fm.close()
-    del A, Lbar
+    del Lbar, Lshort
     torch.cuda.empty_cache()
     print("FP32-mixed (%d FP32 tiles): l = %r grad = %r" % (n32, lm, gm), flush=True)
     assert abs(lm - l0) <= 1e-6 * abs(l0), (lm, l0)

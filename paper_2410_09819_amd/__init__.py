@@ -43,7 +43,7 @@ class Matern(ctypes.Structure):
 
 class Opts(ctypes.Structure):
     _fields_ = [("inplace", ctypes.c_int32), ("fp64_update", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 6)]
+                ("wide_tiles", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
 
 
 class Stats(ctypes.Structure):
@@ -288,11 +288,13 @@ class Factor:
 
 
 def factorize(ctx: Context, A, n: int, nb: int, cmap=None, inplace: bool = False,
-              storage=None, fp64_update: int = 0) -> Factor:
+              storage=None, fp64_update: int = 0, wide_tiles: int = 0) -> Factor:
     """Tile Cholesky of the packed lower tiles A (device float64). With
     inplace=True the factor overwrites A. fp64_update=FP32 computes the
     updates into FP64-class tiles (diagonal SYRK included) in the FP32
-    class's arithmetic. Raises NotPositiveDefinite."""
+    class's arithmetic. wide_tiles: block shape of the low-class update
+    kernels (tc_opts.wide_tiles: 0 auto, 1 256 x 256 when nb allows, -1
+    128 x 128). Raises NotPositiveDefinite."""
     import torch
     if inplace:
         storage = A
@@ -300,7 +302,7 @@ def factorize(ctx: Context, A, n: int, nb: int, cmap=None, inplace: bool = False
         storage = torch.empty(factor_bytes(n, nb, cmap, fp64_update) // 8, dtype=torch.float64,
                               device=A.device)
     m = None if cmap is None else np.ascontiguousarray(cmap, dtype=np.uint8)
-    opts = Opts(1 if inplace else 0, fp64_update)
+    opts = Opts(1 if inplace else 0, fp64_update, wide_tiles)
     st = Stats()
     h = _vp()
     status = lib().tc_factorize(ctx.handle, n, nb, A.data_ptr(), None if m is None else m.ctypes.data,
@@ -420,13 +422,14 @@ def ooc_mixed_cache_bytes(n: int, nb: int, cmap, slots: int, fp64_update: int = 
 
 
 def factorize_ooc_mixed(ctx: Context, A_host, n: int, nb: int, cmap, cache, L_host=None,
-                        fp64_update: int = 0):
+                        fp64_update: int = 0, wide_tiles: int = 0):
     """Out-of-core mixed-precision factorization: A_host (pinned CPU float64
     tensor, packed lower tiles) streams through the device cache `cache`;
     the factor image (tiles in their classes, then the tile scale exponents)
     goes to L_host (pinned CPU uint8 tensor, allocated if None). fp64_update
-    as in factorize (size the cache with the same value). Returns (transfer
-    statistics, L_host). Raises NotPositiveDefinite."""
+    as in factorize (size the cache with the same value), wide_tiles as in
+    factorize. Returns (transfer statistics, L_host). Raises
+    NotPositiveDefinite."""
     import torch
     assert A_host.device.type == "cpu" and A_host.is_pinned()
     m = np.ascontiguousarray(cmap, dtype=np.uint8)
@@ -438,7 +441,8 @@ def factorize_ooc_mixed(ctx: Context, A_host, n: int, nb: int, cmap, cache, L_ho
     _check(lib().tc_factorize_ooc_mixed(ctx.handle, n, nb, A_host.data_ptr(), m.ctypes.data,
                                         L_host.data_ptr(), L_host.numel() * L_host.element_size(),
                                         cache.data_ptr(), cache.numel() * cache.element_size(),
-                                        ctypes.byref(Opts(0, fp64_update)), ctypes.byref(st)))
+                                        ctypes.byref(Opts(0, fp64_update, wide_tiles)),
+                                        ctypes.byref(st)))
     return st.as_dict(), L_host
 
 

@@ -143,14 +143,17 @@ hipError_t launch_mxp_gemm_f64(hipStream_t s, double* W, int Nt, int nb, int k, 
                                const int64_t* toff, const uint8_t* tcls, const int* tscl,
                                double* partial, size_t partial_cap);
 // FP32 group: FP16 MFMA over the two-plane (hi, lo) split copies.
+// wide: 256 x 256 blocks (1: whenever nb allows, 0: when the launch fills
+// the chip twice over with them, -1: never) or 128 x 128 blocks.
 hipError_t launch_mxp_gemm_f32(hipStream_t s, double* W, int Nt, int nb, int k, int nbeg, int nend,
                                const int* rows, int nrows, const char* storage,
-                               const int64_t* shoff, const int* cscl);
+                               const int64_t* shoff, const int* cscl, int wide);
 // FP16 / BF16 / FP8 group: narrow-format MFMA over the class's operand
 // copies (row-major bits, per-copy scale cscl), FP32 accumulation.
 hipError_t launch_mxp_gemm_narrow(hipStream_t s, double* W, int Nt, int nb, int k, int nbeg,
                                   int nend, const int* rows, int nrows, int cls,
-                                  const char* storage, const int64_t* shoff, const int* cscl);
+                                  const char* storage, const int64_t* shoff, const int* cscl,
+                                  int wide);
 // Operand copies of the stored tiles list[0..count) (out of core: tiles
 // loaded into cache slots), from their stored bits and recorded scales.
 hipError_t launch_mxp_copies(hipStream_t s, int nb, const int* list, int count, char* storage,

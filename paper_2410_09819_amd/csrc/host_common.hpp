@@ -96,6 +96,10 @@ struct Plan {
 // SYRK included (TC_FP64, or TC_FP32: the split-FP16 FP32 class; the plan
 // is then mixed even for an all-FP64 map).
 bool make_plan(int64_t n, int nb, const uint8_t* map, Plan& P, int fp64_update = 0);
+// Tile columns per bulk group launch of the mixed schedule (16: measured
+// against 8, 32 and whole columns at n = 131072, nb = 1024). The out-of-core
+// mixed schedule cuts its group launches at the same multiples.
+constexpr int kBulkChunk = 16;
 // Row lists of a mixed factorization: for column k and compute class c, the
 // rows r (tile k + r; r = 0, the diagonal, only in the FP32 list when the
 // diagonal SYRK runs in FP32) at lists[(k * 5 + c) * Nt + i], i < count[k *

@@ -883,6 +883,223 @@ __global__ __launch_bounds__(kGemmThreads, 2) void mxp_gemm_split_kernel(
             }
 }
 
+// ---------------------------------------------------------------------------
+// Wide form of the FP32 / FP16 / BF16 / FP8 groups: 256 x 256 blocks on
+// eight waves (2 x 4 waves of 128 x 64), for launches large enough to fill
+// the chip with them. Per 64-deep (FP16/BF16; 128 FP8; 32 split) stage a
+// block moves half the operand bytes per flop of the 128 x 128 form, and
+// each wave reads 1.5x fewer LDS bytes per flop: the 128 x 128 form is
+// bound by its operands' path through the vector memory unit and LDS, not
+// by the matrix cores. Operands go to LDS by direct-to-LDS loads (wave w
+// fills rows 128 (w & 1) .. + 127 of plane w >> 1; planes A0 A1 B0 B1, or
+// A hi, A lo, B hi, B lo for the split; same swizzle as above) into a
+// double buffer.
+// Scales: instead of a second accumulator per tile column, acc holds the
+// running sum in units of 2^frame, frame = the current tile column's
+// product scale e_a + e_b, and is multiplied by 2^(frame_old - frame_new)
+// when the column changes. The block walks its tile columns in ascending
+// order of that scale (ties by column), so the frame only rises and acc
+// only shrinks: a column's sum is below 2^45 in its own unit (nb <= 4096
+// products of at most 2^33), acc stays below Nt 2^45 and never overflows,
+// and a rescale is exact unless it drops below binary32's range, which
+// only loses terms below 2^-126 of the new unit. (Small terms first is
+// also the more accurate order.) One binary32 chain never spans more than
+// kWGroup tile columns: the launcher cuts longer ranges at multiples of
+// kWGroup columns, and each piece's sum is subtracted from W in binary64,
+// so the chains are as long as those of the in-core bulk launches whatever
+// the caller's chunking.
+constexpr int kWB = 256;              // block rows and columns
+constexpr int kWThreads = 512;        // eight waves
+constexpr int kWPlane = kWB * 64;     // bytes per plane: 256 rows x 64 bytes
+constexpr int kWStage = 4 * kWPlane;  // 64 KiB per stage
+constexpr int kWGroup = 16;           // tile columns one binary32 chain may span
+typedef __attribute__((address_space(3))) void lds_void;
+
+template <int MODE>
+__global__ __launch_bounds__(kWThreads, 1) void mxp_gemm_wide_kernel(
+    double* __restrict__ W, int Nt, int nb, int k, int nbeg, int nend, const int* __restrict__ rows,
+    int nrows, const char* __restrict__ storage, const int64_t* __restrict__ shoff,
+    const int* __restrict__ cscl) {
+    constexpr bool SPLIT = MODE == kFP32;
+    constexpr int EB = MODE == kFP8 ? 1 : 2;
+    constexpr int SK = SPLIT ? 32 : 128 / EB;  // k per stage
+    __shared__ __attribute__((aligned(1024))) uint8_t lds[2 * kWStage];
+    __shared__ int key[kWGroup], order[kWGroup];
+    const int T = nb / kWB;
+    const int64_t total = (int64_t)nrows * T * T;
+    const int64_t b = xcd_remap(blockIdx.x, total);
+    int64_t rt;
+    int br, bc;
+    group_block(b, T, false, rows, rt, br, bc);
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: scalar load bases
+    const int wm = wave & 1, wn = wave >> 1;                     // rows 128 wm, columns 64 wn
+    const int li = lane & 15, lg = lane >> 4;
+    const NarrowOp aop{storage, shoff, cscl, MODE, Nt, nb, k + rt, (int64_t)br * kWB};
+    const NarrowOp bop{storage, shoff, cscl, MODE, Nt, nb, k, (int64_t)bc * kWB};
+    const int spt = nb / SK;  // stages per tile column
+    const int ncols = nend - nbeg;
+    if (ncols > kWGroup) return;  // the launcher never asks for more
+    const int g1 = ncols * spt;   // stages, counted from 0
+    // tile columns in ascending order of product scale (rank sort)
+    for (int c = tid; c < ncols; c += kWThreads) key[c] = aop.scale(nbeg + c) + bop.scale(nbeg + c);
+    __syncthreads();
+    for (int c = tid; c < ncols; c += kWThreads) {
+        const int kc = key[c];
+        int r = 0;
+        for (int j = 0; j < ncols; ++j) r += (key[j] < kc) || (key[j] == kc && j < c);
+        order[r] = c;
+    }
+    __syncthreads();
+    const int pl = wave >> 1, half = wave & 1;
+    const int64_t pbyte = SPLIT ? (pl & 1) * (int64_t)nb * nb * 2 : (pl & 1) * 64;
+    const int lr = lane >> 2;
+    const int lc = (lane & 3) ^ ((lr >> 1) & 3);  // row 16 q + lr swizzles like lr
+    const int64_t goff = (int64_t)(128 * half + lr) * nb * EB + 16 * lc + pbyte;
+    const int64_t gq = (int64_t)16 * nb * EB;  // 16 rows further
+    auto issue = [&](int g) {
+        const int c = g / spt, st = g - c * spt;
+        const int n = nbeg + order[c];
+        const uint8_t* src = (pl < 2 ? aop.rows(n, EB) : bop.rows(n, EB)) + (int64_t)st * SK * EB + goff;
+        uint8_t* dst = lds + (g & 1) * kWStage + pl * kWPlane + half * 128 * 64;
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            __builtin_amdgcn_global_load_lds(src + q * gq, (lds_void*)(dst + q * 1024), 16, 0, 0);
+    };
+    const int ro = swz(li, lg);
+    f4 acc[8][4];
+#pragma unroll
+    for (int mi = 0; mi < 8; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 4; ++ni) acc[mi][ni] = f4{0.f, 0.f, 0.f, 0.f};
+    // this lane's first output element; the others are uniform offsets from it
+    double* const out = W + rt * (int64_t)nb * nb + (int64_t)(bc * kWB + wn * 64 + 4 * lg) * nb +
+                        br * kWB + wm * 128 + li;
+    int frame = 0;
+    if (g1 > 0) {
+        frame = key[order[0]];
+        issue(0);
+    }
+    for (int g = 0; g < g1; ++g) {
+        // stage g landed for every wave, and every wave is done reading
+        // stage g - 1's buffer, which stage g + 1 now overwrites
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
+        if (g + 1 < g1) issue(g + 1);
+        const uint8_t* st = lds + (g & 1) * kWStage;
+        const int ao = wm * 128 * 64 + ro, bo = wn * 64 * 64 + ro;
+        if constexpr (SPLIT) {
+            u4v xa[8], xb[4], ya[8];
+#pragma unroll
+            for (int mi = 0; mi < 8; ++mi) xa[mi] = *reinterpret_cast<const u4v*>(st + ao + mi * 1024);
+#pragma unroll
+            for (int ni = 0; ni < 4; ++ni)
+                xb[ni] = *reinterpret_cast<const u4v*>(st + 2 * kWPlane + bo + ni * 1024);
+#pragma unroll
+            for (int mi = 0; mi < 8; ++mi)
+#pragma unroll
+                for (int ni = 0; ni < 4; ++ni)
+                    acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
+                        __builtin_bit_cast(h8v, xb[ni]), __builtin_bit_cast(h8v, xa[mi]), acc[mi][ni],
+                        0, 0, 0);
+#pragma unroll
+            for (int mi = 0; mi < 8; ++mi)
+                ya[mi] = *reinterpret_cast<const u4v*>(st + kWPlane + ao + mi * 1024);
+#pragma unroll
+            for (int mi = 0; mi < 8; ++mi)
+#pragma unroll
+                for (int ni = 0; ni < 4; ++ni)
+                    acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
+                        __builtin_bit_cast(h8v, xb[ni]), __builtin_bit_cast(h8v, ya[mi]), acc[mi][ni],
+                        0, 0, 0);
+#pragma unroll
+            for (int ni = 0; ni < 4; ++ni)
+                xb[ni] = *reinterpret_cast<const u4v*>(st + 3 * kWPlane + bo + ni * 1024);
+#pragma unroll
+            for (int mi = 0; mi < 8; ++mi)
+#pragma unroll
+                for (int ni = 0; ni < 4; ++ni)
+                    acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
+                        __builtin_bit_cast(h8v, xb[ni]), __builtin_bit_cast(h8v, xa[mi]), acc[mi][ni],
+                        0, 0, 0);
+        } else if constexpr (MODE == kFP8) {
+            // lane group l / 16 takes chunk l / 16 of both planes (32 k)
+            i8v bq[4];
+#pragma unroll
+            for (int ni = 0; ni < 4; ++ni) {
+                const u4v x = *reinterpret_cast<const u4v*>(st + 2 * kWPlane + bo + ni * 1024);
+                const u4v y = *reinterpret_cast<const u4v*>(st + 3 * kWPlane + bo + ni * 1024);
+                bq[ni] = i8v{(int)x.x, (int)x.y, (int)x.z, (int)x.w, (int)y.x, (int)y.y, (int)y.z, (int)y.w};
+            }
+#pragma unroll
+            for (int mi = 0; mi < 8; ++mi) {
+                const u4v x = *reinterpret_cast<const u4v*>(st + ao + mi * 1024);
+                const u4v y = *reinterpret_cast<const u4v*>(st + kWPlane + ao + mi * 1024);
+                const i8v a = i8v{(int)x.x, (int)x.y, (int)x.z, (int)x.w, (int)y.x, (int)y.y, (int)y.z, (int)y.w};
+#pragma unroll
+                for (int ni = 0; ni < 4; ++ni)
+                    acc[mi][ni] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
+                        bq[ni], a, acc[mi][ni], 0, 0, 0, 127, 0, 127);
+            }
+        } else {
+#pragma unroll
+            for (int ks = 0; ks < 2; ++ks) {  // plane ks: k 32 ks .. 32 ks + 31
+                u4v a[8], bq[4];
+#pragma unroll
+                for (int mi = 0; mi < 8; ++mi)
+                    a[mi] = *reinterpret_cast<const u4v*>(st + ks * kWPlane + ao + mi * 1024);
+#pragma unroll
+                for (int ni = 0; ni < 4; ++ni)
+                    bq[ni] = *reinterpret_cast<const u4v*>(st + (2 + ks) * kWPlane + bo + ni * 1024);
+#pragma unroll
+                for (int mi = 0; mi < 8; ++mi)
+#pragma unroll
+                    for (int ni = 0; ni < 4; ++ni) {
+                        if constexpr (MODE == kFP16)
+                            acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
+                                __builtin_bit_cast(h8v, bq[ni]), __builtin_bit_cast(h8v, a[mi]),
+                                acc[mi][ni], 0, 0, 0);
+                        else
+                            acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                __builtin_bit_cast(b8v, bq[ni]), __builtin_bit_cast(b8v, a[mi]),
+                                acc[mi][ni], 0, 0, 0);
+                    }
+            }
+        }
+        if (g + 1 < g1 && (g + 1) % spt == 0) {  // the next stage starts a tile column
+            const int sc = key[order[(g + 1) / spt]];
+            const int d = frame - sc;  // <= 0: the frame rises
+            if (d != 0) {
+#pragma unroll
+                for (int mi = 0; mi < 8; ++mi)
+#pragma unroll
+                    for (int ni = 0; ni < 4; ++ni)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) acc[mi][ni][v] = ldexpf(acc[mi][ni][v], d);
+            }
+            frame = sc;
+        }
+    }
+    // W -= acc 2^frame for this wave's 128 x 64 part
+#pragma unroll
+    for (int ni = 0; ni < 4; ++ni)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            double* const p = out + (int64_t)(ni * 16 + v) * nb;
+#pragma unroll
+            for (int mi = 0; mi < 8; ++mi) p[mi * 16] -= ldexp((double)acc[mi][ni][v], frame);
+        }
+}
+
+// Wide form for this group launch? mode 1: whenever the tile allows it;
+// -1: never; 0: when the launch has at least two rounds of 256 CUs.
+bool use_wide(int mode, int nb, int nrows) {
+    if (mode < 0 || nb % kWB != 0) return false;
+    const int64_t T = nb / kWB;
+    return mode > 0 || (int64_t)nrows * T * T >= 512;
+}
+
 }  // namespace
 
 // Split count of an FP64 group launch: the forward panel's time model
@@ -933,10 +1150,22 @@ hipError_t launch_mxp_gemm_f64(hipStream_t s, double* W, int Nt, int nb, int k, 
 
 hipError_t launch_mxp_gemm_f32(hipStream_t s, double* W, int Nt, int nb, int k, int nbeg, int nend,
                                const int* rows, int nrows, const char* storage,
-                               const int64_t* shoff, const int* cscl) {
+                               const int64_t* shoff, const int* cscl, int wide) {
+    if (nrows <= 0 || nend <= nbeg) return hipSuccess;
+    if (use_wide(wide, nb, nrows)) {
+        const int64_t T = nb / kWB;
+        for (int p0 = nbeg; p0 < nend;) {  // pieces cut at multiples of kWGroup columns
+            const int p1 = std::min(nend, (p0 / kWGroup + 1) * kWGroup);
+            hipLaunchKernelGGL(mxp_gemm_wide_kernel<kFP32>, dim3((unsigned)(nrows * T * T)),
+                               dim3(kWThreads), 0, s, W, Nt, nb, k, p0, p1, rows, nrows, storage,
+                               shoff, cscl);
+            if (hipError_t e = hipGetLastError()) return e;
+            p0 = p1;
+        }
+        return hipSuccess;
+    }
     const int64_t T = nb / kB;
     const int64_t total = (int64_t)nrows * T * T;
-    if (total == 0 || nend <= nbeg) return hipSuccess;
     hipLaunchKernelGGL(mxp_gemm_split_kernel, dim3((unsigned)total), dim3(kGemmThreads), 0, s, W,
                        Nt, nb, k, nbeg, nend, rows, nrows, storage, shoff, cscl);
     return hipGetLastError();
@@ -944,10 +1173,31 @@ hipError_t launch_mxp_gemm_f32(hipStream_t s, double* W, int Nt, int nb, int k, 
 
 hipError_t launch_mxp_gemm_narrow(hipStream_t s, double* W, int Nt, int nb, int k, int nbeg,
                                   int nend, const int* rows, int nrows, int cls,
-                                  const char* storage, const int64_t* shoff, const int* cscl) {
+                                  const char* storage, const int64_t* shoff, const int* cscl,
+                                  int wide) {
+    if (nrows <= 0 || nend <= nbeg) return hipSuccess;
+    if (use_wide(wide, nb, nrows)) {
+        if (cls != kFP16 && cls != kBF16 && cls != kFP8) return hipErrorInvalidValue;
+        const int64_t T = nb / kWB;
+        const dim3 grid((unsigned)(nrows * T * T)), block(kWThreads);
+        for (int p0 = nbeg; p0 < nend;) {  // pieces cut at multiples of kWGroup columns
+            const int p1 = std::min(nend, (p0 / kWGroup + 1) * kWGroup);
+            if (cls == kFP16)
+                hipLaunchKernelGGL(mxp_gemm_wide_kernel<kFP16>, grid, block, 0, s, W, Nt, nb, k,
+                                   p0, p1, rows, nrows, storage, shoff, cscl);
+            else if (cls == kBF16)
+                hipLaunchKernelGGL(mxp_gemm_wide_kernel<kBF16>, grid, block, 0, s, W, Nt, nb, k,
+                                   p0, p1, rows, nrows, storage, shoff, cscl);
+            else
+                hipLaunchKernelGGL(mxp_gemm_wide_kernel<kFP8>, grid, block, 0, s, W, Nt, nb, k,
+                                   p0, p1, rows, nrows, storage, shoff, cscl);
+            if (hipError_t e = hipGetLastError()) return e;
+            p0 = p1;
+        }
+        return hipSuccess;
+    }
     const int64_t T = nb / kB;
     const int64_t total = (int64_t)nrows * T * T;
-    if (total == 0 || nend <= nbeg) return hipSuccess;
     const dim3 grid((unsigned)total), block(kGemmThreads);
     if (cls == kFP16)
         hipLaunchKernelGGL(mxp_gemm_narrow_kernel<kFP16>, grid, block, 0, s, W, Nt, nb, k, nbeg, nend,

@@ -160,6 +160,8 @@ extern "C" tc_status tc_factorize_ooc_mixed(tc_ctx* ctx, int64_t n, int32_t nb, 
     const int fp64_update = opts ? opts->fp64_update : TC_FP64;
     if (fp64_update != TC_FP64 && fp64_update != TC_FP32)
         return fail(TC_EINVAL, "opts->fp64_update must be TC_FP64 or TC_FP32");
+    const int wide = opts ? opts->wide_tiles : 0;
+    if (wide < -1 || wide > 1) return fail(TC_EINVAL, "opts->wide_tiles must be -1, 0 or 1");
     Plan P;
     if (!make_plan(n, nb, map, P, fp64_update)) return fail(TC_EINVAL, "invalid precision map");
     const int Nt = P.Nt;
@@ -375,7 +377,13 @@ extern "C" tc_status tc_factorize_ooc_mixed(tc_ctx* ctx, int64_t n, int32_t nb, 
                     if (tc_status r = apply(upd, rebuild)) return r;
                 }
                 // the low-class groups (disjoint tiles of W) run on a side
-                // stream, concurrently with the FP64 group; both join here
+                // stream, concurrently with the FP64 group; both join here.
+                // Launches follow the in-core schedule's pieces: tile
+                // columns cut at multiples of kBulkChunk up to column k - 1,
+                // then column k - 1 alone (its FP64 group without split-K).
+                // The sums are then formed in the in-core order, and with a
+                // cache that holds the working set the factor is the in-core
+                // one bit for bit.
                 bool low = false;
                 for (int cls = 1; cls <= 4; ++cls) low = low || count(k, cls) > 0;
                 if (low) {
@@ -383,21 +391,30 @@ extern "C" tc_status tc_factorize_ooc_mixed(tc_ctx* ctx, int64_t n, int32_t nb, 
                     if (tc_status r = E.get(ef)) return r;
                     TC_HIP(hipEventRecord(E.ev[ef], cs));
                     TC_HIP(hipStreamWaitEvent(sl, E.ev[ef], 0));
-                    for (int cls = 1; cls <= 4; ++cls) {
+                }
+                for (int p0 = n0; p0 < n1;) {
+                    const int p1 = p0 == k - 1
+                                       ? k
+                                       : std::min({n1, k - 1, (p0 / kBulkChunk + 1) * kBulkChunk});
+                    for (int cls = 1; low && cls <= 4; ++cls) {
                         const int cnt = count(k, cls);
                         if (!cnt) continue;
                         if (cls == TC_FP32)
-                            TC_HIP(tc::launch_mxp_gemm_f32(sl, W, Nt, nb, k, n0, n1, list(k, cls), cnt, cbase,
-                                                           d_shoff, d_cscl));
+                            TC_HIP(tc::launch_mxp_gemm_f32(sl, W, Nt, nb, k, p0, p1, list(k, cls), cnt, cbase,
+                                                           d_shoff, d_cscl, wide));
                         else
-                            TC_HIP(tc::launch_mxp_gemm_narrow(sl, W, Nt, nb, k, n0, n1, list(k, cls), cnt,
-                                                              cls, cbase, d_shoff, d_cscl));
+                            TC_HIP(tc::launch_mxp_gemm_narrow(sl, W, Nt, nb, k, p0, p1, list(k, cls), cnt,
+                                                              cls, cbase, d_shoff, d_cscl, wide));
                     }
+                    if (P.diag64 || count(k, TC_FP64)) {
+                        const bool last = p0 == k - 1;
+                        TC_HIP(tc::launch_mxp_gemm_f64(cs, W, Nt, nb, k, p0, p1, list(k, TC_FP64),
+                                                       count(k, TC_FP64), P.diag64, cbase, d_toff, d_tcls,
+                                                       d_tscl, last ? nullptr : big,
+                                                       last ? 0 : big_cap / sizeof(double)));
+                    }
+                    p0 = p1;
                 }
-                if (P.diag64 || count(k, TC_FP64))
-                    TC_HIP(tc::launch_mxp_gemm_f64(cs, W, Nt, nb, k, n0, n1, list(k, TC_FP64),
-                                                   count(k, TC_FP64), P.diag64, cbase, d_toff, d_tcls,
-                                                   d_tscl, big, big_cap / sizeof(double)));
                 if (low) {
                     int ej;
                     if (tc_status r = E.get(ej)) return r;

@@ -730,12 +730,8 @@ tc_status factorize_fp64(tc_ctx* ctx, int64_t n, int nb, const double* A, double
 // binary64 working column W, subtract the updates class group by class
 // group, POTRF the diagonal tile and TRSM the rest in FP64, then store the
 // diagonal tile in FP64 and round the others into their classes.
-// Tile columns per bulk group launch of the mixed schedule (16: measured
-// against 8, 32 and whole columns at n = 131072, nb = 1024).
-constexpr int kBulkChunk = 16;
-
 tc_status factorize_mixed(tc_ctx* ctx, int64_t n, int nb, const double* A, const Plan& P,
-                          char* storage, tc_factor** Lout, tc_stats* stats) {
+                          char* storage, int wide, tc_factor** Lout, tc_stats* stats) {
     const int Nt = P.Nt;
     const Layout Ly = layout(n, nb);
     int* d_info = reinterpret_cast<int*>(ctx->ws + Ly.info);
@@ -791,10 +787,10 @@ tc_status factorize_mixed(tc_ctx* ctx, int64_t n, int nb, const double* A, const
             if (!cnt) continue;
             if (cls == TC_FP32)
                 TC_HIP(tc::launch_mxp_gemm_f32(st, Wc, Nt, nb, c, n0, n1, list(c, cls), cnt, storage,
-                                               d_shoff, d_cscl));
+                                               d_shoff, d_cscl, wide));
             else
                 TC_HIP(tc::launch_mxp_gemm_narrow(st, Wc, Nt, nb, c, n0, n1, list(c, cls), cnt, cls,
-                                                  storage, d_shoff, d_cscl));
+                                                  storage, d_shoff, d_cscl, wide));
         }
         return TC_OK;
     };
@@ -918,6 +914,8 @@ tc_status tc_factorize(tc_ctx* ctx, int64_t n, int32_t nb, const double* A, cons
     const int fp64_update = opts ? opts->fp64_update : TC_FP64;
     if (fp64_update != TC_FP64 && fp64_update != TC_FP32)
         return fail(TC_EINVAL, "opts->fp64_update must be TC_FP64 or TC_FP32");
+    const int wide = opts ? opts->wide_tiles : 0;
+    if (wide < -1 || wide > 1) return fail(TC_EINVAL, "opts->wide_tiles must be -1, 0 or 1");
     Plan P;
     if (!make_plan(n, nb, map, P, fp64_update))
         return fail(TC_EINVAL, "bad precision map (codes 0..4, diagonal tiles TC_FP64)");
@@ -928,7 +926,8 @@ tc_status tc_factorize(tc_ctx* ctx, int64_t n, int32_t nb, const double* A, cons
         return fail(TC_EINVAL, "a mixed-precision factor cannot overwrite its input");
     if (tc_status s = check_ws(ctx, n, nb)) return s;
     DeviceGuard g(ctx->device);
-    tc_status st = P.mixed ? factorize_mixed(ctx, n, nb, A, P, static_cast<char*>(storage), Lout, stats)
+    tc_status st = P.mixed ? factorize_mixed(ctx, n, nb, A, P, static_cast<char*>(storage), wide,
+                                             Lout, stats)
                            : factorize_fp64(ctx, n, nb, A, static_cast<double*>(storage), Lout, stats);
     if (st > 0) g_err = "matrix is not positive definite (column " + std::to_string(st) + ")";
     return st;

@@ -126,6 +126,10 @@ def test_ooc_mixed_matches_in_core_and_oracle(tc, case, eps, slots, upd):
     assert be <= 10 * be_o and (upd or be <= eps), (be, be_o)
     diff = np.linalg.norm(L - Lin) / np.linalg.norm(Lin)
     assert diff <= 4 * case["kappa"] * (be + be_in) + 1e-13, diff
+    if st["tiles_reloaded"] == 0:
+        # the group launches follow the in-core pieces: the same sums in the
+        # same order, so the same factor bit for bit
+        assert np.array_equal(L, np.tril(Lin))
     # transfer volume
     nb2 = nb * nb
     ntiles = Nt * (Nt + 1) // 2

@@ -143,8 +143,8 @@ hipError_t launch_mxp_gemm_f64(hipStream_t s, double* W, int Nt, int nb, int k, 
                                const int64_t* toff, const uint8_t* tcls, const int* tscl,
                                double* partial, size_t partial_cap);
 // FP32 group: FP16 MFMA over the two-plane (hi, lo) split copies.
-// wide: 256 x 256 blocks (1: whenever nb allows, 0: when the launch fills
-// the chip twice over with them, -1: never) or 128 x 128 blocks.
+// wide: 256 x 256 blocks (1: whenever nb allows, 0: when the launch has at
+// least 256 of them, -1: never) or 128 x 128 blocks.
 hipError_t launch_mxp_gemm_f32(hipStream_t s, double* W, int Nt, int nb, int k, int nbeg, int nend,
                                const int* rows, int nrows, const char* storage,
                                const int64_t* shoff, const int* cscl, int wide);

@@ -1093,11 +1093,14 @@ __global__ __launch_bounds__(kWThreads, 1) void mxp_gemm_wide_kernel(
 }
 
 // Wide form for this group launch? mode 1: whenever the tile allows it;
-// -1: never; 0: when the launch has at least two rounds of 256 CUs.
+// -1: never; 0: when the launch has a block for each of the 256 CUs
+// (threshold measured against 1, 64, 128, 512 and 1024 blocks on the
+// n = 131072 mixed factorization: 256 is best or within 1% for both update
+// arithmetics).
 bool use_wide(int mode, int nb, int nrows) {
     if (mode < 0 || nb % kWB != 0) return false;
     const int64_t T = nb / kWB;
-    return mode > 0 || (int64_t)nrows * T * T >= 512;
+    return mode > 0 || (int64_t)nrows * T * T >= 256;
 }
 
 }  // namespace

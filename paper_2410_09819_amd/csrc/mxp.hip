@@ -40,12 +40,28 @@ constexpr int kThreads = 256;
 // A stage is a 128 x 16 operand slab (16 columns of the tile, 128 rows),
 // loaded with consecutive lanes on consecutive bytes: a binary64 slab as
 // four 16-byte pieces per thread (2 rows each), the other classes as two
-// pieces of 4 consecutive rows (16, 8, 8 or 4 bytes). The raw bits stay in
-// registers while the current stage's MFMAs run; after them they are
-// decoded, scaled by 2^scale (exact) and written to LDS. An operand's class
-// changes only between tile columns, so each tile column's stages run in a
-// loop specialized for its (A class, B class) pair: straight-line loads,
+// pieces of 4 consecutive rows (16, 8, 8 or 4 bytes each). The raw bits
+// stay in registers while the current stage's MFMAs run; after them they
+// are decoded to binary64 and written to LDS. An operand's class changes
+// only between tile columns, so each tile column's stages run in a loop
+// specialized for its (A class, B class) pair: straight-line loads,
 // decodes and waits, as in the all-binary64 main loop.
+//
+// The workgroup is that of the all-binary64 kernels: 256 threads, 2 x 2
+// waves of 64 x 64 of the 128 x 128 block, two workgroups per CU, so one
+// workgroup's barriers and decodes overlap the other's MFMAs. With 64 x 64
+// accumulators per wave, the 25 pair loops inlined into one kernel do not
+// fit in 256 registers (the compiler keeps them apart), so each pair loop
+// is a function of its own: it takes the accumulators from memory (private
+// to the lane) at the start of its tile column and puts them back at the
+// end, 64 moves per tile column of 64 stages.
+//
+// The scaled classes' (FP16, FP8) tile scales are not applied to each
+// decoded element: a pair loop runs in a frame of 2^s, s = the sum of its
+// operands' scales (the accumulators are divided by 2^s on entry and
+// multiplied back on exit). Power-of-two scaling commutes with binary64
+// rounding away from the subnormal range, so the sums are those of scaled
+// operands, with a third fewer decode instructions.
 // ---------------------------------------------------------------------------
 struct MixedTile {
     const char* base;  // tile start
@@ -54,121 +70,136 @@ struct MixedTile {
 };
 
 struct RawSlab {
-    uint4 w[2];
+    uint4 w[4];
 };
 
-// The FP64-group kernel: 512 threads (8 waves, 2 x 4, each 64 rows x 32
-// columns of the 128 x 128 block), so each wave holds half the
-// accumulators of the 4-wave binary64 kernels and every class pair's loop
-// fits in registers.
-constexpr int kF64Threads = 512;
-constexpr int kF64MI = 4, kF64NI = 2;  // 16 x 16 MFMA blocks per wave
+constexpr int kF64Threads = 256;
+constexpr int kF64MI = 4, kF64NI = 4;  // 16 x 16 MFMA blocks per wave
 
 // A thread's pieces of a slab: element offsets in the tile (leading
-// dimension nb) and LDS offsets (leading dimension LD) of its 2 binary64
-// pieces of 2 rows (e2, s2) or its piece of 4 rows of the narrower classes
-// (e4, s4).
+// dimension nb) and LDS offsets of its first binary64 piece of 2 rows
+// (e2, s2; piece q is kQ2 q columns further) or its first piece of 4 rows
+// of the narrower classes (e4, s4; the second is kQ4 columns further).
 struct SlabMap {
-    int e2[2], s2[2], e4, s4;
+    int e2, s2, e4, s4;
 };
+constexpr int kQ2 = 2 * kF64Threads / 128;  // columns between binary64 pieces
+constexpr int kQ4 = 4 * kF64Threads / 128;  // ... between narrower pieces
 
 template <int LD>
 __device__ __forceinline__ SlabMap slab_map(int tid, int nb) {
     SlabMap m;
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-        const int e = (q * kF64Threads + tid) * 2, col = e >> 7, row = e & 127;
-        m.e2[q] = col * nb + row;
-        m.s2[q] = col * LD + row;
-    }
-    const int e = tid * 4, col = e >> 7, row = e & 127;
-    m.e4 = col * nb + row;
-    m.s4 = col * LD + row;
+    const int e2 = tid * 2, e4 = tid * 4;
+    m.e2 = (e2 >> 7) * nb + (e2 & 127);
+    m.s2 = (e2 >> 7) * LD + (e2 & 127);
+    m.e4 = (e4 >> 7) * nb + (e4 & 127);
+    m.s4 = (e4 >> 7) * LD + (e4 & 127);
     return m;
 }
 
+// Loads through global-address-space pointers: the pair loops are
+// functions, where a plain pointer would make flat loads (which the LDS
+// waits would then also wait for).
+#define TC_GLOBAL __attribute__((address_space(1)))
+typedef unsigned gu4v __attribute__((ext_vector_type(4)));
+typedef unsigned gu2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint4 to_u4(gu4v v) { return uint4{v.x, v.y, v.z, v.w}; }
+
 // Raw bits of a thread's pieces of the class-C slab starting at element idx.
 template <int C>
-__device__ __forceinline__ void raw_load(const char* base, int64_t idx, const SlabMap& m, RawSlab& r) {
+__device__ __forceinline__ void raw_load(const char* base, int64_t idx, int64_t nb,
+                                         const SlabMap& m, RawSlab& r) {
+    const TC_GLOBAL char* g = (const TC_GLOBAL char*)base;
     if constexpr (C == kFP64) {
-        const double* p = reinterpret_cast<const double*>(base) + idx;
+        const TC_GLOBAL double* p = (const TC_GLOBAL double*)g + idx + m.e2;
 #pragma unroll
-        for (int q = 0; q < 2; ++q) r.w[q] = *reinterpret_cast<const uint4*>(p + m.e2[q]);
+        for (int q = 0; q < 4; ++q) r.w[q] = to_u4(*(const TC_GLOBAL gu4v*)(p + q * kQ2 * nb));
     } else if constexpr (C == kFP32) {
-        r.w[0] = *reinterpret_cast<const uint4*>(reinterpret_cast<const float*>(base) + idx + m.e4);
+        const TC_GLOBAL float* p = (const TC_GLOBAL float*)g + idx + m.e4;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) r.w[q] = to_u4(*(const TC_GLOBAL gu4v*)(p + q * kQ4 * nb));
     } else if constexpr (C == kFP16 || C == kBF16) {
-        const uint2 v = *reinterpret_cast<const uint2*>(reinterpret_cast<const uint16_t*>(base) + idx + m.e4);
-        r.w[0].x = v.x;
-        r.w[0].y = v.y;
+        const TC_GLOBAL uint16_t* p = (const TC_GLOBAL uint16_t*)g + idx + m.e4;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const gu2v v = *(const TC_GLOBAL gu2v*)(p + q * kQ4 * nb);
+            r.w[q].x = v.x;
+            r.w[q].y = v.y;
+        }
     } else {
-        r.w[0].x = *reinterpret_cast<const uint32_t*>(reinterpret_cast<const uint8_t*>(base) + idx + m.e4);
+        const TC_GLOBAL uint8_t* p = (const TC_GLOBAL uint8_t*)g + idx + m.e4;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) r.w[q].x = *(const TC_GLOBAL uint32_t*)(p + q * kQ4 * nb);
     }
 }
 
 typedef float f2v __attribute__((ext_vector_type(2)));
 
-// Decode a thread's pieces of a class-C slab to binary64 and write them to
-// the LDS stage `dst`. Conversions are exact: FP8 (OCP e4m3, which the
-// gfx950 packed conversion implements) and FP16 through binary32, the tile
-// scale applied afterwards with ldexp in binary64 (scaled classes only).
+// A 4-row piece of a narrower class in binary64, unscaled. Conversions are
+// exact: FP8 (OCP e4m3, which the gfx950 packed conversion implements) and
+// FP16 through binary32.
 template <int C>
-__device__ __forceinline__ void raw_store(const RawSlab& r, int scale, const SlabMap& m, double* dst) {
+__device__ __forceinline__ void decode_piece(const uint4 w, double (&v)[4]) {
+    if constexpr (C == kFP32) {
+        v[0] = (double)__uint_as_float(w.x);
+        v[1] = (double)__uint_as_float(w.y);
+        v[2] = (double)__uint_as_float(w.z);
+        v[3] = (double)__uint_as_float(w.w);
+    } else if constexpr (C == kFP16) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const uint32_t h = ((i < 2 ? w.x : w.y) >> (16 * (i & 1))) & 0xFFFFu;
+            v[i] = (double)(float)__builtin_bit_cast(_Float16, (uint16_t)h);
+        }
+    } else if constexpr (C == kBF16) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const uint32_t h = ((i < 2 ? w.x : w.y) >> (16 * (i & 1))) & 0xFFFFu;
+            v[i] = (double)__uint_as_float(h << 16);
+        }
+    } else {
+        const f2v lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)w.x, false);
+        const f2v hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)w.x, true);
+        v[0] = lo.x;
+        v[1] = lo.y;
+        v[2] = hi.x;
+        v[3] = hi.y;
+    }
+}
+
+// Decode a thread's pieces of a class-C slab and write them to the LDS
+// stage dst.
+template <int C, int LD>
+__device__ __forceinline__ void raw_store(const RawSlab& r, const SlabMap& m, double* dst) {
     if constexpr (C == kFP64) {
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
+        for (int q = 0; q < 4; ++q) {
             const uint4 w = r.w[q];
-            *reinterpret_cast<d2*>(dst + m.s2[q]) =
+            *reinterpret_cast<d2*>(dst + m.s2 + q * kQ2 * LD) =
                 d2{__hiloint2double((int)w.y, (int)w.x), __hiloint2double((int)w.w, (int)w.z)};
         }
     } else {
-        const uint4 w = r.w[0];
-        double v[4];
-        if constexpr (C == kFP32) {
-            v[0] = (double)__uint_as_float(w.x);
-            v[1] = (double)__uint_as_float(w.y);
-            v[2] = (double)__uint_as_float(w.z);
-            v[3] = (double)__uint_as_float(w.w);
-        } else if constexpr (C == kFP16) {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const uint32_t h = ((i < 2 ? w.x : w.y) >> (16 * (i & 1))) & 0xFFFFu;
-                v[i] = (double)(float)__builtin_bit_cast(_Float16, (uint16_t)h);
-            }
-        } else if constexpr (C == kBF16) {
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const uint32_t h = ((i < 2 ? w.x : w.y) >> (16 * (i & 1))) & 0xFFFFu;
-                v[i] = (double)__uint_as_float(h << 16);
-            }
-        } else {
-            const f2v lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)w.x, false);
-            const f2v hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)w.x, true);
-            v[0] = lo.x;
-            v[1] = lo.y;
-            v[2] = hi.x;
-            v[3] = hi.y;
+        for (int q = 0; q < 2; ++q) {
+            double v[4];
+            decode_piece<C>(r.w[q], v);
+            *reinterpret_cast<d2*>(dst + m.s4 + q * kQ4 * LD) = d2{v[0], v[1]};
+            *reinterpret_cast<d2*>(dst + m.s4 + q * kQ4 * LD + 2) = d2{v[2], v[3]};
         }
-        if constexpr (C == kFP16 || C == kFP8) {
-            if (scale != 0) {
-#pragma unroll
-                for (int i = 0; i < 4; ++i) v[i] = ldexp(v[i], scale);
-            }
-        }
-        *reinterpret_cast<d2*>(dst + m.s4) = d2{v[0], v[1]};
-        *reinterpret_cast<d2*>(dst + m.s4 + 2) = d2{v[2], v[3]};
     }
 }
 
 typedef d4 F64Acc[kF64MI][kF64NI];
 
 // Stages c0, c0 + 16, ... < c1 (columns of tile column n) with A of class CA
-// and B of class CB: the double-buffered loop of the all-binary64 main loop,
-// its first stage loaded without overlap. a0, b0: element offsets of the
-// slabs' first row in column 0 of their tiles.
+// (tile at abase) and B of class CB (at bbase): the double-buffered loop of
+// the all-binary64 main loop, its first stage loaded without overlap.
+// a0, b0: element offsets of the slabs' first row in column 0 of their
+// tiles.
 template <int CA, int CB>
-__device__ __forceinline__ void mixed_run(F64Acc& acc, const MixedTile ta, const MixedTile tb,
-                                          int64_t a0, int64_t b0, int64_t nb, int c0, int c1,
-                                          const SlabMap& map, double* lds) {
+__device__ __forceinline__ void mixed_run_body(F64Acc& acc, const char* abase, const char* bbase,
+                                               int64_t a0, int64_t b0, int64_t nb, int c0, int c1,
+                                               const SlabMap& map, double* lds) {
     using T = MfmaTile<kB, kB>;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -177,21 +208,21 @@ __device__ __forceinline__ void mixed_run(F64Acc& acc, const MixedTile ta, const
     double* As = lds;
     double* Bs = lds + 2 * T::BK * T::LDA;
     RawSlab ra, rb;
-    raw_load<CA>(ta.base, a0 + (int64_t)c0 * nb, map, ra);
-    raw_load<CB>(tb.base, b0 + (int64_t)c0 * nb, map, rb);
-    raw_store<CA>(ra, ta.scale, map, As);
-    raw_store<CB>(rb, tb.scale, map, Bs);
+    raw_load<CA>(abase, a0 + (int64_t)c0 * nb, nb, map, ra);
+    raw_load<CB>(bbase, b0 + (int64_t)c0 * nb, nb, map, rb);
+    raw_store<CA, T::LDA>(ra, map, As);
+    raw_store<CB, T::LDB>(rb, map, Bs);
     __syncthreads();
     int buf = 0;
     const int li = lane & 15, lk = lane >> 4;
     for (int c = c0; c < c1; c += T::BK) {
         const bool more = c + T::BK < c1;
         if (more) {
-            raw_load<CA>(ta.base, a0 + (int64_t)(c + T::BK) * nb, map, ra);
-            raw_load<CB>(tb.base, b0 + (int64_t)(c + T::BK) * nb, map, rb);
+            raw_load<CA>(abase, a0 + (int64_t)(c + T::BK) * nb, nb, map, ra);
+            raw_load<CB>(bbase, b0 + (int64_t)(c + T::BK) * nb, nb, map, rb);
         }
         const double* as = As + buf * T::BK * T::LDA + wm * 64 + li;
-        const double* bs = Bs + buf * T::BK * T::LDB + wn * 32 + li;
+        const double* bs = Bs + buf * T::BK * T::LDB + wn * 64 + li;
 #pragma unroll
         for (int ks = 0; ks < T::BK / 4; ++ks) {
             const int k = ks * 4 + lk;
@@ -208,12 +239,50 @@ __device__ __forceinline__ void mixed_run(F64Acc& acc, const MixedTile ta, const
                                                                       0, 0, 0);
         }
         if (more) {
-            raw_store<CA>(ra, ta.scale, map, As + (buf ^ 1) * T::BK * T::LDA);
-            raw_store<CB>(rb, tb.scale, map, Bs + (buf ^ 1) * T::BK * T::LDB);
+            raw_store<CA, T::LDA>(ra, map, As + (buf ^ 1) * T::BK * T::LDA);
+            raw_store<CB, T::LDB>(rb, map, Bs + (buf ^ 1) * T::BK * T::LDB);
         }
         __syncthreads();
         buf ^= 1;
     }
+}
+
+// Wave-uniform copy of a 64-bit value: a function's arguments arrive in
+// vector registers, and loop control and address bases belong in scalar
+// ones.
+__device__ __forceinline__ int64_t uni64(int64_t x) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)x >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// The pair loop of one tile column, a function of its own: the
+// accumulators come in from accm (lane-private memory) divided by 2^s, the
+// frame of the operands' scales, and go back multiplied by it.
+template <int CA, int CB>
+__device__ __attribute__((noinline)) void mixed_run(F64Acc& accm, const MixedTile ta,
+                                                    const MixedTile tb, int64_t a0, int64_t b0,
+                                                    int64_t nb, int c0, int c1, const SlabMap map,
+                                                    double* lds) {
+    const int s = __builtin_amdgcn_readfirstlane((CA == kFP16 || CA == kFP8 ? ta.scale : 0) +
+                                                 (CB == kFP16 || CB == kFP8 ? tb.scale : 0));
+    F64Acc acc;
+#pragma unroll
+    for (int mi = 0; mi < kF64MI; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < kF64NI; ++ni)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[mi][ni][v] = ldexp(accm[mi][ni][v], -s);
+    mixed_run_body<CA, CB>(acc, (const char*)uni64((int64_t)ta.base),
+                           (const char*)uni64((int64_t)tb.base), uni64(a0), uni64(b0), uni64(nb),
+                           __builtin_amdgcn_readfirstlane(c0), __builtin_amdgcn_readfirstlane(c1),
+                           map, (double*)uni64((int64_t)lds));
+#pragma unroll
+    for (int mi = 0; mi < kF64MI; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < kF64NI; ++ni)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) accm[mi][ni][v] = ldexp(acc[mi][ni][v], s);
 }
 
 template <int CA>
@@ -236,7 +305,7 @@ template <class AOp, class BOp>
 __device__ __forceinline__ void mixed_mainloop(F64Acc& acc, const AOp& aop, const BOp& bop,
                                                int64_t nb, int64_t kbeg, int64_t kend, double* lds) {
     using T = MfmaTile<kB, kB>;
-    static_assert(kB * T::BK == 4 * kF64Threads, "four slab elements per thread per operand");
+    static_assert(kB * T::BK == 8 * kF64Threads, "eight slab elements per thread per operand");
     static_assert(T::LDA == T::LDB, "one slab map for both operands");
     const SlabMap map = slab_map<T::LDA>(threadIdx.x, (int)nb);
     for (int64_t kk = kbeg; kk < kend;) {
@@ -296,7 +365,7 @@ __device__ __forceinline__ void group_block(int64_t b, int T, bool diag, const i
 // (lower blocks, when diag) and the listed row tiles. splits > 1: split s
 // covers [K0 + s*kchunk, K0 + (s+1)*kchunk) and writes its 128 x 128 block
 // to partial[(s * nblocks + b) * 128^2] (column-major).
-__global__ __launch_bounds__(kF64Threads, 1) void mxp_gemm_f64_kernel(
+__global__ __launch_bounds__(kF64Threads, 2) void mxp_gemm_f64_kernel(
     double* __restrict__ W, int Nt, int nb, int k, int64_t K0, int64_t K1,
     const int* __restrict__ rows, int nrows, int diag, const char* __restrict__ storage,
     const int64_t* __restrict__ toff, const uint8_t* __restrict__ tcls,
@@ -333,17 +402,13 @@ __global__ __launch_bounds__(kF64Threads, 1) void mxp_gemm_f64_kernel(
     // element v of block (mi, ni): row 64 wm + 16 mi + l % 16, column
     // 32 wn + 16 ni + l / 16 + 4 v (the transposed-block layout of the
     // binary64 kernels)
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int wm = wave & 1, wn = wave >> 1;
 #pragma unroll
     for (int mi = 0; mi < kF64MI; ++mi)
 #pragma unroll
         for (int ni = 0; ni < kF64NI; ++ni)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int row = wm * 64 + mi * 16 + (lane & 15);
-                const int col = wn * 32 + ni * 16 + (lane >> 4) + 4 * v;
-                double* p = out + (int64_t)col * ldo + row;
+                double* p = out + (int64_t)acc_col<kB, kB>(ni, v) * ldo + acc_row<kB, kB>(mi);
                 if (splits == 1)
                     *p -= acc[mi][ni][v];
                 else

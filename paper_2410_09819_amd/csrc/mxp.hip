@@ -1171,9 +1171,10 @@ bool use_wide(int mode, int nb, int nrows) {
 }  // namespace
 
 // Split count of an FP64 group launch: the forward panel's time model
-// (rounds of 256 resident workgroups, one 512-thread workgroup per CU, at
-// the FP64 MFMA rate, plus the partial blocks' traffic), each split keeping
-// >= 1024 of K and the partials within `cap` doubles.
+// (rounds of 256 workgroups at the FP64 MFMA rate, plus the partial
+// blocks' traffic; counting the two resident workgroups per CU as 512
+// slots measured no faster), each split keeping >= 1024 of K and the
+// partials within `cap` doubles.
 static int mxp_f64_splits(int64_t nblocks, int64_t K, size_t cap) {
     int64_t smax = K / 1024;
     if (smax > 16) smax = 16;

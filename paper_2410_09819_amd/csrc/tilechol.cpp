@@ -638,21 +638,28 @@ tc_status factorize_fp64(tc_ctx* ctx, int64_t n, int nb, const double* A, double
         TC_HIP(hipEventCreate(&e));
         ctx->gemm_ev.push_back(e);
     }
-    while (ctx->la_ev.size() < (size_t)2 * Nt + 1) {
+    while (ctx->la_ev.size() < (size_t)3 * Nt + 1) {
         hipEvent_t e;
         TC_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         ctx->la_ev.push_back(e);
     }
     // Lookahead schedule on two streams (same column order as Algorithm 1):
-    //   bulk (aux[0]):   P1(k+1) = column k+1 updated from tile columns [0, k)
-    //                    once TRSM(k-1) is done -- concurrent with POTRF(k)
-    //                    and TRSM(k);
     //   main (stream):   P2(k) = column k updated from tile column k-1 (after
-    //                    P1(k) and TRSM(k-1)), POTRF(k), TRSM(k).
-    // ev_t[k]: TRSM(k) done (main); ev_p[k]: P1(k) done (bulk).
+    //                    P1(k) and TRSM(k-1)), POTRF(k), TRSM(k);
+    //   bulk (aux[0]):   P1(k+1) = column k+1 updated from tile columns [0, k)
+    //                    once P2(k) is done (so after TRSM(k-1)) --
+    //                    concurrent with POTRF(k) and TRSM(k).
+    // P1(k+1) waits for P2(k), not only for TRSM(k-1): launched together,
+    // the two share the CUs and P2(k), which the critical path needs first,
+    // ends with the longer P1(k+1); POTRF(k) and TRSM(k) then run with the
+    // bulk stream idle (measured: every column of the first quarter at
+    // n = 131072).
+    // ev_t[k]: TRSM(k) done (main); ev_p[k]: P1(k) done (bulk); ev_q[k]:
+    // P2(k) done (main).
     hipStream_t sm = ctx->stream, sb = ctx->aux[0];
     hipEvent_t* ev_t = ctx->la_ev.data();
     hipEvent_t* ev_p = ctx->la_ev.data() + Nt;
+    hipEvent_t* ev_q = ctx->la_ev.data() + 2 * Nt + 1;
     hipEvent_t ev_go = ctx->la_ev[2 * Nt];
     TC_HIP(hipEventRecord(ctx->ev0, sm));
     if ((const void*)L != (const void*)A)
@@ -663,10 +670,16 @@ tc_status factorize_fp64(tc_ctx* ctx, int64_t n, int nb, const double* A, double
     double gemm_flops = 0.0, tail_flops = 0.0;
     int launches = 0;
     for (int k = 0; k < Nt; ++k) {
+        if (k >= 1) {
+            if (k >= 2) TC_HIP(hipStreamWaitEvent(sm, ev_p[k], 0));
+            TC_HIP(tc::launch_panel_update(sm, L, Nt, nb, k, k - 1, k, 1, nullptr, true));
+            TC_HIP(hipEventRecord(ev_q[k - 1], sm));
+            tail_flops += (double)nb * nb * (double)nb * (1.0 + 2.0 * (Nt - k - 1));
+        }
         if (k >= 1 && k + 1 < Nt) {
             const int c = k + 1;
             const int sp = tc::panel_splits(Nt, nb, c, k);
-            TC_HIP(hipStreamWaitEvent(sb, ev_t[k - 1], 0));
+            TC_HIP(hipStreamWaitEvent(sb, ev_q[k - 1], 0));
             if (timed) TC_HIP(hipEventRecord(ctx->gemm_ev[2 * launches], sb));
             TC_HIP(tc::launch_panel_update(sb, L, Nt, nb, c, 0, k, sp, big, false));
             if (timed) TC_HIP(hipEventRecord(ctx->gemm_ev[2 * launches + 1], sb));
@@ -675,11 +688,6 @@ tc_status factorize_fp64(tc_ctx* ctx, int64_t n, int nb, const double* A, double
             // algorithmic flops: SYRK nb^2 * K (lower half) + GEMM 2 nb^2 K per tile below
             gemm_flops += (double)nb * nb * ((double)k * nb) * (1.0 + 2.0 * (Nt - c - 1));
             ++launches;
-        }
-        if (k >= 1) {
-            if (k >= 2) TC_HIP(hipStreamWaitEvent(sm, ev_p[k], 0));
-            TC_HIP(tc::launch_panel_update(sm, L, Nt, nb, k, k - 1, k, 1, nullptr, true));
-            tail_flops += (double)nb * nb * (double)nb * (1.0 + 2.0 * (Nt - k - 1));
         }
         double* Tkk = L + tc::tile_off(Nt, k, k) * nb2;
         if (tc_status s = potrf_rec(ctx->stream, Tkk, nb, 0, nb, (int64_t)k * nb, d_info, pot)) return s;

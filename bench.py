@@ -33,8 +33,8 @@ FP64_PEAK_TFLOPS = 78.6
 # HBM bytes per bulk panel-GEMM launch from the calibrated FETCH_SIZE and
 # WRITE_SIZE counter passes (profiles/panel_update_fp64_counters_n65536_nb1024.md),
 # valid for the kernel sources they were taken with.
-PANEL_TRAFFIC = {"bytes_per_launch": 3.2001e10,
-                 "sources_sha256": "a3a2e6f80fd4f414d3d6c84471ac64bceb8326259573d0e1ca6903d74fb9dc90"}
+PANEL_TRAFFIC = {"bytes_per_launch": 3.1901e+10,
+                 "sources_sha256": "b9fd0f1c6e38a5169a4e2af364935472c6baad4828d78cfbd924f66ea08bf591"}
 
 
 def panel_traffic():

@@ -33,7 +33,7 @@ FP64_PEAK_TFLOPS = 78.6
 # HBM bytes per bulk panel-GEMM launch from the calibrated FETCH_SIZE and
 # WRITE_SIZE counter passes (profiles/panel_update_fp64_counters_n65536_nb1024.md),
 # valid for the kernel sources they were taken with.
-PANEL_TRAFFIC = {"bytes_per_launch": 3.1901e+10,
+PANEL_TRAFFIC = {"bytes_per_launch": 2.9906e+10,
                  "sources_sha256": "b9fd0f1c6e38a5169a4e2af364935472c6baad4828d78cfbd924f66ea08bf591"}
 
 

@@ -643,19 +643,26 @@ tc_status factorize_fp64(tc_ctx* ctx, int64_t n, int nb, const double* A, double
         TC_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         ctx->la_ev.push_back(e);
     }
-    // Lookahead schedule on two streams (same column order as Algorithm 1):
-    //   main (stream):   P2(k) = column k updated from tile column k-1 (after
-    //                    P1(k) and TRSM(k-1)), POTRF(k), TRSM(k);
-    //   bulk (aux[0]):   P1(k+1) = column k+1 updated from tile columns [0, k)
-    //                    once P2(k) is done (so after TRSM(k-1)) --
-    //                    concurrent with POTRF(k) and TRSM(k).
-    // P1(k+1) waits for P2(k), not only for TRSM(k-1): launched together,
-    // the two share the CUs and P2(k), which the critical path needs first,
-    // ends with the longer P1(k+1); POTRF(k) and TRSM(k) then run with the
-    // bulk stream idle (measured: every column of the first quarter at
-    // n = 131072).
-    // ev_t[k]: TRSM(k) done (main); ev_p[k]: P1(k) done (bulk); ev_q[k]:
-    // P2(k) done (main).
+    // Lookahead schedule on two streams (same column order as Algorithm 1).
+    // Column c's update is split by tile columns into three launches:
+    //   Pa(c): tile columns [0, c-2)   bulk stream, two columns ahead;
+    //   Pb(c): tile column c-2         bulk stream, one column ahead;
+    //   P2(c): tile column c-1         main stream, right before POTRF(c).
+    // Per column k:
+    //   main (stream):   P2(k) (after Pa(k), Pb(k) and TRSM(k-1)), POTRF(k),
+    //                    TRSM(k);
+    //   bulk (aux[0]):   once P2(k) is done (so after TRSM(k-1)): Pb(k+1),
+    //                    then Pa(k+2) -- concurrent with POTRF(k), TRSM(k).
+    // The bulk waits for P2(k) instead of starting beside it: launched
+    // together, the two share the CUs and P2(k), which the critical path
+    // needs first, ends with the longer bulk; POTRF(k) and TRSM(k) then run
+    // with the bulk stream idle (measured: every column of the first
+    // quarter at n = 131072). Pb(k+1) splits off the tile column that
+    // becomes ready last, so Pa(k+2) can run two columns ahead: in the
+    // first columns, where the bulk is short, POTRF and TRSM then have more
+    // bulk work beside them (n = 65536: 1.527 -> 1.520 s on one box).
+    // ev_t[k]: TRSM(k) done (main); ev_p[k]: Pa(k) and Pb(k) done (bulk);
+    // ev_q[k-1]: P2(k) done (main).
     hipStream_t sm = ctx->stream, sb = ctx->aux[0];
     hipEvent_t* ev_t = ctx->la_ev.data();
     hipEvent_t* ev_p = ctx->la_ev.data() + Nt;
@@ -670,24 +677,28 @@ tc_status factorize_fp64(tc_ctx* ctx, int64_t n, int nb, const double* A, double
     double gemm_flops = 0.0, tail_flops = 0.0;
     int launches = 0;
     for (int k = 0; k < Nt; ++k) {
-        if (k >= 1) {
+        if (k >= 1) {  // P2(k)
             if (k >= 2) TC_HIP(hipStreamWaitEvent(sm, ev_p[k], 0));
             TC_HIP(tc::launch_panel_update(sm, L, Nt, nb, k, k - 1, k, 1, nullptr, true));
             TC_HIP(hipEventRecord(ev_q[k - 1], sm));
             tail_flops += (double)nb * nb * (double)nb * (1.0 + 2.0 * (Nt - k - 1));
         }
         if (k >= 1 && k + 1 < Nt) {
-            const int c = k + 1;
-            const int sp = tc::panel_splits(Nt, nb, c, k);
             TC_HIP(hipStreamWaitEvent(sb, ev_q[k - 1], 0));
-            if (timed) TC_HIP(hipEventRecord(ctx->gemm_ev[2 * launches], sb));
-            TC_HIP(tc::launch_panel_update(sb, L, Nt, nb, c, 0, k, sp, big, false));
-            if (timed) TC_HIP(hipEventRecord(ctx->gemm_ev[2 * launches + 1], sb));
-            TC_HIP(tc::launch_panel_reduce(sb, L, Nt, nb, c, sp, big));
-            TC_HIP(hipEventRecord(ev_p[c], sb));
-            // algorithmic flops: SYRK nb^2 * K (lower half) + GEMM 2 nb^2 K per tile below
-            gemm_flops += (double)nb * nb * ((double)k * nb) * (1.0 + 2.0 * (Nt - c - 1));
-            ++launches;
+            // Pb(k+1): one tile column, launched as a rank-nb update
+            TC_HIP(tc::launch_panel_update(sb, L, Nt, nb, k + 1, k - 1, k, 1, nullptr, true));
+            tail_flops += (double)nb * nb * (double)nb * (1.0 + 2.0 * (Nt - k - 2));
+            TC_HIP(hipEventRecord(ev_p[k + 1], sb));
+            if (k + 2 < Nt) {  // Pa(k+2): the bulk launch
+                const int c = k + 2;
+                const int sp = tc::panel_splits(Nt, nb, c, k);
+                if (timed) TC_HIP(hipEventRecord(ctx->gemm_ev[2 * launches], sb));
+                TC_HIP(tc::launch_panel_update(sb, L, Nt, nb, c, 0, k, sp, big, false));
+                if (timed) TC_HIP(hipEventRecord(ctx->gemm_ev[2 * launches + 1], sb));
+                TC_HIP(tc::launch_panel_reduce(sb, L, Nt, nb, c, sp, big));
+                gemm_flops += (double)nb * nb * ((double)k * nb) * (1.0 + 2.0 * (Nt - c - 1));
+                ++launches;
+            }
         }
         double* Tkk = L + tc::tile_off(Nt, k, k) * nb2;
         if (tc_status s = potrf_rec(ctx->stream, Tkk, nb, 0, nb, (int64_t)k * nb, d_info, pot)) return s;

@@ -661,10 +661,8 @@ tc_status factorize_fp64(tc_ctx* ctx, int64_t n, int nb, const double* A, double
     // becomes ready last, so Pa(k+2) can run two columns ahead: in the
     // first columns, where the bulk is short, POTRF and TRSM then have more
     // bulk work beside them (n = 65536: 1.527 -> 1.520 s on one box).
-    // ev_t[k]: TRSM(k) done (main); ev_p[k]: Pa(k) and Pb(k) done (bulk);
-    // ev_q[k-1]: P2(k) done (main).
+    // ev_p[k]: Pa(k) and Pb(k) done (bulk); ev_q[k-1]: P2(k) done (main).
     hipStream_t sm = ctx->stream, sb = ctx->aux[0];
-    hipEvent_t* ev_t = ctx->la_ev.data();
     hipEvent_t* ev_p = ctx->la_ev.data() + Nt;
     hipEvent_t* ev_q = ctx->la_ev.data() + 2 * Nt + 1;
     hipEvent_t ev_go = ctx->la_ev[2 * Nt];
@@ -705,8 +703,9 @@ tc_status factorize_fp64(tc_ctx* ctx, int64_t n, int nb, const double* A, double
         if (k + 1 < Nt)
             TC_HIP(tc::launch_trsm(sm, L + tc::tile_off(Nt, k + 1, k) * nb2, Tkk, nb,
                                    (int64_t)(Nt - k - 1) * nb, nb));
-        TC_HIP(hipEventRecord(ev_t[k], sm));
     }
+    // the bulk stream's last launch, Pb(Nt-1), precedes P2(Nt-1) on the
+    // main stream, so the main stream has joined it
     TC_HIP(hipEventRecord(ctx->ev1, ctx->stream));
     int info = 0;
     TC_HIP(hipMemcpyAsync(&info, d_info, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));

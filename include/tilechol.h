@@ -84,7 +84,7 @@ typedef struct {
     int32_t fp64_update;
     /* Block shape of the FP32 / FP16 / BF16 / FP8 update kernels: 0
      * (default) takes 256 x 256 blocks when nb is a multiple of 256 and a
-     * group launch has at least 256 of them, else 128 x 128; 1 takes
+     * group launch has at least 128 of them, else 128 x 128; 1 takes
      * 256 x 256 whenever nb is a multiple of 256; -1 always 128 x 128. The
      * two shapes round the binary32 sums in a different order and are
      * otherwise the same arithmetic. */

@@ -955,10 +955,11 @@ __global__ __launch_bounds__(kGemmThreads, 2) void mxp_gemm_split_kernel(
 // block moves half the operand bytes per flop of the 128 x 128 form, and
 // each wave reads 1.5x fewer LDS bytes per flop: the 128 x 128 form is
 // bound by its operands' path through the vector memory unit and LDS, not
-// by the matrix cores. Operands go to LDS by direct-to-LDS loads (wave w
-// fills rows 128 (w & 1) .. + 127 of plane w >> 1; planes A0 A1 B0 B1, or
-// A hi, A lo, B hi, B lo for the split; same swizzle as above) into a
-// double buffer.
+// by the matrix cores. Operands go to a double buffer in LDS through
+// registers (wave w fills rows 128 (w & 1) .. + 127 of plane w >> 1;
+// planes A0 A1 B0 B1, or A hi, A lo, B hi, B lo for the split; same
+// swizzle as above), the next stage's loads in flight under the current
+// stage's MFMAs.
 // Scales: instead of a second accumulator per tile column, acc holds the
 // running sum in units of 2^frame, frame = the current tile column's
 // product scale e_a + e_b, and is multiplied by 2^(frame_old - frame_new)
@@ -978,7 +979,6 @@ constexpr int kWThreads = 512;        // eight waves
 constexpr int kWPlane = kWB * 64;     // bytes per plane: 256 rows x 64 bytes
 constexpr int kWStage = 4 * kWPlane;  // 64 KiB per stage
 constexpr int kWGroup = 16;           // tile columns one binary32 chain may span
-typedef __attribute__((address_space(3))) void lds_void;
 
 template <int MODE>
 __global__ __launch_bounds__(kWThreads, 1) void mxp_gemm_wide_kernel(
@@ -1022,14 +1022,22 @@ __global__ __launch_bounds__(kWThreads, 1) void mxp_gemm_wide_kernel(
     const int lc = (lane & 3) ^ ((lr >> 1) & 3);  // row 16 q + lr swizzles like lr
     const int64_t goff = (int64_t)(128 * half + lr) * nb * EB + 16 * lc + pbyte;
     const int64_t gq = (int64_t)16 * nb * EB;  // 16 rows further
+    // the next stage's pieces are loaded into registers while the current
+    // stage's MFMAs run, then written to their LDS slots (16 bytes per lane
+    // and instruction, lane by lane): on gfx950 this ran 3-12% faster than
+    // direct-to-LDS loads into the same slots
+    u4v rg[8];
     auto issue = [&](int g) {
         const int c = g / spt, st = g - c * spt;
         const int n = nbeg + order[c];
         const uint8_t* src = (pl < 2 ? aop.rows(n, EB) : bop.rows(n, EB)) + (int64_t)st * SK * EB + goff;
-        uint8_t* dst = lds + (g & 1) * kWStage + pl * kWPlane + half * 128 * 64;
 #pragma unroll
-        for (int q = 0; q < 8; ++q)
-            __builtin_amdgcn_global_load_lds(src + q * gq, (lds_void*)(dst + q * 1024), 16, 0, 0);
+        for (int q = 0; q < 8; ++q) rg[q] = *reinterpret_cast<const u4v*>(src + q * gq);
+    };
+    auto commit = [&](int g) {
+        uint8_t* dst = lds + (g & 1) * kWStage + pl * kWPlane + half * 128 * 64 + lane * 16;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) *reinterpret_cast<u4v*>(dst + q * 1024) = rg[q];
     };
     const int ro = swz(li, lg);
     f4 acc[8][4];
@@ -1044,13 +1052,12 @@ __global__ __launch_bounds__(kWThreads, 1) void mxp_gemm_wide_kernel(
     if (g1 > 0) {
         frame = key[order[0]];
         issue(0);
+        commit(0);
     }
     for (int g = 0; g < g1; ++g) {
-        // stage g landed for every wave, and every wave is done reading
-        // stage g - 1's buffer, which stage g + 1 now overwrites
-        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-        __builtin_amdgcn_s_barrier();
-        asm volatile("" ::: "memory");
+        // stage g is in LDS for every wave, and every wave is done reading
+        // stage g - 1's buffer, which stage g + 1 overwrites below
+        __syncthreads();
         if (g + 1 < g1) issue(g + 1);
         const uint8_t* st = lds + (g & 1) * kWStage;
         const int ao = wm * 128 * 64 + ro, bo = wn * 64 * 64 + ro;
@@ -1132,6 +1139,7 @@ __global__ __launch_bounds__(kWThreads, 1) void mxp_gemm_wide_kernel(
                     }
             }
         }
+        if (g + 1 < g1) commit(g + 1);
         if (g + 1 < g1 && (g + 1) % spt == 0) {  // the next stage starts a tile column
             const int sc = key[order[(g + 1) / spt]];
             const int d = frame - sc;  // <= 0: the frame rises
@@ -1158,14 +1166,15 @@ __global__ __launch_bounds__(kWThreads, 1) void mxp_gemm_wide_kernel(
 }
 
 // Wide form for this group launch? mode 1: whenever the tile allows it;
-// -1: never; 0: when the launch has a block for each of the 256 CUs
-// (threshold measured against 1, 64, 128, 512 and 1024 blocks on the
-// n = 131072 mixed factorization: 256 is best or within 1% for both update
-// arithmetics).
+// -1: never; 0: when the launch has at least 128 blocks, half a block per
+// CU (threshold measured on the n = 131072 mixed factorization against 1,
+// 64, 256, 512 and 1024 blocks; with the register-staged loads 128 was
+// 0.6% faster than 256 with binary64 updates into FP64 tiles and equal
+// with FP32-class updates, and 64 was slower).
 bool use_wide(int mode, int nb, int nrows) {
     if (mode < 0 || nb % kWB != 0) return false;
     const int64_t T = nb / kWB;
-    return mode > 0 || (int64_t)nrows * T * T >= 256;
+    return mode > 0 || (int64_t)nrows * T * T >= 128;
 }
 
 }  // namespace

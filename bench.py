@@ -34,7 +34,7 @@ FP64_PEAK_TFLOPS = 78.6
 # WRITE_SIZE counter passes (profiles/panel_update_fp64_counters_n65536_nb1024.md),
 # valid for the kernel sources they were taken with.
 PANEL_TRAFFIC = {"bytes_per_launch": 2.9906e+10,
-                 "sources_sha256": "b9fd0f1c6e38a5169a4e2af364935472c6baad4828d78cfbd924f66ea08bf591"}
+                 "sources_sha256": "a2d96aee56430654b16f5142dc0a1a5037717d8bc0b565c2df82334149fba65d"}
 
 
 def panel_traffic():

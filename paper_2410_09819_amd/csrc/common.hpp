@@ -81,8 +81,10 @@ int syrk_sub_splits(int m, int kdim);
 // TRSM X = C L^{-T} (trsm_f64.hip). C: M rows (a multiple of 64), w columns;
 // row r at C + (r / nb) * nb * nb + (r % nb) + c * nb (rows of consecutive
 // tiles of a tile column, or a sub-block of one tile when M <= nb).
-// L: w x w lower, column-major with leading dimension nb.
-hipError_t launch_trsm(hipStream_t s, double* C, const double* L, int nb, int64_t M, int w);
+// L: w x w lower, column-major with leading dimension nb. leaf: widest
+// column block solved by one leaf launch (a multiple of 128).
+hipError_t launch_trsm(hipStream_t s, double* C, const double* L, int nb, int64_t M, int w,
+                       int leaf = 128);
 // The same solve for a whole nb x nb factor tile (w = nb) in two launches:
 // inverses of L's 64 x 64 diagonal blocks into dinv (nb * 64 doubles), then
 // one pass in which each workgroup walks its 64 rows' column blocks with

@@ -5,11 +5,13 @@
 // Recursive on the width w of L (no explicit inverse anywhere, so the solve
 // stays backward stable):
 //   X1 = C1 L11^{-T};  C2 -= X1 L21^T;  X2 = C2 L22^{-T}
-// The middle step is a large MFMA GEMM (M x w/2 x w/2) and carries 7/8 of
-// the flops for w = 1024. Widths <= 128 are solved by a fused leaf kernel:
+// The middle step is a large MFMA GEMM (M x w/2 x w/2). Widths up to the
+// caller's leaf width (128 by default) are solved by a fused leaf kernel:
 // each workgroup owns 64 rows and walks the columns in 64-wide blocks
 // (MFMA update with the columns already solved, then substitution against
-// the 64 x 64 diagonal block of L in LDS, four threads per row).
+// the 64 x 64 diagonal block of L in LDS, four threads per row). With
+// 128-column leaves the GEMMs carry 7/8 of the flops for w = 1024; wider
+// leaves mean fewer launches and more of the work in the leaves.
 //
 // C rows are "tile-strided": row r of the panel lives at
 // C + (r / nb) * nb^2 + (r % nb), column c at + c * nb (rows of consecutive
@@ -296,14 +298,14 @@ __global__ __launch_bounds__(kGemmThreads) void tiles_inv_kernel(TileView V,
     blockinv_rows(Cb, diag_of(V, k), Dinv + (int64_t)k * nb * kCol, nb, nb, lds);
 }
 
-hipError_t trsm_rec(hipStream_t s, double* C, const double* L, int nb, int64_t M, int w) {
-    if (w <= 128) {
+hipError_t trsm_rec(hipStream_t s, double* C, const double* L, int nb, int64_t M, int w, int leaf) {
+    if (w <= leaf) {
         hipLaunchKernelGGL(trsm_leaf_kernel, dim3((unsigned)(M / kRows)), dim3(kGemmThreads), 0, s,
                            C, L, nb, w);
         return hipGetLastError();
     }
     const int h = ((w / 2 + 127) / 128) * 128;
-    hipError_t e = trsm_rec(s, C, L, nb, M, h);
+    hipError_t e = trsm_rec(s, C, L, nb, M, h, leaf);
     if (e != hipSuccess) return e;
     // C2 -= X1 L21^T: C2 = columns [h, w), X1 = columns [0, h), L21 = L[h:w, 0:h]
     const int64_t blocks = (M / kGB) * ((w - h) / kGB);
@@ -311,14 +313,15 @@ hipError_t trsm_rec(hipStream_t s, double* C, const double* L, int nb, int64_t M
                        C + (int64_t)h * nb, C, L + h, nb, M, w - h, h);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return trsm_rec(s, C + (int64_t)h * nb, L + h + (int64_t)h * nb, nb, M, w - h);
+    return trsm_rec(s, C + (int64_t)h * nb, L + h + (int64_t)h * nb, nb, M, w - h, leaf);
 }
 
 }  // namespace
 
-hipError_t launch_trsm(hipStream_t s, double* C, const double* L, int nb, int64_t M, int w) {
-    if (M % kGB != 0 || w % kGB != 0) return hipErrorInvalidValue;
-    return trsm_rec(s, C, L, nb, M, w);
+hipError_t launch_trsm(hipStream_t s, double* C, const double* L, int nb, int64_t M, int w,
+                       int leaf) {
+    if (M % kGB != 0 || w % kGB != 0 || leaf < 128 || leaf % kGB != 0) return hipErrorInvalidValue;
+    return trsm_rec(s, C, L, nb, M, w, leaf);
 }
 
 hipError_t launch_diag_tiles_inv(hipStream_t s, const TileView& V, double* dinv, double* xinv) {

@@ -34,7 +34,7 @@ FP64_PEAK_TFLOPS = 78.6
 # WRITE_SIZE counter passes (profiles/panel_update_fp64_counters_n65536_nb1024.md),
 # valid for the kernel sources they were taken with.
 PANEL_TRAFFIC = {"bytes_per_launch": 2.9906e+10,
-                 "sources_sha256": "a2d96aee56430654b16f5142dc0a1a5037717d8bc0b565c2df82334149fba65d"}
+                 "sources_sha256": "23aee1e0c1c85c6c8e4b675a14c4b2c183956712798071f07f1af3739e45cf35"}
 
 
 def panel_traffic():

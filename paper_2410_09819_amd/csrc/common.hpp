@@ -85,6 +85,16 @@ int syrk_sub_splits(int m, int kdim);
 // column block solved by one leaf launch (a multiple of 128).
 hipError_t launch_trsm(hipStream_t s, double* C, const double* L, int nb, int64_t M, int w,
                        int leaf = 128);
+// Leaf width of the FP64 factorizations' panel TRSM (the tiles below a
+// diagonal tile). While a bulk panel update holds the chip, a kernel on
+// another stream gets workgroup slots mostly after the bulk's last
+// workgroups are dispatched, so the TRSM waits once per launch: 512-column
+// leaves (a leaf, a GEMM, a leaf for nb = 1024) instead of 128-column ones
+// (fifteen launches) let it finish earlier, and alone it is faster too.
+// The n = 65536, nb = 1024 factorization, alternating runs on one box:
+// 1.528 s (128), 1.520 s (256), 1.516 s (512), 1.520 s (1024: one launch,
+// whose workgroups then walk all 16 column blocks alone).
+constexpr int kPanelTrsmLeaf = 512;
 // The same solve for a whole nb x nb factor tile (w = nb) in two launches:
 // inverses of L's 64 x 64 diagonal blocks into dinv (nb * 64 doubles), then
 // one pass in which each workgroup walks its 64 rows' column blocks with

@@ -98,7 +98,7 @@ extern "C" tc_status tc_factorize_noalloc(tc_ctx* ctx, int64_t n, int32_t nb, co
         if (tc_status s = potrf_rec(sm, Tkk, nb, 0, nb, (int64_t)k * nb, d_info, pot)) return s;
         if (k + 1 < Nt)
             TC_HIP(tc::launch_trsm(sm, L + tc::tile_off(Nt, k + 1, k) * nb2, Tkk, nb,
-                                   (int64_t)(Nt - k - 1) * nb, nb));
+                                   (int64_t)(Nt - k - 1) * nb, nb, tc::kPanelTrsmLeaf));
     }
     int h_info = 0;
     TC_HIP(hipMemcpyAsync(&h_info, d_info, sizeof(int), hipMemcpyDeviceToHost, sm));

@@ -261,7 +261,8 @@ extern "C" tc_status tc_factorize_ooc(tc_ctx* ctx, int64_t n, int32_t nb, const 
         if (rows > 1 && !no_v3) {
             // V3: the diagonal factor stays in the working column for the
             // one TRSM launch over the tiles below it
-            TC_HIP(tc::launch_trsm(cs, W + nb2, W, nb, (int64_t)(rows - 1) * nb, nb));
+            TC_HIP(tc::launch_trsm(cs, W + nb2, W, nb, (int64_t)(rows - 1) * nb, nb,
+                                   tc::kPanelTrsmLeaf));
         } else if (rows > 1) {
             // without V3 the diagonal factor goes back to host memory after
             // POTRF and each tile's TRSM loads it again (two staging slots)

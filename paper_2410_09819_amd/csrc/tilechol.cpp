@@ -620,16 +620,6 @@ size_t tc_factor_bytes(int64_t n, int32_t nb, const uint8_t* map, const tc_opts*
 
 namespace {
 
-// Widest column block the panel TRSM solves in one leaf launch. While a
-// bulk panel update holds the chip, a kernel on the main stream gets
-// workgroup slots mostly after the bulk's last workgroups are dispatched,
-// so the TRSM waits once per launch: 512-column leaves (a leaf, a GEMM, a
-// leaf) instead of 128-column ones (fifteen launches) let it finish
-// earlier. The n = 65536, nb = 1024 factorization, alternating runs on one
-// box: 1.528 s (128), 1.520 s (256), 1.516 s (512), 1.520 s (1024: one
-// launch, whose workgroups then walk all 16 column blocks alone).
-constexpr int kPanelTrsmLeaf = 512;
-
 // All-FP64 factorization (storage: packed binary64 tiles, may equal A).
 tc_status factorize_fp64(tc_ctx* ctx, int64_t n, int nb, const double* A, double* L,
                          tc_factor** Lout, tc_stats* stats) {
@@ -712,7 +702,7 @@ tc_status factorize_fp64(tc_ctx* ctx, int64_t n, int nb, const double* A, double
         if (tc_status s = potrf_rec(ctx->stream, Tkk, nb, 0, nb, (int64_t)k * nb, d_info, pot)) return s;
         if (k + 1 < Nt)
             TC_HIP(tc::launch_trsm(sm, L + tc::tile_off(Nt, k + 1, k) * nb2, Tkk, nb,
-                                   (int64_t)(Nt - k - 1) * nb, nb, kPanelTrsmLeaf));
+                                   (int64_t)(Nt - k - 1) * nb, nb, tc::kPanelTrsmLeaf));
     }
     // the bulk stream's last launch, Pb(Nt-1), precedes P2(Nt-1) on the
     // main stream, so the main stream has joined it

@@ -47,6 +47,29 @@ def test_exact_integer_solve():
     assert np.array_equal(X, x)
 
 
+def test_exact_integer_forward_solve():
+    """L^{-1} b, the first term of the likelihood's quadratic form (Eq. 1):
+    with b = L0 x in small integers every step is exact."""
+    n = 64
+    L0 = si.integer_factor(n, seed=9)
+    x = np.round(si.standard_normal((n, 2), seed=10) * 4.0)
+    assert np.array_equal(oracle.forward_solve(L0, L0 @ x), x)
+    assert np.array_equal(oracle.forward_solve(L0, L0 @ x[:, 0]), x[:, 0])
+
+
+def test_forward_solve_matches_library_routine():
+    """Against LAPACK's triangular solve (scipy) on a well-conditioned
+    lower-triangular matrix with random entries."""
+    from scipy.linalg import solve_triangular
+    n = 200
+    M = si.standard_normal((n, n), seed=11)
+    L = np.tril(M) * 0.1 + np.diag(2.0 + np.abs(np.diag(M)))
+    B = si.standard_normal((n, 5), seed=12)
+    Y = oracle.forward_solve(L, B)
+    ref = solve_triangular(L, B, lower=True)
+    assert np.max(np.abs(Y - ref)) <= 1e-13 * np.max(np.abs(ref))
+
+
 # --- closed form: second-difference matrix ---------------------------------
 
 @pytest.mark.parametrize("nb", [1, 8, 16, 64])

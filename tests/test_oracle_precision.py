@@ -20,6 +20,16 @@ import seeded_inputs as si
 from oracle import FP8, FP16, FP32, FP64, BF16
 
 
+@pytest.mark.parametrize("c,dt", [(FP64, torch.float64), (FP32, torch.float32), (FP16, torch.float16),
+                                  (BF16, torch.bfloat16), (FP8, torch.float8_e4m3fn)])
+def test_class_eps_matches_format(c, dt):
+    """eps_p of the criterion: the format's machine epsilon (spacing above
+    1), or half of it as the unit roundoff, from torch's own description of
+    each format."""
+    assert oracle.class_eps(c) == torch.finfo(dt).eps
+    assert oracle.class_eps(c, unit_roundoff=True) == torch.finfo(dt).eps / 2
+
+
 def test_tile_index_is_packed_column_order():
     Nt = 7
     idx = [oracle.tile_index(Nt, i, j) for j in range(Nt) for i in range(j, Nt)]
